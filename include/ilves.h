@@ -1,0 +1,187 @@
+/*
+ * ilves.h -- C ABI of the MI355X (gfx950) constraint solver.
+ *
+ * The library solves the per-timestep constraint equations of constrained
+ * molecular dynamics (Supplement section 2.3 of the ILVES paper):
+ *
+ *   given old positions r, unconstrained positions r_u, masses m and
+ *   distance constraints k = (a_k, b_k, d_k), find lambda with
+ *
+ *     r'(lambda) = r_u - M^{-1} G(r)^T lambda                  (Eq. 6)
+ *     g_k(r')   = 1/2 (|r'_a - r'_b|^2 - d_k^2) = 0             (Eq. ecconstr)
+ *
+ *   by Newton's method on A(x, y) = G(x) M^{-1} G(y)^T           (Eq. defA)
+ *     A(r'_l, r) z_l = g(r'_l),  lambda_{l+1} = lambda_l + z_l    (Eq. newton-constraint-equation)
+ *   or by the chord method with the constant A(r, r)             (Supplement section 3, ILVES-F)
+ *   until max_k |g_k| / d_k^2 <= tol                              (Supplement section 4).
+ *
+ * Sign convention: g has the opposite sign of the paper's Eq. ecconstr and
+ * lambda carries no time step, lambda_here = -h^2 lambda_paper.
+ *
+ * Every linear system is solved by a sparse LU (Newton) factorisation
+ * without pivoting on a fill-reducing ordering and symbolic factorisation
+ * that ilves_plan_create computes once from the bond graph (Supplement
+ * section 3: line graph L(G) and ordering).
+ *
+ * Conventions for every entry point:
+ *   - positions are structure-of-arrays: x[0..s), y[0..s), z[0..s) back to
+ *     back, 3*s doubles, in nm; masses in amu (> 0);
+ *   - "device" pointers are HIP device (or managed) memory of the current
+ *     device; "host" pointers are ordinary host memory;
+ *   - the caller owns every array it passes; the plan owns its own device
+ *     buffers and workspace;
+ *   - functions return ILVES_OK or an error code and never throw; a message
+ *     for the last error of the calling thread is in ilves_last_error().
+ */
+#ifndef ILVES_H
+#define ILVES_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ilves_plan* ilves_plan_t;
+
+typedef enum {
+  ILVES_OK = 0,
+  ILVES_ERR_ARG = 1,            /* bad argument (null pointer, negative size, ...)          */
+  ILVES_ERR_TOPOLOGY = 2,       /* self pair, duplicate pair, atom index out of range, d<=0 */
+  ILVES_ERR_HIP = 3,            /* a HIP runtime call failed                                */
+  ILVES_ERR_NOMEM = 4,          /* host or device allocation failed                         */
+  ILVES_ERR_SINGULAR = 5,       /* per molecule: a pivot vanished (redundant constraints)   */
+  ILVES_ERR_NOT_CONVERGED = 6,  /* per molecule: iteration cap reached before tol           */
+  ILVES_ERR_NONFINITE = 7,      /* per molecule: NaN or Inf met in the residual             */
+  ILVES_ERR_UNSUPPORTED = 8     /* option combination not built into this library           */
+} ilves_status_t;
+
+enum { ILVES_PREC_FP64 = 0, ILVES_PREC_MIXED = 1 };
+enum { ILVES_VARIANT_NEWTON = 0, ILVES_VARIANT_CHORD = 1 };
+enum { ILVES_WARM_ZERO = 0, ILVES_WARM_MLP = 1, ILVES_WARM_CALLER = 2 };
+
+typedef struct {
+  int32_t precision;     /* ILVES_PREC_FP64: factor and solves in FP64;
+                            ILVES_PREC_MIXED: matrix, factor and triangular solves
+                            in FP32, residual, lambda and positions in FP64      */
+  int32_t variant;       /* ILVES_VARIANT_NEWTON (refactor A(r', r) every
+                            iteration) or ILVES_VARIANT_CHORD (factor A(r, r)
+                            once per solve)                                      */
+  int32_t max_iter;      /* iteration cap; <= 0 selects 20 (Newton FP64) or 40   */
+  int32_t warm_start;    /* ILVES_WARM_ZERO: lambda_0 = 0; ILVES_WARM_CALLER:
+                            lambda_0 read from the lambda argument;
+                            ILVES_WARM_MLP: lambda_0 from the loaded network     */
+  int32_t block_threads; /* threads per workgroup for large molecules; 0 = auto  */
+  int32_t lds_limit;     /* bytes of LDS a molecule may use; 0 = auto            */
+  int32_t ordering;      /* 0 auto, 1 minimum degree, 2 nested dissection        */
+  int32_t reserved;
+} ilves_options_t;
+
+/* Fills *opt with defaults (FP64 Newton, lambda_0 = 0, automatic schedule). */
+void ilves_default_options(ilves_options_t* opt);
+
+/*
+ * Builds a plan for a topology: validates it, splits it into molecules
+ * (connected components of the constraint graph), builds each molecule's
+ * line graph, orders it, computes the symbolic LU factorisation and the
+ * level schedule, and uploads everything to the current device.
+ *   n_atoms        number of atoms s (> 0)
+ *   n_constraints  number of constraints n (>= 0)
+ *   pairs          host int32 [n][2], atom indices, a != b, no duplicates
+ *   d              host double [n], target distances (nm, > 0)
+ *   opt            host options (NULL = defaults)
+ *   out            receives the plan handle
+ * The topology is copied; the caller may free it afterwards.
+ * Errors: ILVES_ERR_ARG, ILVES_ERR_TOPOLOGY, ILVES_ERR_NOMEM, ILVES_ERR_HIP.
+ */
+ilves_status_t ilves_plan_create(int32_t n_atoms, int32_t n_constraints, const int32_t* pairs,
+                                 const double* d, const ilves_options_t* opt, ilves_plan_t* out);
+
+/* Releases the plan and its device memory.  NULL is accepted. */
+ilves_status_t ilves_plan_destroy(ilves_plan_t plan);
+
+/* Number of molecules (components with at least one constraint). */
+int32_t ilves_plan_num_molecules(ilves_plan_t plan);
+
+/*
+ * Plan statistics, host int64 array of ILVES_STAT_COUNT entries:
+ *   [0] molecules, [1] constraints, [2] atoms in constraints,
+ *   [3] stored factor entries, [4] fill entries, [5] factor updates,
+ *   [6] largest level count, [7] sum of level counts, [8] molecules kept in
+ *   LDS, [9] molecules in the global workspace, [10] workspace bytes,
+ *   [11] plan bytes on the device.
+ */
+#define ILVES_STAT_COUNT 12
+ilves_status_t ilves_plan_stats(ilves_plan_t plan, int64_t* stats);
+
+/*
+ * Per-molecule description, host arrays of length num_molecules (any may be
+ * NULL): constraint count, atom count, level count, and the first input
+ * constraint index of each molecule in the plan's molecule order.
+ */
+ilves_status_t ilves_plan_molecules(ilves_plan_t plan, int32_t* n_con, int32_t* n_atoms,
+                                    int32_t* n_levels, int32_t* first_constraint);
+
+/*
+ * One constraint solve (the hot path), asynchronous on hip_stream.
+ *   r, r_u     device double [3][n_atoms]  old and unconstrained positions (nm)
+ *   mass       device double [n_atoms]     masses (amu, > 0)
+ *   tol        bound on max |g_k| / d_k^2 (e.g. 1e-12)
+ *   r_out      device double [3][n_atoms]  constrained positions; atoms in no
+ *              constraint get r_u.  May alias neither r nor r_u.
+ *   lambda     device double [n_constraints] multipliers in input order; read
+ *              as lambda_0 when warm_start = ILVES_WARM_CALLER or MLP
+ *   iters      device int32 [num_molecules] linear solves per molecule
+ *   status     device int32 [num_molecules] ILVES_OK, ILVES_ERR_SINGULAR,
+ *              ILVES_ERR_NOT_CONVERGED or ILVES_ERR_NONFINITE per molecule
+ *   hip_stream hipStream_t (NULL = the null stream)
+ * The call allocates nothing, never synchronises the host and may be
+ * captured in a HIP graph.  One solve per plan may be in flight at a time.
+ * The return code reports argument and launch errors only; convergence is
+ * reported per molecule in status[] (read it after synchronising).
+ */
+ilves_status_t ilves_solve(ilves_plan_t plan, const double* r, const double* r_u, const double* mass,
+                           double tol, double* r_out, double* lambda, int32_t* iters, int32_t* status,
+                           void* hip_stream);
+
+/* Same as ilves_solve with explicit precision / variant / warm start /
+ * iteration cap, overriding the plan's options for this call. */
+ilves_status_t ilves_solve_ex(ilves_plan_t plan, const double* r, const double* r_u, const double* mass,
+                              double tol, int32_t precision, int32_t variant, int32_t warm_start,
+                              int32_t max_iter, double* r_out, double* lambda, int32_t* iters,
+                              int32_t* status, void* hip_stream);
+
+/*
+ * Planner diagnostics (host only, no GPU needed; not a solve path -- the
+ * solve entry points never call it).  Plans the topology like
+ * ilves_plan_create and replays, on the host and in the same order of
+ * operations, the level schedule that the device kernel executes.  Used to
+ * test the ordering, symbolic factorisation and task lists on machines
+ * without a GPU.
+ *   mass [n_atoms], r, r_u, r_out [3][n_atoms], lambda [n_constraints]: host
+ *   iters, status: host int32 arrays with room for n_constraints entries
+ *   (at least the number of molecules); *n_molecules receives that number
+ *   schedule_stats: host int64 [5] (molecules, factor entries, updates,
+ *   largest level count, fill entries) or NULL
+ */
+ilves_status_t ilves_plan_replay_host(int32_t n_atoms, int32_t n_constraints, const int32_t* pairs,
+                                      const double* d, const ilves_options_t* opt, const double* mass,
+                                      const double* r, const double* r_u, double tol, int32_t precision,
+                                      int32_t variant, int32_t max_iter, double* r_out, double* lambda,
+                                      int32_t* iters, int32_t* status, int32_t* n_molecules,
+                                      int64_t* schedule_stats);
+
+/* Static, human readable name of a status code. */
+const char* ilves_status_string(ilves_status_t s);
+
+/* Message describing the last error returned on the calling thread. */
+const char* ilves_last_error(void);
+
+/* Library version string. */
+const char* ilves_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ILVES_H */

@@ -1,0 +1,208 @@
+"""ctypes binding of ``libilves.so`` (argument marshalling only).
+
+Every step of the solve runs in the library's HIP kernels; PyTorch only
+provides device memory (tensors passed by ``data_ptr()``) and streams.
+Nothing here falls back to a CPU implementation: if the library is missing
+the import of the solver fails loudly.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libilves.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "ilves.h")
+
+OK, ERR_ARG, ERR_TOPOLOGY, ERR_HIP, ERR_NOMEM, ERR_SINGULAR, ERR_NOT_CONVERGED, ERR_NONFINITE, ERR_UNSUPPORTED = range(9)
+PREC_FP64, PREC_MIXED = 0, 1
+VARIANT_NEWTON, VARIANT_CHORD = 0, 1
+WARM_ZERO, WARM_MLP, WARM_CALLER = 0, 1, 2
+STAT_NAMES = ["molecules", "constraints", "atoms", "factor_entries", "fill", "updates", "max_levels",
+              "sum_levels", "mol_lds", "mol_workspace", "workspace_bytes", "plan_bytes"]
+
+
+class IlvesError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"ilves error {code}: {msg}")
+        self.code = code
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("variant", ctypes.c_int32), ("max_iter", ctypes.c_int32),
+                ("warm_start", ctypes.c_int32), ("block_threads", ctypes.c_int32), ("lds_limit", ctypes.c_int32),
+                ("ordering", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+_lib = None
+_P = ctypes.c_void_p
+_I32P = ctypes.POINTER(ctypes.c_int32)
+_I64P = ctypes.POINTER(ctypes.c_int64)
+_F64P = ctypes.POINTER(ctypes.c_double)
+
+
+def header_functions() -> list:
+    """Names of the functions that include/ilves.h declares."""
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(ilves_[a-z_]+)\s*\(", txt)))
+
+
+def lib() -> ctypes.CDLL:
+    """Loads the library once.  torch is imported first so that the process
+    has a single HIP runtime (the library's libamdhip64.so.7 dependency then
+    resolves to the copy torch already loaded)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    import torch  # noqa: F401  (HIP runtime first)
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2503_13075_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    L.ilves_default_options.argtypes = [ctypes.POINTER(Options)]
+    L.ilves_default_options.restype = None
+    L.ilves_version.restype = ctypes.c_char_p
+    L.ilves_last_error.restype = ctypes.c_char_p
+    L.ilves_status_string.argtypes = [ctypes.c_int]
+    L.ilves_status_string.restype = ctypes.c_char_p
+    L.ilves_plan_create.argtypes = [ctypes.c_int32, ctypes.c_int32, _I32P, _F64P, ctypes.POINTER(Options),
+                                    ctypes.POINTER(_P)]
+    L.ilves_plan_create.restype = ctypes.c_int
+    L.ilves_plan_destroy.argtypes = [_P]
+    L.ilves_plan_destroy.restype = ctypes.c_int
+    L.ilves_plan_num_molecules.argtypes = [_P]
+    L.ilves_plan_num_molecules.restype = ctypes.c_int32
+    L.ilves_plan_stats.argtypes = [_P, _I64P]
+    L.ilves_plan_stats.restype = ctypes.c_int
+    L.ilves_plan_molecules.argtypes = [_P, _I32P, _I32P, _I32P, _I32P]
+    L.ilves_plan_molecules.restype = ctypes.c_int
+    L.ilves_solve.argtypes = [_P, _P, _P, _P, ctypes.c_double, _P, _P, _P, _P, _P]
+    L.ilves_solve.restype = ctypes.c_int
+    L.ilves_solve_ex.argtypes = [_P, _P, _P, _P, ctypes.c_double, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                 ctypes.c_int32, _P, _P, _P, _P, _P]
+    L.ilves_solve_ex.restype = ctypes.c_int
+    L.ilves_plan_replay_host.argtypes = [ctypes.c_int32, ctypes.c_int32, _I32P, _F64P, ctypes.POINTER(Options),
+                                         _F64P, _F64P, _F64P, ctypes.c_double, ctypes.c_int32, ctypes.c_int32,
+                                         ctypes.c_int32, _F64P, _F64P, _I32P, _I32P, _I32P, _I64P]
+    L.ilves_plan_replay_host.restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def check(code: int):
+    if code != OK:
+        raise IlvesError(code, lib().ilves_last_error().decode())
+
+
+def _ptr(a: np.ndarray, ctype):
+    return a.ctypes.data_as(ctypes.POINTER(ctype))
+
+
+def make_options(precision=PREC_FP64, variant=VARIANT_NEWTON, max_iter=0, warm_start=WARM_ZERO,
+                 block_threads=0, lds_limit=0, ordering=0) -> Options:
+    o = Options()
+    lib().ilves_default_options(ctypes.byref(o))
+    o.precision, o.variant, o.max_iter, o.warm_start = precision, variant, max_iter, warm_start
+    o.block_threads, o.lds_limit, o.ordering = block_threads, lds_limit, ordering
+    return o
+
+
+def _topology(pairs, d):
+    pairs = np.ascontiguousarray(np.asarray(pairs, dtype=np.int32).reshape(-1, 2))
+    d = np.ascontiguousarray(np.asarray(d, dtype=np.float64).reshape(-1))
+    if pairs.shape[0] != d.shape[0]:
+        raise ValueError("pairs and d have different lengths")
+    return pairs, d
+
+
+def replay_host(n_atoms, pairs, d, mass, r_soa, ru_soa, tol, precision=PREC_FP64, variant=VARIANT_NEWTON,
+                max_iter=0, ordering=0):
+    """Runs the planner and replays the device schedule on the host
+    (planner diagnostics; see ilves_plan_replay_host)."""
+    L = lib()
+    pairs, d = _topology(pairs, d)
+    n = pairs.shape[0]
+    mass = np.ascontiguousarray(mass, dtype=np.float64)
+    r_soa = np.ascontiguousarray(r_soa, dtype=np.float64)
+    ru_soa = np.ascontiguousarray(ru_soa, dtype=np.float64)
+    r_out = np.zeros_like(ru_soa)
+    lam = np.zeros(n)
+    iters = np.zeros(max(n, 1), np.int32)
+    status = np.zeros(max(n, 1), np.int32)
+    nm = ctypes.c_int32(0)
+    st = np.zeros(5, np.int64)
+    o = make_options(ordering=ordering)
+    check(L.ilves_plan_replay_host(n_atoms, n, _ptr(pairs, ctypes.c_int32), _ptr(d, ctypes.c_double), ctypes.byref(o),
+                                   _ptr(mass, ctypes.c_double), _ptr(r_soa, ctypes.c_double),
+                                   _ptr(ru_soa, ctypes.c_double), tol, precision, variant, max_iter,
+                                   _ptr(r_out, ctypes.c_double), _ptr(lam, ctypes.c_double),
+                                   _ptr(iters, ctypes.c_int32), _ptr(status, ctypes.c_int32), ctypes.byref(nm),
+                                   _ptr(st, ctypes.c_int64)))
+    k = nm.value
+    return {"r_out": r_out, "lam": lam, "iters": iters[:k].copy(), "status": status[:k].copy(),
+            "stats": dict(zip(["molecules", "factor_entries", "updates", "max_levels", "fill"], st.tolist()))}
+
+
+class Plan:
+    """A planned topology on the current GPU (wraps ilves_plan_create)."""
+
+    def __init__(self, n_atoms, pairs, d, precision=PREC_FP64, variant=VARIANT_NEWTON, max_iter=0,
+                 warm_start=WARM_ZERO, block_threads=0, lds_limit=0, ordering=0):
+        L = lib()
+        self._L = L
+        pairs, d = _topology(pairs, d)
+        self.n_atoms = int(n_atoms)
+        self.n_constraints = int(pairs.shape[0])
+        o = make_options(precision, variant, max_iter, warm_start, block_threads, lds_limit, ordering)
+        h = _P()
+        check(L.ilves_plan_create(self.n_atoms, self.n_constraints, _ptr(pairs, ctypes.c_int32),
+                                  _ptr(d, ctypes.c_double), ctypes.byref(o), ctypes.byref(h)))
+        self._h = h
+        self.n_molecules = int(L.ilves_plan_num_molecules(h))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.ilves_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def stats(self) -> dict:
+        st = np.zeros(len(STAT_NAMES), np.int64)
+        check(self._L.ilves_plan_stats(self._h, _ptr(st, ctypes.c_int64)))
+        return dict(zip(STAT_NAMES, st.tolist()))
+
+    def molecules(self) -> dict:
+        k = self.n_molecules
+        a = [np.zeros(max(k, 1), np.int32) for _ in range(4)]
+        check(self._L.ilves_plan_molecules(self._h, *[_ptr(x, ctypes.c_int32) for x in a]))
+        return {"n_con": a[0][:k], "n_atoms": a[1][:k], "n_levels": a[2][:k], "first_constraint": a[3][:k]}
+
+    def solve(self, r, r_u, mass, tol, r_out, lam, iters, status, precision=PREC_FP64, variant=VARIANT_NEWTON,
+              warm_start=WARM_ZERO, max_iter=0, stream=None):
+        """Enqueues one solve.  All tensors are CUDA (HIP) tensors: r, r_u,
+        r_out float64 [3, n_atoms] contiguous, mass float64 [n_atoms], lam
+        float64 [n_constraints], iters/status int32 [n_molecules]."""
+        import torch
+        for t, dt in ((r, torch.float64), (r_u, torch.float64), (mass, torch.float64), (r_out, torch.float64),
+                      (lam, torch.float64), (iters, torch.int32), (status, torch.int32)):
+            if not t.is_cuda or t.dtype != dt or not t.is_contiguous():
+                raise ValueError("solve expects contiguous device tensors of the documented dtypes")
+        if r.shape != (3, self.n_atoms) or r_u.shape != (3, self.n_atoms) or r_out.shape != (3, self.n_atoms):
+            raise ValueError("positions must have shape [3, n_atoms]")
+        if mass.shape != (self.n_atoms,) or lam.shape != (self.n_constraints,):
+            raise ValueError("mass / lambda have the wrong length")
+        if iters.numel() < self.n_molecules or status.numel() < self.n_molecules:
+            raise ValueError("iters / status need one entry per molecule")
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        check(self._L.ilves_solve_ex(self._h, r.data_ptr(), r_u.data_ptr(), mass.data_ptr(), float(tol), precision,
+                                     variant, warm_start, max_iter, r_out.data_ptr(), lam.data_ptr(),
+                                     iters.data_ptr(), status.data_ptr(), ctypes.c_void_p(stream.cuda_stream)))

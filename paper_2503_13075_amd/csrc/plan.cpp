@@ -1,0 +1,550 @@
+// Host planner (runs once per topology).
+//
+// Supplement section 3 of the ILVES paper: the constrained bonds form a graph
+// G (atoms, constraints) that is usually disconnected; its line graph L(G)
+// (one vertex per constraint, an edge when two constraints share an atom)
+// has the sparsity pattern of the Newton matrix A (Eq. defA); a fill-reducing
+// ordering is computed once and the factorisation is then reused every step.
+//
+// The GPU cost of a sparse LU on one workgroup is set by the number of
+// dependent elimination levels as much as by the fill, so the planner
+// compares a minimum-degree ordering (zero fill on trees, but one level per
+// bond along a chain) with a nested-dissection ordering (logarithmic depth
+// along chains, some fill) under a simple latency/work model and keeps the
+// cheaper one.
+#include "plan.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <functional>
+#include <numeric>
+#include <set>
+#include <tuple>
+#include <unordered_set>
+
+namespace ilves {
+
+std::string validate_topology(int32_t n_atoms, int32_t n_con, const int32_t* pairs, const double* d) {
+  if (n_atoms <= 0) return "n_atoms must be positive";
+  if (n_con < 0) return "n_constraints must be non-negative";
+  if (n_con > 0 && (pairs == nullptr || d == nullptr)) return "pairs and d must not be NULL";
+  std::unordered_set<uint64_t> seen;
+  seen.reserve(static_cast<size_t>(n_con) * 2);
+  for (int32_t k = 0; k < n_con; ++k) {
+    int32_t a = pairs[2 * k], b = pairs[2 * k + 1];
+    if (a < 0 || b < 0 || a >= n_atoms || b >= n_atoms)
+      return "constraint " + std::to_string(k) + ": atom index out of range";
+    if (a == b) return "constraint " + std::to_string(k) + ": both atoms are the same";
+    if (!(d[k] > 0.0) || !std::isfinite(d[k]))
+      return "constraint " + std::to_string(k) + ": distance must be positive and finite";
+    uint64_t lo = static_cast<uint64_t>(std::min(a, b)), hi = static_cast<uint64_t>(std::max(a, b));
+    if (!seen.insert((lo << 32) | hi).second)
+      return "constraint " + std::to_string(k) + ": duplicate atom pair";
+  }
+  return std::string();
+}
+
+std::vector<std::vector<int32_t>> split_molecules(int32_t n_atoms, int32_t n_con, const int32_t* pairs,
+                                                  std::vector<int32_t>& free_atoms) {
+  std::vector<int32_t> parent(n_atoms);
+  std::iota(parent.begin(), parent.end(), 0);
+  std::function<int32_t(int32_t)> find = [&](int32_t x) {
+    while (parent[x] != x) {
+      parent[x] = parent[parent[x]];
+      x = parent[x];
+    }
+    return x;
+  };
+  std::vector<char> used(n_atoms, 0);
+  for (int32_t k = 0; k < n_con; ++k) {
+    int32_t a = find(pairs[2 * k]), b = find(pairs[2 * k + 1]);
+    used[pairs[2 * k]] = used[pairs[2 * k + 1]] = 1;
+    if (a != b) parent[std::max(a, b)] = std::min(a, b);
+  }
+  std::vector<int32_t> mol_of_root(n_atoms, -1);
+  std::vector<std::vector<int32_t>> mols;
+  for (int32_t k = 0; k < n_con; ++k) {
+    int32_t root = find(pairs[2 * k]);
+    if (mol_of_root[root] < 0) {
+      mol_of_root[root] = static_cast<int32_t>(mols.size());
+      mols.emplace_back();
+    }
+    mols[mol_of_root[root]].push_back(k);
+  }
+  free_atoms.clear();
+  for (int32_t i = 0; i < n_atoms; ++i)
+    if (!used[i]) free_atoms.push_back(i);
+  return mols;
+}
+
+// ---------------------------------------------------------------------------
+// orderings
+
+std::vector<int32_t> order_min_degree(const std::vector<std::vector<int32_t>>& adj) {
+  // Minimum deficiency (fewest fill edges), ties broken by degree then
+  // index.  On chordal graphs -- the line graph of a tree is one -- the
+  // simplicial vertices have deficiency zero, so the order is a perfect
+  // elimination order and produces no fill at all.
+  const int32_t n = static_cast<int32_t>(adj.size());
+  std::vector<std::vector<int32_t>> g = adj;
+  auto has_edge = [&](int32_t a, int32_t b) { return std::binary_search(g[a].begin(), g[a].end(), b); };
+  auto deficiency = [&](int32_t v) {
+    int64_t miss = 0;
+    const auto& nb = g[v];
+    for (size_t i = 0; i < nb.size(); ++i)
+      for (size_t j = i + 1; j < nb.size(); ++j)
+        if (!has_edge(nb[i], nb[j])) ++miss;
+    return miss;
+  };
+  using Key = std::tuple<int64_t, int32_t, int32_t>;
+  std::set<Key> pq;
+  std::vector<Key> key(n);
+  for (int32_t v = 0; v < n; ++v) {
+    key[v] = Key{deficiency(v), static_cast<int32_t>(g[v].size()), v};
+    pq.insert(key[v]);
+  }
+  std::vector<int32_t> order;
+  order.reserve(n);
+  std::vector<int32_t> tmp, rest, touched;
+  std::vector<char> mark(n, 0);
+  while (!pq.empty()) {
+    const int32_t v = std::get<2>(*pq.begin());
+    pq.erase(pq.begin());
+    order.push_back(v);
+    const std::vector<int32_t> nb = g[v];
+    for (int32_t u : nb) {
+      rest.clear();
+      for (int32_t w : g[u])
+        if (w != v) rest.push_back(w);
+      tmp.clear();
+      // g[u] <- (g[u] \ {v}) union (nb \ {u}); both sorted
+      size_t i = 0, j = 0;
+      while (i < rest.size() || j < nb.size()) {
+        if (j < nb.size() && nb[j] == u) { ++j; continue; }
+        if (j >= nb.size() || (i < rest.size() && rest[i] < nb[j])) tmp.push_back(rest[i++]);
+        else if (i >= rest.size() || nb[j] < rest[i]) tmp.push_back(nb[j++]);
+        else { tmp.push_back(rest[i]); ++i; ++j; }
+      }
+      g[u] = tmp;
+    }
+    g[v].clear();
+    // deficiencies change within two hops of v
+    touched.clear();
+    for (int32_t u : nb) {
+      if (!mark[u]) { mark[u] = 1; touched.push_back(u); }
+      for (int32_t w : g[u])
+        if (!mark[w]) { mark[w] = 1; touched.push_back(w); }
+    }
+    for (int32_t w : touched) {
+      mark[w] = 0;
+      pq.erase(key[w]);
+      key[w] = Key{deficiency(w), static_cast<int32_t>(g[w].size()), w};
+      pq.insert(key[w]);
+    }
+  }
+  return order;
+}
+
+namespace {
+
+std::vector<int32_t> induced_md(const std::vector<std::vector<int32_t>>& adj, const std::vector<int32_t>& nodes,
+                                std::vector<int32_t>& local_of) {
+  for (size_t i = 0; i < nodes.size(); ++i) local_of[nodes[i]] = static_cast<int32_t>(i);
+  std::vector<std::vector<int32_t>> sub(nodes.size());
+  for (size_t i = 0; i < nodes.size(); ++i)
+    for (int32_t u : adj[nodes[i]])
+      if (local_of[u] >= 0) sub[i].push_back(local_of[u]);
+  for (auto& s : sub) std::sort(s.begin(), s.end());
+  std::vector<int32_t> o = order_min_degree(sub);
+  for (int32_t v : nodes) local_of[v] = -1;
+  std::vector<int32_t> out(o.size());
+  for (size_t i = 0; i < o.size(); ++i) out[i] = nodes[o[i]];
+  return out;
+}
+
+}  // namespace
+
+std::vector<int32_t> order_nested_dissection(const std::vector<std::vector<int32_t>>& adj, int leaf) {
+  const int32_t n = static_cast<int32_t>(adj.size());
+  std::vector<int32_t> order;
+  order.reserve(n);
+  std::vector<int32_t> mark(n, -1), lev(n, -1), local_of(n, -1);
+  int32_t next_id = 0;
+  std::vector<int32_t> queue;
+  queue.reserve(n);
+
+  // BFS restricted to vertices with mark == id; returns the visit order.
+  auto bfs = [&](int32_t start, int32_t id) {
+    queue.clear();
+    queue.push_back(start);
+    lev[start] = 0;
+    for (size_t h = 0; h < queue.size(); ++h) {
+      int32_t v = queue[h];
+      for (int32_t u : adj[v])
+        if (mark[u] == id && lev[u] < 0) {
+          lev[u] = lev[v] + 1;
+          queue.push_back(u);
+        }
+    }
+    return queue;
+  };
+
+  std::function<void(const std::vector<int32_t>&)> rec = [&](const std::vector<int32_t>& nodes) {
+    const int32_t sz = static_cast<int32_t>(nodes.size());
+    if (sz <= leaf) {
+      std::vector<int32_t> o = induced_md(adj, nodes, local_of);
+      order.insert(order.end(), o.begin(), o.end());
+      return;
+    }
+    const int32_t id = next_id++;
+    for (int32_t v : nodes) mark[v] = id;
+    // pseudo-peripheral start vertex (George-Liu style)
+    int32_t start = nodes[0];
+    int32_t ecc = -1;
+    for (int rep = 0; rep < 4; ++rep) {
+      for (int32_t v : nodes) lev[v] = -1;
+      std::vector<int32_t> vis = bfs(start, id);
+      int32_t e = lev[vis.back()];
+      if (e <= ecc) break;
+      ecc = e;
+      int32_t best = vis.back();
+      for (int32_t v : vis)
+        if (lev[v] == e && adj[v].size() < adj[best].size()) best = v;
+      start = best;
+    }
+    for (int32_t v : nodes) lev[v] = -1;
+    std::vector<int32_t> vis = bfs(start, id);
+    const int32_t d = lev[vis.back()];
+    if (d < 2 || static_cast<int32_t>(vis.size()) != sz) {
+      for (int32_t v : nodes) mark[v] = -1;
+      std::vector<int32_t> o = induced_md(adj, nodes, local_of);
+      order.insert(order.end(), o.begin(), o.end());
+      return;
+    }
+    std::vector<int32_t> cnt(d + 1, 0);
+    for (int32_t v : nodes) cnt[lev[v]]++;
+    std::vector<int32_t> below(d + 2, 0);
+    for (int32_t l = 0; l <= d; ++l) below[l + 1] = below[l] + cnt[l];
+    int32_t best_l = -1;
+    double best_score = 1e300;
+    for (int32_t l = 1; l < d; ++l) {
+      int32_t lo = below[l], hi = sz - below[l + 1];
+      double bal = static_cast<double>(std::min(lo, hi)) / sz;
+      if (bal < 0.2) continue;
+      double score = cnt[l] * (1.0 + 2.0 * (0.5 - bal));
+      if (score < best_score) { best_score = score; best_l = l; }
+    }
+    if (best_l < 0) best_l = d / 2;
+    // separator: level best_l vertices that touch level best_l + 1
+    std::vector<int32_t> sep;
+    for (int32_t v : nodes)
+      if (lev[v] == best_l) {
+        bool touches = false;
+        for (int32_t u : adj[v])
+          if (mark[u] == id && lev[u] == best_l + 1) { touches = true; break; }
+        if (touches) sep.push_back(v);
+      }
+    for (int32_t v : sep) mark[v] = -2;  // excluded from the parts
+    // connected components of the rest
+    std::vector<std::vector<int32_t>> parts;
+    for (int32_t v : nodes) lev[v] = -1;
+    for (int32_t v : nodes) {
+      if (mark[v] != id || lev[v] >= 0) continue;
+      std::vector<int32_t> comp = bfs(v, id);
+      parts.push_back(comp);
+    }
+    for (int32_t v : nodes) {
+      lev[v] = -1;
+      if (mark[v] == id) mark[v] = -1;
+    }
+    for (auto& p : parts) rec(p);
+    for (int32_t v : sep) mark[v] = -1;
+    std::vector<int32_t> o = induced_md(adj, sep, local_of);
+    order.insert(order.end(), o.begin(), o.end());
+  };
+
+  // each connected component separately
+  std::vector<char> seen(n, 0);
+  for (int32_t v = 0; v < n; ++v) {
+    if (seen[v]) continue;
+    std::vector<int32_t> comp{v};
+    seen[v] = 1;
+    for (size_t h = 0; h < comp.size(); ++h)
+      for (int32_t u : adj[comp[h]])
+        if (!seen[u]) {
+          seen[u] = 1;
+          comp.push_back(u);
+        }
+    rec(comp);
+  }
+  return order;
+}
+
+// ---------------------------------------------------------------------------
+// symbolic factorisation
+
+namespace {
+
+struct Symbolic {
+  std::vector<std::vector<int32_t>> up, low;  // strict upper / lower structure per row
+  std::vector<int32_t> level;
+  int32_t n_levels = 0;
+  int64_t nnz_off = 0;
+  double cost = 0.0;
+};
+
+// adj: adjacency in the permuted numbering.
+Symbolic symbolic(const std::vector<std::vector<int32_t>>& adj) {
+  const int32_t n = static_cast<int32_t>(adj.size());
+  Symbolic S;
+  S.up.resize(n);
+  S.low.resize(n);
+  S.level.assign(n, 0);
+  for (int32_t p = 0; p < n; ++p)
+    for (int32_t q : adj[p])
+      if (q > p) S.up[p].push_back(q);
+  for (int32_t p = 0; p < n; ++p) {
+    auto& u = S.up[p];
+    std::sort(u.begin(), u.end());
+    u.erase(std::unique(u.begin(), u.end()), u.end());
+    if (!u.empty()) {
+      auto& par = S.up[u[0]];  // elimination-tree parent inherits the rest
+      par.insert(par.end(), u.begin() + 1, u.end());
+    }
+  }
+  for (int32_t p = 0; p < n; ++p)
+    for (int32_t q : S.up[p]) {
+      S.low[q].push_back(p);
+      S.level[q] = std::max(S.level[q], S.level[p] + 1);
+    }
+  for (int32_t p = 0; p < n; ++p) {
+    S.n_levels = std::max(S.n_levels, S.level[p] + 1);
+    S.nnz_off += static_cast<int64_t>(S.up[p].size());
+  }
+  // cost model: every level costs a barrier (SYNC) plus its work spread over
+  // LANES lanes; the backward solve walks the levels again.
+  const double SYNC = 16.0, LANES = 256.0;
+  std::vector<double> work(S.n_levels, 0.0), bwork(S.n_levels, 0.0);
+  for (int32_t j = 0; j < n; ++j) {
+    double w = 1.0 + static_cast<double>(S.low[j].size());
+    for (int32_t m : S.up[j]) {
+      // |low(j) ∩ low(m)|, both sorted
+      const auto& a = S.low[j];
+      const auto& b = S.low[m];
+      size_t i = 0, k = 0, c = 0;
+      while (i < a.size() && k < b.size()) {
+        if (a[i] < b[k]) ++i;
+        else if (b[k] < a[i]) ++k;
+        else { ++c; ++i; ++k; }
+      }
+      w += 1.0 + 2.0 * static_cast<double>(c);
+    }
+    work[S.level[j]] += w;
+    bwork[S.level[j]] += 1.0 + static_cast<double>(S.up[j].size());
+  }
+  for (int32_t h = 0; h < S.n_levels; ++h)
+    S.cost += 2.0 * SYNC + std::ceil(work[h] / LANES) * 4.0 + std::ceil(bwork[h] / LANES) * 2.0;
+  return S;
+}
+
+std::vector<std::vector<int32_t>> permute_graph(const std::vector<std::vector<int32_t>>& adj,
+                                                const std::vector<int32_t>& perm) {
+  const int32_t n = static_cast<int32_t>(adj.size());
+  std::vector<int32_t> inv(n);
+  for (int32_t p = 0; p < n; ++p) inv[perm[p]] = p;
+  std::vector<std::vector<int32_t>> out(n);
+  for (int32_t p = 0; p < n; ++p) {
+    for (int32_t u : adj[perm[p]]) out[p].push_back(inv[u]);
+    std::sort(out[p].begin(), out[p].end());
+  }
+  return out;
+}
+
+int32_t find_sorted(const std::vector<int32_t>& v, int32_t x) {
+  auto it = std::lower_bound(v.begin(), v.end(), x);
+  return static_cast<int32_t>(it - v.begin());
+}
+
+}  // namespace
+
+MolPlan plan_molecule(const std::vector<int32_t>& cons, const int32_t* pairs, const double* d,
+                      const PlanOptions& opt) {
+  MolPlan P;
+  const int32_t n = static_cast<int32_t>(cons.size());
+  P.n = n;
+  // local atoms
+  std::vector<int32_t> atoms;
+  atoms.reserve(2 * n);
+  for (int32_t c : cons) {
+    atoms.push_back(pairs[2 * c]);
+    atoms.push_back(pairs[2 * c + 1]);
+  }
+  std::sort(atoms.begin(), atoms.end());
+  atoms.erase(std::unique(atoms.begin(), atoms.end()), atoms.end());
+  P.s = static_cast<int32_t>(atoms.size());
+  P.atom_gid = atoms;
+  std::vector<int32_t> la(n), lb(n);
+  for (int32_t c = 0; c < n; ++c) {
+    la[c] = find_sorted(atoms, pairs[2 * cons[c]]);
+    lb[c] = find_sorted(atoms, pairs[2 * cons[c] + 1]);
+  }
+  // incidence (local constraint order) and line graph
+  std::vector<std::vector<int32_t>> inc(P.s);
+  for (int32_t c = 0; c < n; ++c) {
+    inc[la[c]].push_back(c);
+    inc[lb[c]].push_back(c);
+  }
+  std::vector<std::vector<int32_t>> adj(n);
+  for (int32_t x = 0; x < P.s; ++x)
+    for (size_t i = 0; i < inc[x].size(); ++i)
+      for (size_t j = 0; j < inc[x].size(); ++j)
+        if (i != j) adj[inc[x][i]].push_back(inc[x][j]);
+  int64_t n_edges = 0;
+  for (auto& a : adj) {
+    std::sort(a.begin(), a.end());
+    a.erase(std::unique(a.begin(), a.end()), a.end());
+    n_edges += static_cast<int64_t>(a.size());
+  }
+  n_edges /= 2;
+
+  // ordering
+  std::vector<int32_t> perm = order_min_degree(adj);
+  Symbolic S = symbolic(permute_graph(adj, perm));
+  P.ordering = 1;
+  if (opt.ordering == 2 || (opt.ordering == 0 && n > 2 * opt.nd_leaf)) {
+    std::vector<int32_t> perm_nd = order_nested_dissection(adj, opt.nd_leaf);
+    Symbolic Snd = symbolic(permute_graph(adj, perm_nd));
+    if (opt.ordering == 2 || Snd.cost < S.cost) {
+      perm = perm_nd;
+      S = std::move(Snd);
+      P.ordering = 2;
+    }
+  }
+  std::vector<int32_t> inv(n);
+  for (int32_t p = 0; p < n; ++p) inv[perm[p]] = p;
+  P.n_levels = S.n_levels;
+  P.fill = S.nnz_off - n_edges;
+
+  // rows in elimination order
+  P.cid.resize(n);
+  P.ra.resize(n);
+  P.rb.resize(n);
+  P.d2.resize(n);
+  P.row_start.resize(n + 1);
+  P.row_nup.resize(n);
+  P.row_start[0] = 0;
+  for (int32_t p = 0; p < n; ++p) {
+    int32_t c = perm[p];
+    P.cid[p] = cons[c];
+    P.ra[p] = la[c];
+    P.rb[p] = lb[c];
+    P.d2[p] = d[cons[c]] * d[cons[c]];
+    P.row_nup[p] = static_cast<int32_t>(S.up[p].size());
+    P.row_start[p + 1] = P.row_start[p] + 1 + static_cast<int32_t>(S.up[p].size() + S.low[p].size());
+  }
+  P.nslots = P.row_start[n];
+  auto slot = [&](int32_t k, int32_t j) -> int32_t {
+    if (j == k) return P.row_start[k];
+    if (j > k) return P.row_start[k] + 1 + find_sorted(S.up[k], j);
+    return P.row_start[k] + 1 + static_cast<int32_t>(S.up[k].size()) + find_sorted(S.low[k], j);
+  };
+  P.slot_col.assign(P.nslots, 0);
+  P.slot_coef.assign(P.nslots, 0);
+  for (int32_t k = 0; k < n; ++k) {
+    P.slot_col[P.row_start[k]] = k;
+    auto fill_entry = [&](int32_t j) {
+      int32_t sl = slot(k, j);
+      P.slot_col[sl] = j;
+      int32_t ck = perm[k], cj = perm[j];
+      int32_t x = -1;
+      if (la[ck] == la[cj] || la[ck] == lb[cj]) x = la[ck];
+      else if (lb[ck] == la[cj] || lb[ck] == lb[cj]) x = lb[ck];
+      if (x < 0) {
+        P.slot_coef[sl] = P.s << 1;  // fill: zero coupling (sentinel atom)
+      } else {
+        int sk = (x == la[ck]) ? 1 : -1;
+        int sj = (x == la[cj]) ? 1 : -1;
+        P.slot_coef[sl] = (x << 1) | ((sk * sj) < 0 ? 1 : 0);
+      }
+    };
+    for (int32_t j : S.up[k]) fill_entry(j);
+    for (int32_t j : S.low[k]) fill_entry(j);
+  }
+  // incidence in elimination order
+  P.inc_ptr.assign(P.s + 1, 0);
+  for (int32_t x = 0; x < P.s; ++x) P.inc_ptr[x + 1] = P.inc_ptr[x] + static_cast<int32_t>(inc[x].size());
+  P.inc.resize(P.inc_ptr[P.s]);
+  for (int32_t x = 0; x < P.s; ++x) {
+    std::vector<int32_t> rows;
+    for (int32_t c : inc[x]) rows.push_back(inv[c]);
+    std::sort(rows.begin(), rows.end());
+    for (size_t t = 0; t < rows.size(); ++t) {
+      int32_t p = rows[t];
+      P.inc[P.inc_ptr[x] + t] = (p << 1) | (P.rb[p] == x ? 1 : 0);
+    }
+  }
+  // tasks level by level
+  std::vector<std::vector<int32_t>> by_level(S.n_levels);
+  for (int32_t j = 0; j < n; ++j) by_level[S.level[j]].push_back(j);
+  P.lvl_task.assign(S.n_levels + 1, 0);
+  P.lvl_node.assign(S.n_levels + 1, 0);
+  for (int32_t h = 0; h < S.n_levels; ++h) {
+    struct Pending { Task t; std::vector<Update> u; };
+    std::vector<Pending> pend;
+    for (int32_t j : by_level[h]) {
+      Pending dg;
+      dg.t.out0 = P.row_start[j];
+      dg.t.out1 = -(j + 1);
+      for (int32_t i : S.low[j]) {
+        Update u{};
+        u.a = slot(j, i);
+        u.b = slot(i, j);
+        u.c = i;
+        u.e = 0;
+        u.d = P.row_start[i];
+        dg.u.push_back(u);
+      }
+      pend.push_back(std::move(dg));
+      for (int32_t m : S.up[j]) {
+        Pending pr;
+        pr.t.out0 = slot(j, m);
+        pr.t.out1 = slot(m, j);
+        const auto& A = S.low[j];
+        const auto& B = S.low[m];
+        size_t ia = 0, ib = 0;
+        while (ia < A.size() && ib < B.size()) {
+          if (A[ia] < B[ib]) ++ia;
+          else if (B[ib] < A[ia]) ++ib;
+          else {
+            int32_t i = A[ia];
+            Update u{};
+            u.a = slot(j, i);
+            u.b = slot(i, m);
+            u.c = slot(m, i);
+            u.e = slot(i, j);
+            u.d = P.row_start[i];
+            pr.u.push_back(u);
+            ++ia;
+            ++ib;
+          }
+        }
+        pend.push_back(std::move(pr));
+      }
+    }
+    // longest tasks first so that the lanes finish together
+    std::stable_sort(pend.begin(), pend.end(),
+                     [](const Pending& x, const Pending& y) { return x.u.size() > y.u.size(); });
+    for (auto& pd : pend) {
+      pd.t.u0 = static_cast<int32_t>(P.upd.size());
+      P.upd.insert(P.upd.end(), pd.u.begin(), pd.u.end());
+      pd.t.u1 = static_cast<int32_t>(P.upd.size());
+      P.tasks.push_back(pd.t);
+    }
+    P.lvl_task[h + 1] = static_cast<int32_t>(P.tasks.size());
+    for (int32_t j : by_level[h]) P.nodes.push_back(j);
+    P.lvl_node[h + 1] = static_cast<int32_t>(P.nodes.size());
+  }
+  return P;
+}
+
+}  // namespace ilves

@@ -1,0 +1,170 @@
+"""GPU parity of the HIP solve path against the CPU oracle.
+
+Bar (per result): max relative constraint violation <= 1e-12 and max
+position difference to the oracle <= 1e-10 nm, for the FP64 Newton path,
+the mixed-precision path and the chord variant.  The oracle runs to
+stagnation (its own violation ~1e-16), so the difference measures the GPU
+result.  All calls go through the C ABI (ctypes binding).
+"""
+import os
+
+import numpy as np
+import pytest
+
+from oracle import newton_dense as O
+from paper_2503_13075_amd import _lib as L
+from paper_2503_13075_amd import synth as S
+from paper_2503_13075_amd.device import solve_once
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+POS_TOL = 1e-10
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    L.lib()
+    return torch
+
+
+def _oracle(sm, ru, **kw):
+    return O.solve(sm.pairs, sm.d, sm.mass, sm.r, ru, tol=1e-15, until_stagnation=True, max_iter=40, **kw)
+
+
+def _check(sm, ru, out, ref, label):
+    assert np.all(out["status"] == L.OK), (label, np.unique(out["status"], return_counts=True))
+    viol = np.max(O.relative_violation(out["r_out"], sm.pairs, sm.d))
+    dpos = np.max(np.abs(out["r_out"] - ref["r_new"]))
+    lam_scale = np.max(np.abs(ref["lam"]))
+    dlam = np.max(np.abs(out["lam"] - ref["lam"])) / lam_scale
+    print(f"{label}: max rel violation {viol:.2e}, max |dr'| {dpos:.2e} nm, max |dlambda|/max|lambda| {dlam:.2e}, "
+          f"iters {np.unique(out['iters'], return_counts=True)}", flush=True)
+    assert viol <= TOL, (label, viol)
+    assert dpos <= POS_TOL, (label, dpos)
+    assert dlam <= 1e-6, (label, dlam)
+
+
+VARIANTS = [("fp64", L.PREC_FP64, L.VARIANT_NEWTON), ("mixed", L.PREC_MIXED, L.VARIANT_NEWTON),
+            ("chord64", L.PREC_FP64, L.VARIANT_CHORD), ("chord_mixed", L.PREC_MIXED, L.VARIANT_CHORD)]
+
+
+@pytest.mark.parametrize("name,prec,variant", VARIANTS)
+def test_chain64(name, prec, variant):
+    sm = S.chain64(0)
+    ru = S.perturb(sm.r, 0.002, 1)
+    out = solve_once(sm, ru, TOL, prec, variant)
+    _check(sm, ru, out, _oracle(sm, ru), f"chain64/{name}")
+
+
+@pytest.fixture(scope="module")
+def protein_case():
+    sm = S.protein_system(seed=1, n_res=300)
+    ru = S.perturb(sm.r, 0.002, 1000)
+    return sm, ru, _oracle(sm, ru)
+
+
+@pytest.mark.parametrize("name,prec,variant", VARIANTS[:2])
+def test_protein_full_size(protein_case, name, prec, variant):
+    sm, ru, ref = protein_case
+    out = solve_once(sm, ru, TOL, prec, variant)
+    _check(sm, ru, out, ref, f"protein300/{name}")
+
+
+@pytest.fixture(scope="module")
+def batch_case():
+    sizes = [8, 9, 11, 16, 23, 40, 64, 65, 100, 128, 200, 300, 513, 900, 1400, 2048]
+    sm = S.concat([S.random_tree(n, seed=100 + i) for i, n in enumerate(sizes)])
+    ru = S.perturb(sm.r, 0.002, 5)
+    return sm, ru, _oracle(sm, ru)
+
+
+@pytest.mark.parametrize("name,prec,variant", VARIANTS)
+def test_batch_of_trees(batch_case, name, prec, variant):
+    sm, ru, ref = batch_case
+    out = solve_once(sm, ru, TOL, prec, variant)
+    _check(sm, ru, out, ref, f"batch16/{name}")
+
+
+@pytest.fixture(scope="module")
+def angles_case():
+    mols = [S.add_h_angles(S.protein(40, seed=70 + i)) for i in range(2)]
+    mols += [S.lipid_chain(900 + j) for j in range(20)]
+    sm = S.concat(mols)
+    ru = S.perturb(sm.r, 0.006, 9)
+    return sm, ru, _oracle(sm, ru)
+
+
+@pytest.mark.parametrize("name,prec,variant", VARIANTS[:2])
+def test_angles(angles_case, name, prec, variant):
+    sm, ru, ref = angles_case
+    out = solve_once(sm, ru, TOL, prec, variant)
+    _check(sm, ru, out, ref, f"angles/{name}")
+
+
+def test_workspace_and_lds_paths_agree_bitwise(batch_case):
+    sm, ru, _ = batch_case
+    a = solve_once(sm, ru, TOL, L.PREC_FP64)
+    b = solve_once(sm, ru, TOL, L.PREC_FP64, lds_limit=1024)       # everything in the global workspace
+    c = solve_once(sm, ru, TOL, L.PREC_FP64, block_threads=64)      # other lane mapping
+    assert b["plan"].stats()["mol_workspace"] == len(b["iters"])
+    assert np.array_equal(a["r_out"], b["r_out"]) and np.array_equal(a["lam"], b["lam"])
+    assert np.array_equal(a["r_out"], c["r_out"]) and np.array_equal(a["lam"], c["lam"])
+
+
+def test_deterministic_repeat(batch_case):
+    sm, ru, _ = batch_case
+    plan = L.Plan(sm.n_atoms, sm.pairs, sm.d)
+    a = solve_once(sm, ru, TOL, L.PREC_MIXED, plan=plan)
+    b = solve_once(sm, ru, TOL, L.PREC_MIXED, plan=plan)
+    assert np.array_equal(a["r_out"], b["r_out"]) and np.array_equal(a["lam"], b["lam"])
+
+
+def test_free_atoms_and_empty_topology():
+    sm = S.chain64(0)
+    r = np.concatenate([sm.r, np.ones((3, 3))])
+    ru = np.concatenate([S.perturb(sm.r, 0.002, 1), 2 * np.ones((3, 3))])
+    ext = S.System(pairs=sm.pairs, d=sm.d, mass=np.concatenate([sm.mass, np.ones(3)]), r=r, kind=sm.kind)
+    out = solve_once(ext, ru, TOL)
+    assert np.array_equal(out["r_out"][64:], ru[64:])
+    empty = S.System(pairs=np.zeros((0, 2), np.int32), d=np.zeros(0), mass=np.ones(5), r=np.zeros((5, 3)),
+                     kind=np.zeros(0, np.int8))
+    ru5 = np.arange(15.0).reshape(5, 3)
+    out = solve_once(empty, ru5, TOL)
+    assert np.array_equal(out["r_out"], ru5) and out["plan"].n_molecules == 0
+
+
+def test_failure_statuses():
+    sm = S.chain64(0)
+    ru = S.perturb(sm.r, 0.002, 1)
+    out = solve_once(sm, ru, TOL, max_iter=1)
+    assert out["status"][0] == L.ERR_NOT_CONVERGED and out["iters"][0] == 1
+    bad = ru.copy()
+    bad[7, 2] = np.nan
+    out = solve_once(sm, bad, TOL)
+    assert out["status"][0] == L.ERR_NONFINITE
+    pts = np.array([[0, 0, 0], [0.1, 0, 0], [0, 0.1, 0], [0.1, 0.1, 0]], float)
+    pairs = np.array([(i, j) for i in range(4) for j in range(i + 1, 4)], np.int32)
+    d = np.array([np.linalg.norm(pts[i] - pts[j]) for i, j in pairs])
+    red = S.System(pairs=pairs, d=d, mass=np.ones(4), r=pts, kind=np.zeros(6, np.int8))
+    out = solve_once(red, S.perturb(pts, 0.001, 2), TOL)
+    assert out["status"][0] == L.ERR_SINGULAR
+
+
+def test_caller_warm_start_from_solution():
+    sm = S.chain64(0)
+    ru = S.perturb(sm.r, 0.002, 1)
+    ref = _oracle(sm, ru)
+    out = solve_once(sm, ru, TOL, lam0=ref["lam"])
+    assert out["status"][0] == L.OK and out["iters"][0] <= 1
+    assert np.max(np.abs(out["r_out"] - ref["r_new"])) <= POS_TOL
+
+
+def test_native_library_is_loaded_once():
+    maps = open(f"/proc/{os.getpid()}/maps").read()
+    assert "libilves.so" in maps
+    hip = {line.split()[-1] for line in maps.splitlines() if "libamdhip64" in line}
+    assert len(hip) == 1, hip
