@@ -162,12 +162,20 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(const DevPlan P, const int
   const double* __restrict__ rx = A.r;
   const double* __restrict__ ux = A.r_u;
 
-  // ---- set-up: 1/m, old bond vectors, lambda_0
-  for (int32_t a = tid; a < s; a += BLOCK) invm[a] = 1.0 / A.mass[atom_gid[a]];
+  // ---- set-up: 1/m, old bond vectors, lambda_0, coordinate magnitude
+  double rmax = 0.0;
+  for (int32_t a = tid; a < s; a += BLOCK) {
+    const int32_t g = atom_gid[a];
+    invm[a] = 1.0 / A.mass[g];
+    rmax = fmax(rmax, fmax(fabs(ux[g]), fmax(fabs(ux[S + g]), fabs(ux[2 * S + g]))));
+  }
   if (tid == 0) {
     invm[s] = 0.0;  // fill entries point here: zero coupling
     singular = 0;
   }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) rmax = fmax(rmax, __shfl_xor(rmax, off, 64));
+  if ((tid & 63) == 0) red[tid >> 6] = rmax;
   for (int32_t k = tid; k < n; k += BLOCK) {
     const int32_t ga = atom_gid[ra[k]], gb = atom_gid[rb[k]];
     ex[k] = rx[ga] - rx[gb];
@@ -175,6 +183,17 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(const DevPlan P, const int
     ez[k] = rx[2 * S + ga] - rx[2 * S + gb];
     lam[k] = A.warm ? A.lambda[cid[k]] : 0.0;
   }
+  __syncthreads();
+  // Rounding r' to doubles moves each output coordinate by at most
+  // |r'| 2^-53, so a bond vector formed from the returned positions differs
+  // from the one iterated here by at most delta = sqrt(3) rmax 2^-52.  The
+  // convergence test adds the resulting bound on |g| so that the returned
+  // positions themselves satisfy the tolerance.
+  double gr = red[0];
+#pragma unroll
+  for (int w = 1; w < BLOCK / 64; ++w) gr = fmax(gr, red[w]);
+  const double delta = 1.7320508075688772 * gr * 0x1.0p-52;
+  const double delta2 = 0.5 * delta * delta;
   __syncthreads();
 
   const int32_t H = md.n_levels;
@@ -247,8 +266,9 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(const DevPlan P, const int
         py -= c * ey[j];
         pz -= c * ez[j];
       }
-      const double g = 0.5 * (px * px + py * py + pz * pz - d2[k]);
-      double rel = fabs(g) / d2[k];
+      const double pp = px * px + py * py + pz * pz;
+      const double g = 0.5 * (pp - d2[k]);
+      double rel = (fabs(g) + sqrt(pp) * delta + delta2) / d2[k];
       if (!(rel <= DBL_MAX)) rel = INFINITY;  // NaN or Inf
       vmax = fmax(vmax, rel);
       y[k] = static_cast<T>(g);

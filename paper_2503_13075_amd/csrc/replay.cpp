@@ -26,7 +26,14 @@ int32_t replay_molecule(const ilves::MolPlan& M, int32_t S, const double* mass, 
   const int32_t n = M.n, s = M.s;
   std::vector<double> ex(n), ey(n), ez(n), lam(n, 0.0), invm(s + 1, 0.0);
   std::vector<T> y(n), F(M.nslots);
-  for (int32_t a = 0; a < s; ++a) invm[a] = 1.0 / mass[M.atom_gid[a]];
+  double rmax = 0.0;
+  for (int32_t a = 0; a < s; ++a) {
+    const int32_t g = M.atom_gid[a];
+    invm[a] = 1.0 / mass[g];
+    rmax = std::fmax(rmax, std::fmax(std::fabs(ru[g]), std::fmax(std::fabs(ru[S + g]), std::fabs(ru[2 * S + g]))));
+  }
+  const double delta = 1.7320508075688772 * rmax * 0x1.0p-52;
+  const double delta2 = 0.5 * delta * delta;
   for (int32_t k = 0; k < n; ++k) {
     const int32_t ga = M.atom_gid[M.ra[k]], gb = M.atom_gid[M.rb[k]];
     ex[k] = r[ga] - r[gb];
@@ -100,8 +107,9 @@ int32_t replay_molecule(const ilves::MolPlan& M, int32_t S, const double* mass, 
         py -= c * ey[j];
         pz -= c * ez[j];
       }
-      const double g = 0.5 * (px * px + py * py + pz * pz - M.d2[k]);
-      double rel = std::fabs(g) / M.d2[k];
+      const double pp = px * px + py * py + pz * pz;
+      const double g = 0.5 * (pp - M.d2[k]);
+      double rel = (std::fabs(g) + std::sqrt(pp) * delta + delta2) / M.d2[k];
       if (!(rel <= DBL_MAX)) rel = INFINITY;
       vmax = std::fmax(vmax, rel);
       y[k] = static_cast<T>(g);

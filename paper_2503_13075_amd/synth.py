@@ -535,8 +535,10 @@ def add_h_angles(sysm: System) -> System:
 # combining molecules
 
 def concat(systems: list, spacing: float = 2.0, name: str = "") -> System:
-    """Places molecules on a cubic grid ``spacing`` nm apart (inside a box of
-    a few tens of nm, like an MD system) and renumbers atoms."""
+    """Places molecule centres on a cubic grid ``spacing`` nm apart and
+    renumbers atoms.  Molecules may overlap in space (there are no
+    interactions between them); the grid keeps coordinates within a box of
+    a few tens of nm, like an MD system of the same atom count."""
     nm = len(systems)
     side = max(1, int(math.ceil(nm ** (1.0 / 3.0))))
     pairs, d, mass, r, kind, elem, starts = [], [], [], [], [], [], []
@@ -571,7 +573,7 @@ def random_tree_batch(n_mol: int = 4096, seed: int = 2, lo: int = 8, hi: int = 2
     """Many random-tree molecules of log-uniform size (all bonds constrained)."""
     sizes = batch_sizes(n_mol, seed, lo, hi)
     mols = [random_tree(int(sz), seed * 1_000_003 + i) for i, sz in enumerate(sizes)]
-    return concat(mols, spacing=4.0, name=f"random_tree_batch{n_mol}")
+    return concat(mols, spacing=1.5, name=f"random_tree_batch{n_mol}")
 
 
 def protein_system(seed: int = 1, n_res: int = 300) -> System:
@@ -586,7 +588,7 @@ def angles_system(seed: int = 3, n_prot: int = 20, n_res: int = 315, n_lipid: in
     H-X-H / H-X-Y angle constraints (lipids have no H so only bonds)."""
     mols = [add_h_angles(protein(n_res=n_res, seed=seed * 7919 + i)) for i in range(n_prot)]
     mols += [lipid_chain(seed * 104729 + j, lipid_len) for j in range(n_lipid)]
-    return concat(mols, spacing=6.0, name=f"angles_{n_prot}prot_{n_lipid}lipid")
+    return concat(mols, spacing=1.2, name=f"angles_{n_prot}prot_{n_lipid}lipid")
 
 
 def perturb(r: np.ndarray, sigma: float, seed: int) -> np.ndarray:
