@@ -107,8 +107,8 @@ int32_t ilves_plan_num_molecules(ilves_plan_t plan);
  * Plan statistics, host int64 array of ILVES_STAT_COUNT entries:
  *   [0] molecules, [1] constraints, [2] atoms in constraints,
  *   [3] stored factor entries, [4] fill entries, [5] factor updates,
- *   [6] largest level count, [7] sum of level counts, [8] molecules kept in
- *   LDS, [9] molecules in the global workspace, [10] workspace bytes,
+ *   [6] largest level count, [7] sum of level counts, [8] molecules whose factor fits in
+ *   LDS (mixed precision), [9] the others, [10] workspace bytes,
  *   [11] plan bytes on the device.
  */
 #define ILVES_STAT_COUNT 12
@@ -161,7 +161,7 @@ ilves_status_t ilves_solve_ex(ilves_plan_t plan, const double* r, const double* 
  *   mass [n_atoms], r, r_u, r_out [3][n_atoms], lambda [n_constraints]: host
  *   iters, status: host int32 arrays with room for n_constraints entries
  *   (at least the number of molecules); *n_molecules receives that number
- *   schedule_stats: host int64 [5] (molecules, factor entries, updates,
+ *   schedule_stats: host int64 [5] (molecules, factor entries, factor updates,
  *   largest level count, fill entries) or NULL
  */
 ilves_status_t ilves_plan_replay_host(int32_t n_atoms, int32_t n_constraints, const int32_t* pairs,

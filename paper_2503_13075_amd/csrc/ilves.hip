@@ -14,13 +14,22 @@
 //   C_kk = 1/m_a + 1/m_b,  C_kj = s_kx s_jx / m_x  (x the shared atom),
 // which is the position map of Eq. 6 taken along constraint k, so no atom
 // positions are formed until the end.  The Newton matrix has the same
-// pattern: A_kj = C_kj (e'_k . e_j).  Per molecule the vectors e, lambda,
-// 1/m and the LU factor live in LDS when they fit (a global workspace, L2
-// resident in practice, otherwise).  The LU is an up-looking factorisation
-// scheduled by elimination-tree level (all entries owned by the nodes of one
-// level are independent); the forward substitution is fused into it; the
-// backward substitution walks the levels down.  No atomics: every value has
-// one writer, so results are bitwise reproducible.
+// pattern: A_kj = C_kj (e'_k . e_j).
+//
+// The LU is an up-looking factorisation scheduled by elimination level:
+// rows are numbered level by level, and the entries owned by the rows of one
+// level (their diagonal and upper entries, plus the transposed lower ones)
+// are independent.  A diagonal entry gathers over its row's lower pattern
+// (and performs the forward substitution for its row at the same time) and
+// stores 1/U_jj in place of A_jj; an upper entry (j, m) and its transpose
+// (m, j) run over the planned list of rows coupled to both.  The backward
+// substitution walks the levels down.  Everything one level needs -- the
+// slot structure (column, transpose link, update lists) and the factor
+// values -- is kept in LDS when it fits, so a level costs a few dependent
+// LDS accesses plus one barrier; data used once per iteration (old and
+// unconstrained bond vectors, couplings, lambda) stays in a per-molecule
+// workspace in global memory, where it is L2 resident.  No atomics: every value has one writer, so results are bitwise
+// reproducible.
 //
 // Precision: FP64 throughout, or mixed (matrix, factor and triangular solves
 // in FP32 while e', g, lambda and positions stay FP64), which makes Newton
@@ -58,40 +67,46 @@ ilves_status_t fail(ilves_status_t s, const std::string& msg) {
 // ---------------------------------------------------------------------------
 // device plan layout
 
+// Placement of a molecule's per-level data:
+//   ALL_LDS:    slot structure and factor values in LDS
+//   STRUCT_LDS: slot structure in LDS, factor values in the workspace
+//   GLOBAL:     both read from global memory (molecules too large for LDS)
+enum { ALL_LDS = 0, STRUCT_LDS = 1, GLOBAL = 2 };
+
 struct MolDesc {
-  int32_t n, s, nslots, n_levels;
-  int32_t row_off;    // per-row arrays (ra, rb, d2, cid, row_nup)
-  int32_t rowp_off;   // row_start, n + 1 entries
-  int32_t slot_off;   // slot_col, slot_coef
+  int32_t n, s, n_up, n_l, n_upd, n_levels, n_pl;
+  int32_t wide;       // 0: 16-bit structure indices, 1: 32-bit
+  int32_t ix_off;     // structure block in the index pool of its width
+  int32_t coef_off;   // ucoef then lcoef
+  int32_t row_off;    // ra, rb, cid, d2
   int32_t atom_off;   // atom_gid
   int32_t incp_off;   // inc_ptr, s + 1 entries
   int32_t inc_off;    // inc
-  int32_t task_off;   // tasks
-  int32_t upd_off;    // upd4, updd
-  int32_t lvl_off;    // lvl_task and lvl_node, n_levels + 1 entries each
-  int32_t node_off;   // nodes
-  int64_t ws_off;     // byte offset of the molecule's arena in the workspace
+  int64_t ws_off;     // byte offset of the molecule's workspace
 };
+
+// Structure block of one molecule, in this order:
+//   up_start[n+1] l_start[n+1] lvl_row[H+1] pl_start[H+1] ustart[n_up+1]
+//   ucol[n_up] utr[n_up] lcol[n_l] ltr[n_l] upd_a[n_upd] upd_b[n_upd]
+//   plist[n_pl]
+__host__ __device__ inline int64_t struct_elems(int32_t n, int32_t H, int32_t n_up, int32_t n_l, int32_t n_upd,
+                                                int32_t n_pl) {
+  return 2 * (static_cast<int64_t>(n) + 1) + 2 * (static_cast<int64_t>(H) + 1) + 3 * static_cast<int64_t>(n_up) + 1 +
+         2 * static_cast<int64_t>(n_l) + 2 * static_cast<int64_t>(n_upd) + n_pl;
+}
 
 struct DevPlan {
   const MolDesc* mol;
+  const uint16_t* ix16;
+  const int32_t* ix32;
+  const int32_t* coef;
+  const int32_t* ra;
+  const int32_t* rb;
+  const int32_t* cid;
+  const double* d2;
   const int32_t* atom_gid;
   const int32_t* inc_ptr;
   const int32_t* inc;
-  const int32_t* row_start;
-  const int32_t* row_nup;
-  const int32_t* ra;
-  const int32_t* rb;
-  const double* d2;
-  const int32_t* cid;
-  const int32_t* slot_col;
-  const int32_t* slot_coef;
-  const int4* tasks;
-  const int4* upd4;
-  const int32_t* updd;
-  const int32_t* lvl_task;
-  const int32_t* lvl_node;
-  const int32_t* nodes;
 };
 
 struct SolveArgs {
@@ -110,10 +125,17 @@ struct SolveArgs {
   int32_t chord;     // 0: Newton, 1: chord
 };
 
+__host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~static_cast<size_t>(15); }
+
+// FP64 workspace of a molecule: e, u (3n each), lambda, C_kk (n each), the
+// couplings of every off-diagonal slot, 1/m (s + 1)
+__host__ __device__ inline size_t ws_vec_bytes(int32_t n, int32_t s, int32_t n_up, int32_t n_l) {
+  return align16(8 * (8 * static_cast<size_t>(n) + n_up + n_l + s + 1));
+}
+// factor values: F (off-diagonal slots), D (diagonal, then 1/U_jj), y
 template <typename T>
-__host__ __device__ constexpr size_t arena_bytes(int32_t n, int32_t s, int32_t nslots) {
-  return (static_cast<size_t>(8) * (4 * static_cast<size_t>(n) + s + 1) +
-          sizeof(T) * (static_cast<size_t>(n) + nslots) + 15) & ~static_cast<size_t>(15);
+__host__ __device__ inline size_t value_bytes(int32_t n, int32_t n_up, int32_t n_l) {
+  return align16(sizeof(T) * (static_cast<size_t>(n_up) + n_l + 2 * static_cast<size_t>(n)));
 }
 
 template <typename T> __device__ inline T pivot_eps();
@@ -123,7 +145,7 @@ template <> __device__ inline float pivot_eps<float>() { return 1e-6f; }
 // ---------------------------------------------------------------------------
 // the solve kernel: one workgroup per molecule
 
-template <typename T, bool IN_LDS, int BLOCK>
+template <typename T, typename Idx, int MODE, int BLOCK>
 __global__ void __launch_bounds__(BLOCK) solve_kernel(const DevPlan P, const int32_t* __restrict__ mols,
                                                       const SolveArgs A) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -131,38 +153,73 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(const DevPlan P, const int
   __shared__ int32_t singular;
 
   const int tid = threadIdx.x;
-  const int32_t m = mols[blockIdx.x];
-  const MolDesc md = P.mol[m];
-  const int32_t n = md.n, s = md.s;
-  unsigned char* base = IN_LDS ? smem : (A.ws + md.ws_off);
-  double* __restrict__ ex = reinterpret_cast<double*>(base);
+  const int32_t m_idx = mols[blockIdx.x];
+  const MolDesc md = P.mol[m_idx];
+  const int32_t n = md.n, s = md.s, n_up = md.n_up, n_l = md.n_l, n_upd = md.n_upd, H = md.n_levels;
+  const int32_t n_pl = md.n_pl;
+  const int32_t S = A.n_atoms;
+
+  // ---- structure (LDS copy unless GLOBAL)
+  const Idx* gst = reinterpret_cast<const Idx*>(sizeof(Idx) == 2 ? static_cast<const void*>(P.ix16)
+                                                                  : static_cast<const void*>(P.ix32)) +
+                   md.ix_off;
+  const int64_t nst = struct_elems(n, H, n_up, n_l, n_upd, n_pl);
+  const Idx* st;
+  if (MODE == GLOBAL) {
+    st = gst;
+  } else {
+    Idx* lst = reinterpret_cast<Idx*>(smem);
+    // 16-byte copies of the (16-byte aligned) block, then the tail
+    const int64_t nvec = (nst * static_cast<int64_t>(sizeof(Idx))) / 16;
+    const int4* gv = reinterpret_cast<const int4*>(gst);
+    int4* lv = reinterpret_cast<int4*>(lst);
+    for (int64_t i = tid; i < nvec; i += BLOCK) lv[i] = gv[i];
+    for (int64_t i = nvec * 16 / static_cast<int64_t>(sizeof(Idx)) + tid; i < nst; i += BLOCK) lst[i] = gst[i];
+    st = lst;
+  }
+  const Idx* __restrict__ up_start = st;
+  const Idx* __restrict__ l_start = up_start + n + 1;
+  const Idx* __restrict__ lvl_row = l_start + n + 1;
+  const Idx* __restrict__ pl_start = lvl_row + H + 1;
+  const Idx* __restrict__ ustart = pl_start + H + 1;
+  const Idx* __restrict__ ucol = ustart + n_up + 1;
+  const Idx* __restrict__ utr = ucol + n_up;
+  // lower-slot arrays are indexed by the F index t in [n_up, n_up + n_l)
+  const Idx* __restrict__ lcol = (utr + n_up) - n_up;
+  const Idx* __restrict__ ltr = (utr + n_up + n_l) - n_up;
+  const Idx* __restrict__ upd_a = utr + n_up + 2 * n_l;
+  const Idx* __restrict__ upd_b = upd_a + n_upd;
+  const Idx* __restrict__ plist = upd_b + n_upd;
+  const int32_t* __restrict__ coef = P.coef + md.coef_off;
+
+  // ---- workspace and values
+  unsigned char* wsb = A.ws + md.ws_off;
+  double* __restrict__ ex = reinterpret_cast<double*>(wsb);
   double* __restrict__ ey = ex + n;
   double* __restrict__ ez = ey + n;
-  double* __restrict__ lam = ez + n;
-  double* __restrict__ invm = lam + n;
-  T* __restrict__ y = reinterpret_cast<T*>(invm + s + 1);
-  T* __restrict__ F = y + n;
+  double* __restrict__ u_x = ez + n;
+  double* __restrict__ u_y = u_x + n;
+  double* __restrict__ u_z = u_y + n;
+  double* __restrict__ lam = u_z + n;
+  double* __restrict__ cd = lam + n;
+  double* __restrict__ cf = cd + n;
+  double* __restrict__ invm = cf + n_up + n_l;
+  T* __restrict__ F;
+  if (MODE == ALL_LDS) F = reinterpret_cast<T*>(smem + align16(sizeof(Idx) * static_cast<size_t>(nst)));
+  else F = reinterpret_cast<T*>(wsb + ws_vec_bytes(n, s, n_up, n_l));
+  T* __restrict__ D = F + n_up + n_l;
+  T* __restrict__ y = D + n;
 
   const int32_t* __restrict__ atom_gid = P.atom_gid + md.atom_off;
   const int32_t* __restrict__ ra = P.ra + md.row_off;
   const int32_t* __restrict__ rb = P.rb + md.row_off;
-  const double* __restrict__ d2 = P.d2 + md.row_off;
   const int32_t* __restrict__ cid = P.cid + md.row_off;
-  const int32_t* __restrict__ row_nup = P.row_nup + md.row_off;
-  const int32_t* __restrict__ row_start = P.row_start + md.rowp_off;
-  const int32_t* __restrict__ slot_col = P.slot_col + md.slot_off;
-  const int32_t* __restrict__ slot_coef = P.slot_coef + md.slot_off;
-  const int4* __restrict__ tasks = P.tasks + md.task_off;
-  const int4* __restrict__ upd4 = P.upd4 + md.upd_off;
-  const int32_t* __restrict__ updd = P.updd + md.upd_off;
-  const int32_t* __restrict__ lvl_task = P.lvl_task + md.lvl_off;
-  const int32_t* __restrict__ lvl_node = P.lvl_node + md.lvl_off;
-  const int32_t* __restrict__ nodes = P.nodes + md.node_off;
-  const int32_t S = A.n_atoms;
+  const double* __restrict__ d2 = P.d2 + md.row_off;
   const double* __restrict__ rx = A.r;
   const double* __restrict__ ux = A.r_u;
 
-  // ---- set-up: 1/m, old bond vectors, lambda_0, coordinate magnitude
+  // ---- set-up: 1/m, old and unconstrained bond vectors, lambda_0,
+  //      couplings, coordinate magnitude
   double rmax = 0.0;
   for (int32_t a = tid; a < s; a += BLOCK) {
     const int32_t g = atom_gid[a];
@@ -173,17 +230,26 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(const DevPlan P, const int
     invm[s] = 0.0;  // fill entries point here: zero coupling
     singular = 0;
   }
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) rmax = fmax(rmax, __shfl_xor(rmax, off, 64));
-  if ((tid & 63) == 0) red[tid >> 6] = rmax;
   for (int32_t k = tid; k < n; k += BLOCK) {
     const int32_t ga = atom_gid[ra[k]], gb = atom_gid[rb[k]];
     ex[k] = rx[ga] - rx[gb];
     ey[k] = rx[S + ga] - rx[S + gb];
     ez[k] = rx[2 * S + ga] - rx[2 * S + gb];
+    u_x[k] = ux[ga] - ux[gb];
+    u_y[k] = ux[S + ga] - ux[S + gb];
+    u_z[k] = ux[2 * S + ga] - ux[2 * S + gb];
     lam[k] = A.warm ? A.lambda[cid[k]] : 0.0;
   }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) rmax = fmax(rmax, __shfl_xor(rmax, off, 64));
+  if ((tid & 63) == 0) red[tid >> 6] = rmax;
   __syncthreads();
+  for (int32_t k = tid; k < n; k += BLOCK) cd[k] = invm[ra[k]] + invm[rb[k]];
+  for (int32_t q = tid; q < n_up + n_l; q += BLOCK) {
+    const int32_t c = coef[q];
+    const double v = invm[c >> 1];
+    cf[q] = (c & 1) ? -v : v;
+  }
   // Rounding r' to doubles moves each output coordinate by at most
   // |r'| 2^-53, so a bond vector formed from the returned positions differs
   // from the one iterated here by at most delta = sqrt(3) rmax 2^-52.  The
@@ -196,72 +262,98 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(const DevPlan P, const int
   const double delta2 = 0.5 * delta * delta;
   __syncthreads();
 
-  const int32_t H = md.n_levels;
+  // row k of A(x, r), x having bond vector (px, py, pz); level-0 rows have
+  // no lower entries, so their factorisation is just the inverted pivot
+  const int32_t level1 = H > 1 ? static_cast<int32_t>(lvl_row[1]) : n;
+  auto build_row = [&](int32_t k, double px, double py, double pz) {
+    const T akk = static_cast<T>(cd[k] * (px * ex[k] + py * ey[k] + pz * ez[k]));
+    if (k < level1) {
+      if (!(fabs(akk) > T(0))) singular = 1;
+      D[k] = T(1) / akk;
+    } else {
+      D[k] = akk;
+    }
+    for (int32_t q = up_start[k], q1 = up_start[k + 1]; q < q1; ++q) {
+      const int32_t j = ucol[q];
+      F[q] = static_cast<T>(cf[q] * (px * ex[j] + py * ey[j] + pz * ez[j]));
+    }
+    for (int32_t t = l_start[k], t1 = l_start[k + 1]; t < t1; ++t) {
+      const int32_t j = lcol[t];
+      F[t] = static_cast<T>(cf[t] * (px * ex[j] + py * ey[j] + pz * ez[j]));
+    }
+  };
+
+  // one elimination level: diagonal entries (forward substitution fused)
+  // and, unless only the forward substitution is wanted, upper entries
+  auto factor_level = [&](int32_t h, bool with_forward, bool with_factor) {
+    const int32_t r0 = lvl_row[h], r1 = lvl_row[h + 1];
+    const int32_t nr = r1 - r0;
+    const int32_t p0 = pl_start[h];
+    const int32_t items = nr + (with_factor ? static_cast<int32_t>(pl_start[h + 1]) - p0 : 0);
+    for (int32_t idx = tid; idx < items; idx += BLOCK) {
+      if (idx < nr) {
+        const int32_t j = r0 + idx;
+        T acc = D[j], yj = y[j];
+        const T a0 = acc;
+        for (int32_t t = l_start[j], t1 = l_start[j + 1]; t < t1; ++t) {
+          const int32_t i = lcol[t];
+          const T l = F[t] * D[i];
+          if (with_factor) acc -= l * F[ltr[t]];
+          if (with_forward) yj -= l * y[i];
+        }
+        if (with_factor) {
+          if (!(fabs(acc) > pivot_eps<T>() * fabs(a0))) singular = 1;
+          D[j] = T(1) / acc;
+        }
+        if (with_forward) y[j] = yj;
+      } else {
+        const int32_t q = plist[p0 + idx - nr];
+        const int32_t tr = utr[q];
+        T au = F[q], aw = F[tr];
+        for (int32_t u = ustart[q], u1 = ustart[q + 1]; u < u1; ++u) {
+          const int32_t pa = upd_a[u], pb = upd_b[u];
+          const T di = D[lcol[pa]];
+          au -= F[pa] * di * F[ltr[pb]];
+          aw -= F[pb] * di * F[ltr[pa]];
+        }
+        F[q] = au;
+        F[tr] = aw;
+      }
+    }
+  };
 
   // ---- chord: factor A(r, r) once
   if (A.chord) {
-    for (int32_t k = tid; k < n; k += BLOCK) {
-      const double w = invm[ra[k]] + invm[rb[k]];
-      const double ekx = ex[k], eky = ey[k], ekz = ez[k];
-      const int32_t q0 = row_start[k], q1 = row_start[k + 1];
-      F[q0] = static_cast<T>(w * (ekx * ekx + eky * eky + ekz * ekz));
-      for (int32_t q = q0 + 1; q < q1; ++q) {
-        const int32_t j = slot_col[q];
-        const int32_t cf = slot_coef[q];
-        const double c = (cf & 1) ? -invm[cf >> 1] : invm[cf >> 1];
-        F[q] = static_cast<T>(c * (ekx * ex[j] + eky * ey[j] + ekz * ez[j]));
-      }
-    }
+    for (int32_t k = tid; k < n; k += BLOCK) build_row(k, ex[k], ey[k], ez[k]);
     __syncthreads();
-    for (int32_t h = 0; h < H; ++h) {
-      for (int32_t t = lvl_task[h] + tid; t < lvl_task[h + 1]; t += BLOCK) {
-        const int4 tk = tasks[t];
-        if (tk.y < 0) {
-          T acc = F[tk.x];
-          const T a0 = acc;
-          for (int32_t u = tk.z; u < tk.w; ++u) {
-            const int4 q = upd4[u];
-            acc -= F[q.x] * F[updd[u]] * F[q.y];
-          }
-          if (!(fabs(acc) > pivot_eps<T>() * fabs(a0))) singular = 1;
-          F[tk.x] = T(1) / acc;
-        } else {
-          T au = F[tk.x], aw = F[tk.y];
-          for (int32_t u = tk.z; u < tk.w; ++u) {
-            const int4 q = upd4[u];
-            const T dinv = F[updd[u]];
-            au -= F[q.x] * dinv * F[q.y];
-            aw -= F[q.z] * dinv * F[q.w];
-          }
-          F[tk.x] = au;
-          F[tk.y] = aw;
-        }
-      }
+    for (int32_t h = 1; h < H; ++h) {
+      factor_level(h, false, true);
       __syncthreads();
     }
   }
 
   int32_t it = 0;
-  int32_t st = ILVES_ERR_NOT_CONVERGED;
+  int32_t st_code = ILVES_ERR_NOT_CONVERGED;
   const bool chord_singular = A.chord && singular;
-  if (chord_singular) st = ILVES_ERR_SINGULAR;
+  if (chord_singular) st_code = ILVES_ERR_SINGULAR;
   while (!chord_singular) {
     // ---- residual at the current lambda; Newton: rebuild the matrix rows
     double vmax = 0.0;
     for (int32_t k = tid; k < n; k += BLOCK) {
-      const int32_t la = ra[k], lb = rb[k];
-      const int32_t ga = atom_gid[la], gb = atom_gid[lb];
-      const double w = invm[la] + invm[lb];
-      const double lk = lam[k] * w;
-      const double ekx = ex[k], eky = ey[k], ekz = ez[k];
-      double px = ux[ga] - ux[gb] - lk * ekx;
-      double py = ux[S + ga] - ux[S + gb] - lk * eky;
-      double pz = ux[2 * S + ga] - ux[2 * S + gb] - lk * ekz;
-      const int32_t q0 = row_start[k], q1 = row_start[k + 1];
-      for (int32_t q = q0 + 1; q < q1; ++q) {
-        const int32_t j = slot_col[q];
-        const int32_t cf = slot_coef[q];
-        const double c = ((cf & 1) ? -invm[cf >> 1] : invm[cf >> 1]) * lam[j];
+      const double lk = lam[k] * cd[k];
+      double px = u_x[k] - lk * ex[k];
+      double py = u_y[k] - lk * ey[k];
+      double pz = u_z[k] - lk * ez[k];
+      for (int32_t q = up_start[k], q1 = up_start[k + 1]; q < q1; ++q) {
+        const int32_t j = ucol[q];
+        const double c = cf[q] * lam[j];
+        px -= c * ex[j];
+        py -= c * ey[j];
+        pz -= c * ez[j];
+      }
+      for (int32_t t = l_start[k], t1 = l_start[k + 1]; t < t1; ++t) {
+        const int32_t j = lcol[t];
+        const double c = cf[t] * lam[j];
         px -= c * ex[j];
         py -= c * ey[j];
         pz -= c * ez[j];
@@ -272,15 +364,7 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(const DevPlan P, const int
       if (!(rel <= DBL_MAX)) rel = INFINITY;  // NaN or Inf
       vmax = fmax(vmax, rel);
       y[k] = static_cast<T>(g);
-      if (!A.chord) {
-        F[q0] = static_cast<T>(w * (px * ekx + py * eky + pz * ekz));
-        for (int32_t q = q0 + 1; q < q1; ++q) {
-          const int32_t j = slot_col[q];
-          const int32_t cf = slot_coef[q];
-          const double c = (cf & 1) ? -invm[cf >> 1] : invm[cf >> 1];
-          F[q] = static_cast<T>(c * (px * ex[j] + py * ey[j] + pz * ez[j]));
-        }
-      }
+      if (!A.chord) build_row(k, px, py, pz);
     }
     // workgroup max of the relative violation
 #pragma unroll
@@ -290,60 +374,24 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(const DevPlan P, const int
     double gmax = red[0];
 #pragma unroll
     for (int w = 1; w < BLOCK / 64; ++w) gmax = fmax(gmax, red[w]);
-    if (gmax == INFINITY) { st = ILVES_ERR_NONFINITE; break; }
-    if (gmax <= A.tol) { st = ILVES_OK; break; }
-    if (it >= A.max_iter) { st = ILVES_ERR_NOT_CONVERGED; break; }
+    if (gmax == INFINITY) { st_code = ILVES_ERR_NONFINITE; break; }
+    if (gmax <= A.tol) { st_code = ILVES_OK; break; }
+    if (it >= A.max_iter) { st_code = ILVES_ERR_NOT_CONVERGED; break; }
 
     // ---- factorisation fused with the forward substitution (Newton), or
     //      the forward substitution alone (chord)
-    for (int32_t h = 0; h < H; ++h) {
-      for (int32_t t = lvl_task[h] + tid; t < lvl_task[h + 1]; t += BLOCK) {
-        const int4 tk = tasks[t];
-        if (tk.y < 0) {
-          const int32_t j = -tk.y - 1;
-          T yj = y[j];
-          if (A.chord) {
-            for (int32_t u = tk.z; u < tk.w; ++u) {
-              const int4 q = upd4[u];
-              yj -= F[q.x] * F[updd[u]] * y[q.z];
-            }
-          } else {
-            T acc = F[tk.x];
-            const T a0 = acc;
-            for (int32_t u = tk.z; u < tk.w; ++u) {
-              const int4 q = upd4[u];
-              const T l = F[q.x] * F[updd[u]];
-              acc -= l * F[q.y];
-              yj -= l * y[q.z];
-            }
-            if (!(fabs(acc) > pivot_eps<T>() * fabs(a0))) singular = 1;
-            F[tk.x] = T(1) / acc;
-          }
-          y[j] = yj;
-        } else if (!A.chord) {
-          T au = F[tk.x], aw = F[tk.y];
-          for (int32_t u = tk.z; u < tk.w; ++u) {
-            const int4 q = upd4[u];
-            const T dinv = F[updd[u]];
-            au -= F[q.x] * dinv * F[q.y];
-            aw -= F[q.z] * dinv * F[q.w];
-          }
-          F[tk.x] = au;
-          F[tk.y] = aw;
-        }
-      }
+    for (int32_t h = 1; h < H; ++h) {
+      factor_level(h, true, !A.chord);
       __syncthreads();
     }
-    if (singular) { st = ILVES_ERR_SINGULAR; break; }
+    if (singular) { st_code = ILVES_ERR_SINGULAR; break; }
 
     // ---- backward substitution and lambda update
     for (int32_t h = H - 1; h >= 0; --h) {
-      for (int32_t i = lvl_node[h] + tid; i < lvl_node[h + 1]; i += BLOCK) {
-        const int32_t k = nodes[i];
-        const int32_t q0 = row_start[k];
+      for (int32_t k = lvl_row[h] + tid, k1 = lvl_row[h + 1]; k < k1; k += BLOCK) {
         T acc = y[k];
-        for (int32_t q = q0 + 1; q <= q0 + row_nup[k]; ++q) acc -= F[q] * y[slot_col[q]];
-        const T z = acc * F[q0];
+        for (int32_t q = up_start[k], q1 = up_start[k + 1]; q < q1; ++q) acc -= F[q] * y[ucol[q]];
+        const T z = acc * D[k];
         y[k] = z;
         lam[k] += static_cast<double>(z);
       }
@@ -373,8 +421,8 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(const DevPlan P, const int
     A.r_out[2 * S + g] = ux[2 * S + g] - im * dz;
   }
   if (tid == 0) {
-    A.iters[m] = it;
-    A.status[m] = st;
+    A.iters[m_idx] = it;
+    A.status[m_idx] = st_code;
   }
 }
 
@@ -391,20 +439,27 @@ __global__ void copy_free_atoms(const int32_t* __restrict__ idx, int32_t n_free,
 
 using KernelFn = void (*)(DevPlan, const int32_t*, SolveArgs);
 
-template <typename T, bool L>
+template <typename T, typename Idx, int MODE>
 KernelFn pick_block(int block) {
   switch (block) {
-    case 64: return solve_kernel<T, L, 64>;
-    case 128: return solve_kernel<T, L, 128>;
-    case 256: return solve_kernel<T, L, 256>;
-    case 512: return solve_kernel<T, L, 512>;
-    default: return solve_kernel<T, L, 1024>;
+    case 64: return solve_kernel<T, Idx, MODE, 64>;
+    case 128: return solve_kernel<T, Idx, MODE, 128>;
+    case 256: return solve_kernel<T, Idx, MODE, 256>;
+    case 512: return solve_kernel<T, Idx, MODE, 512>;
+    default: return solve_kernel<T, Idx, MODE, 1024>;
   }
 }
 
-KernelFn pick_kernel(bool fp32, bool lds, int block) {
-  if (fp32) return lds ? pick_block<float, true>(block) : pick_block<float, false>(block);
-  return lds ? pick_block<double, true>(block) : pick_block<double, false>(block);
+template <typename T>
+KernelFn pick_mode(int mode, bool wide, int block) {
+  if (wide) return pick_block<T, int32_t, GLOBAL>(block);
+  if (mode == ALL_LDS) return pick_block<T, uint16_t, ALL_LDS>(block);
+  if (mode == STRUCT_LDS) return pick_block<T, uint16_t, STRUCT_LDS>(block);
+  return pick_block<T, uint16_t, GLOBAL>(block);
+}
+
+KernelFn pick_kernel(bool fp32, int mode, bool wide, int block) {
+  return fp32 ? pick_mode<float>(mode, wide, block) : pick_mode<double>(mode, wide, block);
 }
 
 constexpr int kLdsMax = 160 * 1024 - 1024;  // dynamic LDS a molecule may use
@@ -412,7 +467,8 @@ constexpr int kStreams = 4;                 // concurrent launch groups
 
 struct Group {
   int block = 256;
-  bool lds = true;
+  int mode = ALL_LDS;
+  bool wide = false;
   int lds_bytes = 0;
   int32_t first = 0;  // into the device molecule-list array
   int32_t count = 0;
@@ -428,7 +484,6 @@ struct ilves_plan {
   int32_t n_atoms = 0, n_con = 0;
   ilves_options_t opt{};
   std::vector<ilves::MolPlan> mols;   // host copy, in plan order
-  std::vector<int32_t> order;         // launch order (largest first)
   DevPlan dp{};
   void* d_buf = nullptr;
   size_t buf_bytes = 0;
@@ -447,7 +502,7 @@ struct ilves_plan {
 namespace {
 
 int auto_block(int32_t n, int32_t cap) {
-  int b = n <= 64 ? 64 : n <= 256 ? 128 : n <= 1024 ? 256 : 512;
+  int b = n <= 64 ? 64 : n <= 256 ? 128 : n <= 1024 ? 256 : n <= 4096 ? 512 : 1024;
   return std::min(b, cap);
 }
 
@@ -459,143 +514,154 @@ size_t push_array(std::vector<unsigned char>& blob, const std::vector<V>& v) {
   return off;
 }
 
+template <typename V>
+void append(std::vector<V>& dst, const std::vector<int32_t>& src) {
+  for (int32_t x : src) dst.push_back(static_cast<V>(x));
+}
+
+// placement of one molecule for value type T: mode and LDS bytes
+template <typename T>
+std::pair<int, int> placement(const ilves::MolPlan& M, bool wide, int64_t lds_limit) {
+  if (wide) return {GLOBAL, 0};
+  const size_t sb = align16(2 * static_cast<size_t>(
+      struct_elems(M.n, M.n_levels, M.n_up, M.n_l, M.n_upd, static_cast<int32_t>(M.plist.size()))));
+  const size_t vb = value_bytes<T>(M.n, M.n_up, M.n_l);
+  if (static_cast<int64_t>(sb + vb) <= lds_limit) return {ALL_LDS, static_cast<int>(sb + vb)};
+  if (static_cast<int64_t>(sb) <= lds_limit) return {STRUCT_LDS, static_cast<int>(sb)};
+  return {GLOBAL, 0};
+}
+
 ilves_status_t build_device_plan(ilves_plan* P) {
   const int32_t nm = static_cast<int32_t>(P->mols.size());
   std::vector<MolDesc> desc(nm);
-  std::vector<int32_t> atom_gid, inc_ptr, inc, row_start, row_nup, ra, rb, cid, slot_col, slot_coef,
-      updd, lvl_task, lvl_node, nodes;
+  std::vector<uint16_t> ix16;
+  std::vector<int32_t> ix32, coef, ra, rb, cid, atom_gid, inc_ptr, inc;
   std::vector<double> d2;
-  std::vector<int4> tasks, upd4;
-  int64_t fill = 0, nupd = 0, maxlev = 0, sumlev = 0, nslots = 0, natoms = 0, ncon = 0;
+  std::vector<char> wide(nm, 0);
+  int64_t fill = 0, work = 0, maxlev = 0, sumlev = 0, nslots = 0, natoms = 0, ncon = 0;
   size_t ws = 0;
-  int64_t in_lds = 0, in_ws = 0;
   for (int32_t i = 0; i < nm; ++i) {
     const ilves::MolPlan& M = P->mols[i];
     MolDesc& D = desc[i];
     D.n = M.n;
     D.s = M.s;
-    D.nslots = M.nslots;
+    D.n_up = M.n_up;
+    D.n_l = M.n_l;
+    D.n_upd = M.n_upd;
     D.n_levels = M.n_levels;
+    D.n_pl = static_cast<int32_t>(M.plist.size());
+    const int64_t total = static_cast<int64_t>(M.n_up) + M.n_l;
+    wide[i] = (total >= 65535 || M.n >= 65535 || M.n_upd >= 65535) ? 1 : 0;
+    D.wide = wide[i];
+    std::vector<int32_t> blockv;
+    blockv.reserve(static_cast<size_t>(struct_elems(M.n, M.n_levels, M.n_up, M.n_l, M.n_upd, D.n_pl)));
+    for (const auto* v : {&M.up_start, &M.l_start, &M.lvl_row, &M.pl_start, &M.ustart, &M.ucol, &M.utr, &M.lcol,
+                          &M.ltr, &M.upd_a, &M.upd_b, &M.plist})
+      blockv.insert(blockv.end(), v->begin(), v->end());
+    if (static_cast<int64_t>(blockv.size()) != struct_elems(M.n, M.n_levels, M.n_up, M.n_l, M.n_upd, D.n_pl))
+      return fail(ILVES_ERR_ARG, "internal: structure block size mismatch");
+    if (wide[i]) {
+      while (ix32.size() % 4) ix32.push_back(0);
+      D.ix_off = static_cast<int32_t>(ix32.size());
+      append(ix32, blockv);
+    } else {
+      while (ix16.size() % 8) ix16.push_back(0);  // 16-byte aligned blocks
+      D.ix_off = static_cast<int32_t>(ix16.size());
+      append(ix16, blockv);
+    }
+    D.coef_off = static_cast<int32_t>(coef.size());
+    coef.insert(coef.end(), M.ucoef.begin(), M.ucoef.end());
+    coef.insert(coef.end(), M.lcoef.begin(), M.lcoef.end());
     D.row_off = static_cast<int32_t>(ra.size());
-    D.rowp_off = static_cast<int32_t>(row_start.size());
-    D.slot_off = static_cast<int32_t>(slot_col.size());
-    D.atom_off = static_cast<int32_t>(atom_gid.size());
-    D.incp_off = static_cast<int32_t>(inc_ptr.size());
-    D.inc_off = static_cast<int32_t>(inc.size());
-    D.task_off = static_cast<int32_t>(tasks.size());
-    D.upd_off = static_cast<int32_t>(upd4.size());
-    D.lvl_off = static_cast<int32_t>(lvl_task.size());
-    D.node_off = static_cast<int32_t>(nodes.size());
-    atom_gid.insert(atom_gid.end(), M.atom_gid.begin(), M.atom_gid.end());
-    inc_ptr.insert(inc_ptr.end(), M.inc_ptr.begin(), M.inc_ptr.end());
-    inc.insert(inc.end(), M.inc.begin(), M.inc.end());
-    row_start.insert(row_start.end(), M.row_start.begin(), M.row_start.end());
-    row_nup.insert(row_nup.end(), M.row_nup.begin(), M.row_nup.end());
     ra.insert(ra.end(), M.ra.begin(), M.ra.end());
     rb.insert(rb.end(), M.rb.begin(), M.rb.end());
-    d2.insert(d2.end(), M.d2.begin(), M.d2.end());
     cid.insert(cid.end(), M.cid.begin(), M.cid.end());
-    slot_col.insert(slot_col.end(), M.slot_col.begin(), M.slot_col.end());
-    slot_coef.insert(slot_coef.end(), M.slot_coef.begin(), M.slot_coef.end());
-    for (const auto& t : M.tasks) tasks.push_back(make_int4(t.out0, t.out1, t.u0, t.u1));
-    for (const auto& u : M.upd) {
-      upd4.push_back(make_int4(u.a, u.b, u.c, u.e));
-      updd.push_back(u.d);
-    }
-    lvl_task.insert(lvl_task.end(), M.lvl_task.begin(), M.lvl_task.end());
-    lvl_node.insert(lvl_node.end(), M.lvl_node.begin(), M.lvl_node.end());
-    nodes.insert(nodes.end(), M.nodes.begin(), M.nodes.end());
-    const size_t a64 = arena_bytes<double>(M.n, M.s, M.nslots);
-    if (static_cast<int64_t>(a64) > P->opt.lds_limit) {
-      D.ws_off = static_cast<int64_t>(ws);
-      ws += (a64 + 255) & ~static_cast<size_t>(255);
-    } else {
-      D.ws_off = -1;
-    }
+    d2.insert(d2.end(), M.d2.begin(), M.d2.end());
+    D.atom_off = static_cast<int32_t>(atom_gid.size());
+    atom_gid.insert(atom_gid.end(), M.atom_gid.begin(), M.atom_gid.end());
+    D.incp_off = static_cast<int32_t>(inc_ptr.size());
+    inc_ptr.insert(inc_ptr.end(), M.inc_ptr.begin(), M.inc_ptr.end());
+    D.inc_off = static_cast<int32_t>(inc.size());
+    inc.insert(inc.end(), M.inc.begin(), M.inc.end());
+    D.ws_off = static_cast<int64_t>(ws);
+    ws += (ws_vec_bytes(M.n, M.s, M.n_up, M.n_l) + value_bytes<double>(M.n, M.n_up, M.n_l) + 255) &
+          ~static_cast<size_t>(255);
     fill += M.fill;
-    nupd += static_cast<int64_t>(M.upd.size());
+    work += M.n_upd;
     maxlev = std::max<int64_t>(maxlev, M.n_levels);
     sumlev += M.n_levels;
-    nslots += M.nslots;
+    nslots += total + M.n;
     natoms += M.s;
     ncon += M.n;
   }
-  // launch groups per precision: molecules sorted by FP64 arena size
-  // (largest first), grouped by block size and LDS residency
+  // launch order: largest structure first
   std::vector<int32_t> ord(nm);
   for (int32_t i = 0; i < nm; ++i) ord[i] = i;
   std::stable_sort(ord.begin(), ord.end(), [&](int32_t x, int32_t y) {
-    return arena_bytes<double>(desc[x].n, desc[x].s, desc[x].nslots) >
-           arena_bytes<double>(desc[y].n, desc[y].s, desc[y].nslots);
+    return static_cast<int64_t>(desc[x].n_up) + desc[x].n_l + desc[x].n >
+           static_cast<int64_t>(desc[y].n_up) + desc[y].n_l + desc[y].n;
   });
-  P->order = ord;
   std::vector<int32_t> lists;
+  int64_t in_lds = 0, in_ws = 0;
   for (int prec = 0; prec < 2; ++prec) {
     P->groups[prec].clear();
-    // key: (lds, block); bucket the LDS size by powers of two to keep occupancy
-    struct Key { bool lds; int block; int bucket; };
+    struct Key { int mode; bool wide; int block; int bucket; };
     std::vector<std::pair<Key, std::vector<int32_t>>> buckets;
+    std::vector<int> lds_of(nm, 0);
     for (int32_t i : ord) {
-      const MolDesc& D = desc[i];
-      const size_t a = prec == 0 ? arena_bytes<double>(D.n, D.s, D.nslots) : arena_bytes<float>(D.n, D.s, D.nslots);
-      const bool lds = static_cast<int64_t>(a) <= P->opt.lds_limit;
-      if (!lds && D.ws_off < 0) return fail(ILVES_ERR_ARG, "internal: molecule without workspace");
-      const int cap = P->opt.block_threads > 0 ? P->opt.block_threads : 1024;
-      const int block = auto_block(D.n, cap);
-      int bucket = 0;
-      if (lds) {
-        size_t lim = 1024;
-        while (lim < a) { lim <<= 1; ++bucket; }
+      const ilves::MolPlan& M = P->mols[i];
+      auto pl = prec == 0 ? placement<double>(M, wide[i], P->opt.lds_limit)
+                          : placement<float>(M, wide[i], P->opt.lds_limit);
+      lds_of[i] = pl.second;
+      if (prec == 1) {
+        if (pl.first == ALL_LDS) ++in_lds; else ++in_ws;
       }
+      const int cap = P->opt.block_threads > 0 ? P->opt.block_threads : 1024;
+      const int block = auto_block(M.n, cap);
+      int bucket = 0;
+      if (pl.second > 0) {
+        size_t lim = 1024;
+        while (static_cast<int>(lim) < pl.second) { lim <<= 1; ++bucket; }
+      }
+      Key key{pl.first, wide[i] != 0, block, bucket};
       bool found = false;
       for (auto& b : buckets)
-        if (b.first.lds == lds && b.first.block == block && b.first.bucket == bucket) {
+        if (b.first.mode == key.mode && b.first.wide == key.wide && b.first.block == key.block &&
+            b.first.bucket == key.bucket) {
           b.second.push_back(i);
           found = true;
           break;
         }
-      if (!found) buckets.push_back({Key{lds, block, bucket}, std::vector<int32_t>{i}});
+      if (!found) buckets.push_back({key, std::vector<int32_t>{i}});
     }
     for (auto& b : buckets) {
       Group g;
       g.block = b.first.block;
-      g.lds = b.first.lds;
+      g.mode = b.first.mode;
+      g.wide = b.first.wide;
       int mx = 0;
-      for (int32_t i : b.second) {
-        const MolDesc& D = desc[i];
-        const size_t a = prec == 0 ? arena_bytes<double>(D.n, D.s, D.nslots) : arena_bytes<float>(D.n, D.s, D.nslots);
-        mx = std::max<int>(mx, static_cast<int>(a));
-      }
-      g.lds_bytes = g.lds ? mx : 0;
+      for (int32_t i : b.second) mx = std::max(mx, lds_of[i]);
+      g.lds_bytes = mx;
       g.first = static_cast<int32_t>(lists.size());
       g.count = static_cast<int32_t>(b.second.size());
       lists.insert(lists.end(), b.second.begin(), b.second.end());
       P->groups[prec].push_back(g);
     }
   }
-  for (int32_t i = 0; i < nm; ++i) {
-    if (desc[i].ws_off < 0) ++in_lds; else ++in_ws;
-  }
-
+  if (ix16.empty()) ix16.push_back(0);
+  if (ix32.empty()) ix32.push_back(0);
   std::vector<unsigned char> blob;
   const size_t o_desc = push_array(blob, desc);
+  const size_t o_ix16 = push_array(blob, ix16);
+  const size_t o_ix32 = push_array(blob, ix32);
+  const size_t o_coef = push_array(blob, coef);
+  const size_t o_ra = push_array(blob, ra);
+  const size_t o_rb = push_array(blob, rb);
+  const size_t o_cid = push_array(blob, cid);
+  const size_t o_d2 = push_array(blob, d2);
   const size_t o_atom = push_array(blob, atom_gid);
   const size_t o_incp = push_array(blob, inc_ptr);
   const size_t o_inc = push_array(blob, inc);
-  const size_t o_rows = push_array(blob, row_start);
-  const size_t o_nup = push_array(blob, row_nup);
-  const size_t o_ra = push_array(blob, ra);
-  const size_t o_rb = push_array(blob, rb);
-  const size_t o_d2 = push_array(blob, d2);
-  const size_t o_cid = push_array(blob, cid);
-  const size_t o_scol = push_array(blob, slot_col);
-  const size_t o_scoef = push_array(blob, slot_coef);
-  const size_t o_tasks = push_array(blob, tasks);
-  const size_t o_upd4 = push_array(blob, upd4);
-  const size_t o_updd = push_array(blob, updd);
-  const size_t o_lt = push_array(blob, lvl_task);
-  const size_t o_ln = push_array(blob, lvl_node);
-  const size_t o_nodes = push_array(blob, nodes);
   const size_t o_lists = push_array(blob, lists);
   blob.resize(blob.size() + 256);
 
@@ -604,23 +670,16 @@ ilves_status_t build_device_plan(ilves_plan* P) {
   P->buf_bytes = blob.size();
   unsigned char* b = static_cast<unsigned char*>(P->d_buf);
   P->dp.mol = reinterpret_cast<const MolDesc*>(b + o_desc);
+  P->dp.ix16 = reinterpret_cast<const uint16_t*>(b + o_ix16);
+  P->dp.ix32 = reinterpret_cast<const int32_t*>(b + o_ix32);
+  P->dp.coef = reinterpret_cast<const int32_t*>(b + o_coef);
+  P->dp.ra = reinterpret_cast<const int32_t*>(b + o_ra);
+  P->dp.rb = reinterpret_cast<const int32_t*>(b + o_rb);
+  P->dp.cid = reinterpret_cast<const int32_t*>(b + o_cid);
+  P->dp.d2 = reinterpret_cast<const double*>(b + o_d2);
   P->dp.atom_gid = reinterpret_cast<const int32_t*>(b + o_atom);
   P->dp.inc_ptr = reinterpret_cast<const int32_t*>(b + o_incp);
   P->dp.inc = reinterpret_cast<const int32_t*>(b + o_inc);
-  P->dp.row_start = reinterpret_cast<const int32_t*>(b + o_rows);
-  P->dp.row_nup = reinterpret_cast<const int32_t*>(b + o_nup);
-  P->dp.ra = reinterpret_cast<const int32_t*>(b + o_ra);
-  P->dp.rb = reinterpret_cast<const int32_t*>(b + o_rb);
-  P->dp.d2 = reinterpret_cast<const double*>(b + o_d2);
-  P->dp.cid = reinterpret_cast<const int32_t*>(b + o_cid);
-  P->dp.slot_col = reinterpret_cast<const int32_t*>(b + o_scol);
-  P->dp.slot_coef = reinterpret_cast<const int32_t*>(b + o_scoef);
-  P->dp.tasks = reinterpret_cast<const int4*>(b + o_tasks);
-  P->dp.upd4 = reinterpret_cast<const int4*>(b + o_upd4);
-  P->dp.updd = reinterpret_cast<const int32_t*>(b + o_updd);
-  P->dp.lvl_task = reinterpret_cast<const int32_t*>(b + o_lt);
-  P->dp.lvl_node = reinterpret_cast<const int32_t*>(b + o_ln);
-  P->dp.nodes = reinterpret_cast<const int32_t*>(b + o_nodes);
   P->d_lists = reinterpret_cast<int32_t*>(b + o_lists);
   if (ws > 0) {
     HIP_TRY(hipMalloc(&P->d_ws, ws));
@@ -631,7 +690,7 @@ ilves_status_t build_device_plan(ilves_plan* P) {
   P->stats[2] = natoms;
   P->stats[3] = nslots;
   P->stats[4] = fill;
-  P->stats[5] = nupd;
+  P->stats[5] = work;
   P->stats[6] = maxlev;
   P->stats[7] = sumlev;
   P->stats[8] = in_lds;
@@ -717,7 +776,7 @@ ilves_status_t ilves_plan_create(int32_t n_atoms, int32_t n_constraints, const i
   for (int prec = 0; prec < 2; ++prec)
     for (const Group& g : P->groups[prec])
       if (g.lds_bytes > 0)
-        HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(pick_kernel(prec == 1, g.lds, g.block)),
+        HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(pick_kernel(prec == 1, g.mode, g.wide, g.block)),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, g.lds_bytes));
   for (int i = 0; i < kStreams; ++i) {
     HIP_TRY(hipStreamCreateWithFlags(&P->streams[i], hipStreamNonBlocking));
@@ -809,7 +868,7 @@ ilves_status_t ilves_solve_ex(ilves_plan_t P, const double* r, const double* r_u
   for (int i = 0; i < ns; ++i) HIP_TRY(hipStreamWaitEvent(P->streams[i], P->ev_fork, 0));
   for (size_t gi = 0; gi < groups.size(); ++gi) {
     const Group& g = groups[gi];
-    KernelFn k = pick_kernel(precision == ILVES_PREC_MIXED, g.lds, g.block);
+    KernelFn k = pick_kernel(precision == ILVES_PREC_MIXED, g.mode, g.wide, g.block);
     hipStream_t s = P->streams[gi % ns];
     DevPlan dp = P->dp;
     const int32_t* list = P->d_lists + g.first;

@@ -19,6 +19,7 @@
 #include <functional>
 #include <numeric>
 #include <set>
+#include <stdexcept>
 #include <tuple>
 #include <unordered_set>
 
@@ -327,18 +328,7 @@ Symbolic symbolic(const std::vector<std::vector<int32_t>>& adj) {
   std::vector<double> work(S.n_levels, 0.0), bwork(S.n_levels, 0.0);
   for (int32_t j = 0; j < n; ++j) {
     double w = 1.0 + static_cast<double>(S.low[j].size());
-    for (int32_t m : S.up[j]) {
-      // |low(j) ∩ low(m)|, both sorted
-      const auto& a = S.low[j];
-      const auto& b = S.low[m];
-      size_t i = 0, k = 0, c = 0;
-      while (i < a.size() && k < b.size()) {
-        if (a[i] < b[k]) ++i;
-        else if (b[k] < a[i]) ++k;
-        else { ++c; ++i; ++k; }
-      }
-      w += 1.0 + 2.0 * static_cast<double>(c);
-    }
+    for (int32_t m : S.up[j]) w += 1.0 + static_cast<double>(S.low[j].size() + S.low[m].size());
     work[S.level[j]] += w;
     bwork[S.level[j]] += 1.0 + static_cast<double>(S.up[j].size());
   }
@@ -420,56 +410,110 @@ MolPlan plan_molecule(const std::vector<int32_t>& cons, const int32_t* pairs, co
       P.ordering = 2;
     }
   }
+  // Renumber rows by elimination level (stable within a level).  Any
+  // topological order of the elimination tree is an equivalent ordering:
+  // same filled pattern, same tree, same levels.
+  {
+    std::vector<int32_t> idx(n);
+    std::iota(idx.begin(), idx.end(), 0);
+    std::stable_sort(idx.begin(), idx.end(), [&](int32_t a, int32_t b) { return S.level[a] < S.level[b]; });
+    std::vector<int32_t> perm2(n);
+    for (int32_t p = 0; p < n; ++p) perm2[p] = perm[idx[p]];
+    const int64_t nnz_before = S.nnz_off;
+    const int32_t lev_before = S.n_levels;
+    perm = perm2;
+    S = symbolic(permute_graph(adj, perm));
+    if (S.nnz_off != nnz_before || S.n_levels != lev_before)
+      throw std::logic_error("level renumbering changed the filled pattern");
+    for (int32_t p = 1; p < n; ++p)
+      if (S.level[p] < S.level[p - 1]) throw std::logic_error("rows are not sorted by level");
+  }
   std::vector<int32_t> inv(n);
   for (int32_t p = 0; p < n; ++p) inv[perm[p]] = p;
   P.n_levels = S.n_levels;
   P.fill = S.nnz_off - n_edges;
 
-  // rows in elimination order
   P.cid.resize(n);
   P.ra.resize(n);
   P.rb.resize(n);
   P.d2.resize(n);
-  P.row_start.resize(n + 1);
-  P.row_nup.resize(n);
-  P.row_start[0] = 0;
   for (int32_t p = 0; p < n; ++p) {
-    int32_t c = perm[p];
+    const int32_t c = perm[p];
     P.cid[p] = cons[c];
     P.ra[p] = la[c];
     P.rb[p] = lb[c];
     P.d2[p] = d[cons[c]] * d[cons[c]];
-    P.row_nup[p] = static_cast<int32_t>(S.up[p].size());
-    P.row_start[p + 1] = P.row_start[p] + 1 + static_cast<int32_t>(S.up[p].size() + S.low[p].size());
   }
-  P.nslots = P.row_start[n];
-  auto slot = [&](int32_t k, int32_t j) -> int32_t {
-    if (j == k) return P.row_start[k];
-    if (j > k) return P.row_start[k] + 1 + find_sorted(S.up[k], j);
-    return P.row_start[k] + 1 + static_cast<int32_t>(S.up[k].size()) + find_sorted(S.low[k], j);
+  // slot regions
+  P.up_start.assign(n + 1, 0);
+  P.l_start.assign(n + 1, 0);
+  for (int32_t p = 0; p < n; ++p) P.up_start[p + 1] = P.up_start[p] + static_cast<int32_t>(S.up[p].size());
+  P.n_up = P.up_start[n];
+  P.l_start[0] = P.n_up;
+  for (int32_t p = 0; p < n; ++p) P.l_start[p + 1] = P.l_start[p] + static_cast<int32_t>(S.low[p].size());
+  P.n_l = P.l_start[n] - P.n_up;
+  auto up_slot = [&](int32_t j, int32_t m) { return P.up_start[j] + find_sorted(S.up[j], m); };   // m > j
+  auto l_slot = [&](int32_t k, int32_t i) { return P.l_start[k] + find_sorted(S.low[k], i); };   // i < k
+  auto coupling = [&](int32_t k, int32_t j) -> int32_t {
+    const int32_t ck = perm[k], cj = perm[j];
+    int32_t x = -1;
+    if (la[ck] == la[cj] || la[ck] == lb[cj]) x = la[ck];
+    else if (lb[ck] == la[cj] || lb[ck] == lb[cj]) x = lb[ck];
+    if (x < 0) return P.s << 1;  // fill: zero coupling (sentinel atom)
+    const int sk = (x == la[ck]) ? 1 : -1;
+    const int sj = (x == la[cj]) ? 1 : -1;
+    return (x << 1) | ((sk * sj) < 0 ? 1 : 0);
   };
-  P.slot_col.assign(P.nslots, 0);
-  P.slot_coef.assign(P.nslots, 0);
-  for (int32_t k = 0; k < n; ++k) {
-    P.slot_col[P.row_start[k]] = k;
-    auto fill_entry = [&](int32_t j) {
-      int32_t sl = slot(k, j);
-      P.slot_col[sl] = j;
-      int32_t ck = perm[k], cj = perm[j];
-      int32_t x = -1;
-      if (la[ck] == la[cj] || la[ck] == lb[cj]) x = la[ck];
-      else if (lb[ck] == la[cj] || lb[ck] == lb[cj]) x = lb[ck];
-      if (x < 0) {
-        P.slot_coef[sl] = P.s << 1;  // fill: zero coupling (sentinel atom)
-      } else {
-        int sk = (x == la[ck]) ? 1 : -1;
-        int sj = (x == la[cj]) ? 1 : -1;
-        P.slot_coef[sl] = (x << 1) | ((sk * sj) < 0 ? 1 : 0);
+  P.ucol.assign(P.n_up, 0);
+  P.utr.assign(P.n_up, 0);
+  P.ucoef.assign(P.n_up, 0);
+  P.ustart.assign(P.n_up + 1, 0);
+  P.lcol.assign(P.n_l, 0);
+  P.ltr.assign(P.n_l, 0);
+  P.lcoef.assign(P.n_l, 0);
+  for (int32_t j = 0; j < n; ++j) {
+    for (size_t t = 0; t < S.up[j].size(); ++t) {
+      const int32_t m = S.up[j][t];
+      const int32_t q = P.up_start[j] + static_cast<int32_t>(t);
+      P.ucol[q] = m;
+      P.utr[q] = l_slot(m, j);
+      P.ucoef[q] = coupling(j, m);
+      // rows i < j coupled to both j and m: low(j) intersect low(m)
+      const auto& A = S.low[j];
+      const auto& B = S.low[m];
+      size_t ia = 0, ib = 0;
+      while (ia < A.size() && ib < B.size()) {
+        if (A[ia] < B[ib]) ++ia;
+        else if (B[ib] < A[ia]) ++ib;
+        else {
+          P.upd_a.push_back(l_slot(j, A[ia]));
+          P.upd_b.push_back(l_slot(m, B[ib]));
+          ++ia;
+          ++ib;
+        }
       }
-    };
-    for (int32_t j : S.up[k]) fill_entry(j);
-    for (int32_t j : S.low[k]) fill_entry(j);
+      P.ustart[q + 1] = static_cast<int32_t>(P.upd_a.size());
+    }
+    for (size_t t = 0; t < S.low[j].size(); ++t) {
+      const int32_t i = S.low[j][t];
+      const int32_t q = P.l_start[j] + static_cast<int32_t>(t) - P.n_up;
+      P.lcol[q] = i;
+      P.ltr[q] = up_slot(i, j);
+      P.lcoef[q] = coupling(j, i);
+    }
   }
+  P.n_upd = static_cast<int32_t>(P.upd_a.size());
+  P.lvl_row.assign(S.n_levels + 1, n);
+  P.lvl_row[0] = 0;
+  for (int32_t p = n - 1; p >= 0; --p) P.lvl_row[S.level[p]] = p;
+  P.pl_start.assign(S.n_levels + 1, 0);
+  for (int32_t h = 0; h < S.n_levels; ++h) {
+    for (int32_t q = P.up_start[P.lvl_row[h]]; q < P.up_start[P.lvl_row[h + 1]]; ++q)
+      if (P.ustart[q + 1] > P.ustart[q]) P.plist.push_back(q);
+    P.pl_start[h + 1] = static_cast<int32_t>(P.plist.size());
+  }
+  for (int32_t p = 0; p < n; ++p)
+    if ((S.level[p] == 0) != S.low[p].empty()) throw std::logic_error("level 0 must be the rows without lower entries");
   // incidence in elimination order
   P.inc_ptr.assign(P.s + 1, 0);
   for (int32_t x = 0; x < P.s; ++x) P.inc_ptr[x + 1] = P.inc_ptr[x] + static_cast<int32_t>(inc[x].size());
@@ -479,70 +523,9 @@ MolPlan plan_molecule(const std::vector<int32_t>& cons, const int32_t* pairs, co
     for (int32_t c : inc[x]) rows.push_back(inv[c]);
     std::sort(rows.begin(), rows.end());
     for (size_t t = 0; t < rows.size(); ++t) {
-      int32_t p = rows[t];
+      const int32_t p = rows[t];
       P.inc[P.inc_ptr[x] + t] = (p << 1) | (P.rb[p] == x ? 1 : 0);
     }
-  }
-  // tasks level by level
-  std::vector<std::vector<int32_t>> by_level(S.n_levels);
-  for (int32_t j = 0; j < n; ++j) by_level[S.level[j]].push_back(j);
-  P.lvl_task.assign(S.n_levels + 1, 0);
-  P.lvl_node.assign(S.n_levels + 1, 0);
-  for (int32_t h = 0; h < S.n_levels; ++h) {
-    struct Pending { Task t; std::vector<Update> u; };
-    std::vector<Pending> pend;
-    for (int32_t j : by_level[h]) {
-      Pending dg;
-      dg.t.out0 = P.row_start[j];
-      dg.t.out1 = -(j + 1);
-      for (int32_t i : S.low[j]) {
-        Update u{};
-        u.a = slot(j, i);
-        u.b = slot(i, j);
-        u.c = i;
-        u.e = 0;
-        u.d = P.row_start[i];
-        dg.u.push_back(u);
-      }
-      pend.push_back(std::move(dg));
-      for (int32_t m : S.up[j]) {
-        Pending pr;
-        pr.t.out0 = slot(j, m);
-        pr.t.out1 = slot(m, j);
-        const auto& A = S.low[j];
-        const auto& B = S.low[m];
-        size_t ia = 0, ib = 0;
-        while (ia < A.size() && ib < B.size()) {
-          if (A[ia] < B[ib]) ++ia;
-          else if (B[ib] < A[ia]) ++ib;
-          else {
-            int32_t i = A[ia];
-            Update u{};
-            u.a = slot(j, i);
-            u.b = slot(i, m);
-            u.c = slot(m, i);
-            u.e = slot(i, j);
-            u.d = P.row_start[i];
-            pr.u.push_back(u);
-            ++ia;
-            ++ib;
-          }
-        }
-        pend.push_back(std::move(pr));
-      }
-    }
-    // longest tasks first so that the lanes finish together
-    std::stable_sort(pend.begin(), pend.end(),
-                     [](const Pending& x, const Pending& y) { return x.u.size() > y.u.size(); });
-    for (auto& pd : pend) {
-      pd.t.u0 = static_cast<int32_t>(P.upd.size());
-      P.upd.insert(P.upd.end(), pd.u.begin(), pd.u.end());
-      pd.t.u1 = static_cast<int32_t>(P.upd.size());
-      P.tasks.push_back(pd.t);
-    }
-    P.lvl_task[h + 1] = static_cast<int32_t>(P.tasks.size());
-    for (int32_t j : by_level[h]) P.nodes.push_back(j);
-    P.lvl_node[h + 1] = static_cast<int32_t>(P.nodes.size());
   }
   return P;
 }

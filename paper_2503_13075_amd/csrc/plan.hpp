@@ -8,41 +8,43 @@
 
 namespace ilves {
 
-// One factorisation task.  Diagonal task: out0 = diagonal slot of row j,
-// out1 = -(j + 1).  Pair task for (j, m), m > j: out0 = slot of U_jm in row
-// j, out1 = slot of W_mj in row m.  Updates are [u0, u1).
-struct Task {
-  int32_t out0, out1, u0, u1;
-};
-
-// Update of a diagonal task: acc -= W[s_wji] * D[s_dii] * U[s_uij], and the
-// forward solve y_j -= W[s_wji] * D[s_dii] * y[i].
-// Update of a pair task: U_jm -= W[a] * D[d] * U[b];  W_mj -= W[c] * D[d] * U[e].
-struct Update {
-  int32_t a, b, c, e;   // diag: a = slot(j,i), b = slot(i,j), c = i, e unused
-  int32_t d;            // diagonal slot of row i (holds 1/U_ii once factored)
-};
-
-// Plan of one molecule (all indices local to it; rows in elimination order).
+// Plan of one molecule.  Rows (constraints) are numbered in elimination
+// order, grouped by elimination level: level h holds rows
+// [lvl_row[h], lvl_row[h+1]).  The diagonal of row j has its own entry
+// (index j of the diagonal array); every off-diagonal entry of the filled
+// LU pattern has one "slot" (an index into the value array F):
+//   * upper slots [0, n_up): row j owns [up_start[j], up_start[j+1]) =
+//     its entries (j, m), m > j, ascending in m;
+//   * lower slots [n_up, n_up + n_l): row k owns [l_start[k], l_start[k+1])
+//     = its entries (k, i), i < k, ascending in i.
+// utr / ltr link an entry to its transpose.  The factor update of an upper
+// entry (j, m) and of its transpose (m, j) runs over the rows i < j that
+// are coupled to both j and m; the pairs (slot (j, i), slot (m, i)) of
+// those rows are listed in upd_a / upd_b over [ustart[q], ustart[q+1]) for
+// upper slot q.  Level h's upper slots that have at least one update are
+// listed in plist[pl_start[h] .. pl_start[h+1]); the others keep their
+// matrix value.  Level 0 holds exactly the rows without lower entries, whose
+// factorisation is just 1/A_jj.  *coef hold
+// the coupling of an original entry: (shared atom << 1) | (sign < 0), or
+// (s << 1) for a fill entry.
 struct MolPlan {
-  int32_t n = 0, s = 0, n_levels = 0, nslots = 0;
+  int32_t n = 0, s = 0, n_levels = 0, n_up = 0, n_l = 0, n_upd = 0;
   std::vector<int32_t> cid;        // row -> input constraint index
   std::vector<int32_t> atom_gid;   // local atom -> input atom index
   std::vector<int32_t> ra, rb;     // row -> local atoms a_k, b_k
   std::vector<double> d2;          // row -> d_k^2
-  std::vector<int32_t> row_start;  // n + 1; row k = [diag][upper (cols > k)][lower (cols < k)]
-  std::vector<int32_t> row_nup;    // number of upper entries of row k
-  std::vector<int32_t> slot_col;   // slot -> column (row index)
-  std::vector<int32_t> slot_coef;  // slot -> (shared atom << 1) | (sign < 0); fill: (s << 1)
+  std::vector<int32_t> up_start, l_start;            // n + 1 each
+  std::vector<int32_t> ucol, utr, ucoef;             // n_up each
+  std::vector<int32_t> ustart;                       // n_up + 1
+  std::vector<int32_t> lcol, ltr, lcoef;             // n_l each
+  std::vector<int32_t> upd_a, upd_b;                 // n_upd each
+  std::vector<int32_t> lvl_row;    // n_levels + 1
+  std::vector<int32_t> pl_start;   // n_levels + 1
+  std::vector<int32_t> plist;      // upper slots with updates, level by level
   std::vector<int32_t> inc_ptr;    // s + 1
   std::vector<int32_t> inc;        // (row << 1) | (atom is b_k)
-  std::vector<int32_t> lvl_task;   // n_levels + 1 pointers into tasks
-  std::vector<Task> tasks;
-  std::vector<Update> upd;
-  std::vector<int32_t> lvl_node;   // n_levels + 1 pointers into nodes
-  std::vector<int32_t> nodes;      // rows sorted by level
   int64_t fill = 0;
-  int ordering = 0;                // 1 minimum degree, 2 nested dissection
+  int ordering = 0;                // 1 minimum fill, 2 nested dissection
 };
 
 struct PlanOptions {
