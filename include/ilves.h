@@ -70,7 +70,8 @@ typedef struct {
   int32_t max_iter;      /* iteration cap; <= 0 selects 20 (Newton FP64) or 40   */
   int32_t warm_start;    /* ILVES_WARM_ZERO: lambda_0 = 0; ILVES_WARM_CALLER:
                             lambda_0 read from the lambda argument;
-                            ILVES_WARM_MLP: lambda_0 from the loaded network     */
+                            ILVES_WARM_MLP: lambda_0 from the loaded network
+                            (see ilves_solve_learned)                           */
   int32_t block_threads; /* threads per workgroup for large molecules; 0 = auto  */
   int32_t lds_limit;     /* bytes of LDS a molecule may use; 0 = auto            */
   int32_t ordering;      /* 0 auto, 1 minimum degree, 2 nested dissection        */
@@ -150,6 +151,71 @@ ilves_status_t ilves_solve_ex(ilves_plan_t plan, const double* r, const double* 
                               double tol, int32_t precision, int32_t variant, int32_t warm_start,
                               int32_t max_iter, double* r_out, double* lambda, int32_t* iters,
                               int32_t* status, void* hip_stream);
+
+/*
+ * Learned warm start.  A small network predicts lambda_0 for the Newton
+ * iteration (whose own start is lambda_0 = 0, Supplement section 2.3) from
+ * 16 per-constraint features of the local geometry (see
+ * ilves_features).  With w_k = 1/m_a + 1/m_b and t0_k the decoupled
+ * (diatomic) solution of constraint k,
+ *   lambda_0,k = (t0_k + scale * MLP((f_k - mean) / std)) / w_k,
+ * MLP = [16 -> 64 -> 64 -> 1] with exact GELU, evaluated in BF16 on the
+ * matrix cores with FP32 accumulation.  Parameters are a flat float array
+ * of ilves_mlp_param_count() values: W1 [16][64] row-major (input x hidden),
+ * b1 [64], W2 [64][64], b2 [64], W3 [64], b3 [1]; the normalisation block
+ * has ilves_mlp_norm_count() values: mean [16], std [16] (> 0), scale.
+ */
+int32_t ilves_mlp_param_count(void);
+int32_t ilves_mlp_norm_count(void);
+
+/* Copies network parameters and normalisation (host float arrays) into the
+ * plan and reserves the plan's feature buffers (4 * 17 bytes per
+ * constraint).  Errors: ILVES_ERR_ARG, ILVES_ERR_HIP. */
+ilves_status_t ilves_mlp_load(ilves_plan_t plan, const float* params, const float* norm);
+
+/* Features of every constraint, in plan row order (ilves_plan_row_constraints
+ * maps rows to input constraints): feat device float [n_constraints][16],
+ * w device float [n_constraints].  Asynchronous on hip_stream. */
+ilves_status_t ilves_features(ilves_plan_t plan, const double* r, const double* r_u, const double* mass,
+                              float* feat, float* w, void* hip_stream);
+
+/* Host int32 [n_constraints]: input constraint index of each plan row. */
+ilves_status_t ilves_plan_row_constraints(ilves_plan_t plan, int32_t* cid);
+
+/* The network's lambda_0 (device double [n_constraints], input order).
+ * Errors: ILVES_ERR_UNSUPPORTED if no network was loaded. */
+ilves_status_t ilves_mlp_predict(ilves_plan_t plan, const double* r, const double* r_u, const double* mass,
+                                 double* lambda, void* hip_stream);
+
+/* Solve started from the network's lambda_0, with a per-molecule fallback to
+ * lambda_0 = 0 when the prediction's maximum relative violation is not below
+ * that of lambda = 0 (or not finite), or when the violation rises in two
+ * consecutive iterations.  fallback: device int32 [num_molecules] set to 1
+ * where the fallback was taken (may be NULL).  Other arguments as
+ * ilves_solve_ex.  Errors as ilves_solve_ex, plus ILVES_ERR_UNSUPPORTED
+ * without a loaded network. */
+ilves_status_t ilves_solve_learned(ilves_plan_t plan, const double* r, const double* r_u, const double* mass,
+                                   double tol, int32_t precision, int32_t variant, int32_t max_iter,
+                                   double* r_out, double* lambda, int32_t* iters, int32_t* status,
+                                   int32_t* fallback, void* hip_stream);
+
+/* Training kernels (FP32, device arrays, asynchronous on hip_stream).
+ * Forward pass of normalised inputs x [n][16] -> out [n]. */
+ilves_status_t ilves_mlp_forward_f32(const float* params, const float* x, int32_t n, float* out,
+                                     void* hip_stream);
+
+/* Floats of workspace ilves_mlp_grad_f32 needs for n samples. */
+int64_t ilves_mlp_grad_workspace(int32_t n);
+
+/* Gradient of L = 1/(2n) sum_s (out_s - y_s)^2 with respect to the
+ * parameters: grad [param_count], loss [1], work [ilves_mlp_grad_workspace(n)].
+ * Partial sums are combined in a fixed order (deterministic). */
+ilves_status_t ilves_mlp_grad_f32(const float* params, const float* x, const float* y, int32_t n, float* grad,
+                                  float* loss, float* work, int64_t work_floats, void* hip_stream);
+
+/* One Adam step (Kingma and Ba) on n parameters, step counting from 1. */
+ilves_status_t ilves_mlp_adam_f32(float* params, const float* grad, float* m, float* v, int32_t n, float lr,
+                                  float beta1, float beta2, float eps, int32_t step, void* hip_stream);
 
 /*
  * Planner diagnostics (host only, no GPU needed; not a solve path -- the

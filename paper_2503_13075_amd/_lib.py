@@ -42,6 +42,7 @@ _P = ctypes.c_void_p
 _I32P = ctypes.POINTER(ctypes.c_int32)
 _I64P = ctypes.POINTER(ctypes.c_int64)
 _F64P = ctypes.POINTER(ctypes.c_double)
+_F32P = ctypes.POINTER(ctypes.c_float)
 
 
 def header_functions() -> list:
@@ -88,6 +89,28 @@ def lib() -> ctypes.CDLL:
                                          _F64P, _F64P, _F64P, ctypes.c_double, ctypes.c_int32, ctypes.c_int32,
                                          ctypes.c_int32, _F64P, _F64P, _I32P, _I32P, _I32P, _I64P]
     L.ilves_plan_replay_host.restype = ctypes.c_int
+    L.ilves_mlp_param_count.restype = ctypes.c_int32
+    L.ilves_mlp_norm_count.restype = ctypes.c_int32
+    L.ilves_mlp_load.argtypes = [_P, _F32P, _F32P]
+    L.ilves_mlp_load.restype = ctypes.c_int
+    L.ilves_features.argtypes = [_P, _P, _P, _P, _P, _P, _P]
+    L.ilves_features.restype = ctypes.c_int
+    L.ilves_plan_row_constraints.argtypes = [_P, _I32P]
+    L.ilves_plan_row_constraints.restype = ctypes.c_int
+    L.ilves_mlp_predict.argtypes = [_P, _P, _P, _P, _P, _P]
+    L.ilves_mlp_predict.restype = ctypes.c_int
+    L.ilves_solve_learned.argtypes = [_P, _P, _P, _P, ctypes.c_double, ctypes.c_int32, ctypes.c_int32,
+                                      ctypes.c_int32, _P, _P, _P, _P, _P, _P]
+    L.ilves_solve_learned.restype = ctypes.c_int
+    L.ilves_mlp_forward_f32.argtypes = [_P, _P, ctypes.c_int32, _P, _P]
+    L.ilves_mlp_forward_f32.restype = ctypes.c_int
+    L.ilves_mlp_grad_workspace.argtypes = [ctypes.c_int32]
+    L.ilves_mlp_grad_workspace.restype = ctypes.c_int64
+    L.ilves_mlp_grad_f32.argtypes = [_P, _P, _P, ctypes.c_int32, _P, _P, _P, ctypes.c_int64, _P]
+    L.ilves_mlp_grad_f32.restype = ctypes.c_int
+    L.ilves_mlp_adam_f32.argtypes = [_P, _P, _P, _P, ctypes.c_int32, ctypes.c_float, ctypes.c_float,
+                                     ctypes.c_float, ctypes.c_float, ctypes.c_int32, _P]
+    L.ilves_mlp_adam_f32.restype = ctypes.c_int
     _lib = L
     return L
 
@@ -206,3 +229,103 @@ class Plan:
         check(self._L.ilves_solve_ex(self._h, r.data_ptr(), r_u.data_ptr(), mass.data_ptr(), float(tol), precision,
                                      variant, warm_start, max_iter, r_out.data_ptr(), lam.data_ptr(),
                                      iters.data_ptr(), status.data_ptr(), ctypes.c_void_p(stream.cuda_stream)))
+
+
+def _stream(stream):
+    import torch
+    return ctypes.c_void_p((stream or torch.cuda.current_stream()).cuda_stream)
+
+
+def _dev(t, dtype, shape=None):
+    import torch
+    if not t.is_cuda or t.dtype != dtype or not t.is_contiguous():
+        raise ValueError("expected a contiguous device tensor of dtype %s" % dtype)
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"expected shape {shape}, got {tuple(t.shape)}")
+    return t.data_ptr()
+
+
+def mlp_param_count() -> int:
+    return int(lib().ilves_mlp_param_count())
+
+
+def mlp_norm_count() -> int:
+    return int(lib().ilves_mlp_norm_count())
+
+
+def mlp_forward_f32(params, x, out, stream=None):
+    """FP32 forward pass of normalised inputs x [n, 16] (device tensors)."""
+    import torch
+    n = x.shape[0]
+    check(lib().ilves_mlp_forward_f32(_dev(params, torch.float32), _dev(x, torch.float32, (n, 16)), n,
+                                      _dev(out, torch.float32, (n,)), _stream(stream)))
+
+
+def mlp_grad_f32(params, x, y, grad, loss, work, stream=None):
+    """Gradient of 1/(2n) sum (out - y)^2 (device tensors)."""
+    import torch
+    n = x.shape[0]
+    check(lib().ilves_mlp_grad_f32(_dev(params, torch.float32), _dev(x, torch.float32, (n, 16)),
+                                   _dev(y, torch.float32, (n,)), n, _dev(grad, torch.float32),
+                                   _dev(loss, torch.float32), _dev(work, torch.float32), work.numel(),
+                                   _stream(stream)))
+
+
+def mlp_grad_workspace(n) -> int:
+    return int(lib().ilves_mlp_grad_workspace(int(n)))
+
+
+def mlp_adam(params, grad, m, v, lr, step, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    import torch
+    check(lib().ilves_mlp_adam_f32(_dev(params, torch.float32), _dev(grad, torch.float32), _dev(m, torch.float32),
+                                   _dev(v, torch.float32), params.numel(), lr, beta1, beta2, eps, int(step),
+                                   _stream(stream)))
+
+
+def _plan_load_mlp(self, params, norm):
+    """Loads network parameters and normalisation (host float arrays)."""
+    params = np.ascontiguousarray(params, dtype=np.float32)
+    norm = np.ascontiguousarray(norm, dtype=np.float32)
+    if params.size != mlp_param_count() or norm.size != mlp_norm_count():
+        raise ValueError("wrong parameter or normalisation size")
+    check(self._L.ilves_mlp_load(self._h, _ptr(params, ctypes.c_float), _ptr(norm, ctypes.c_float)))
+
+
+def _plan_row_constraints(self):
+    out = np.zeros(max(1, self.n_constraints), np.int32)
+    check(self._L.ilves_plan_row_constraints(self._h, _ptr(out, ctypes.c_int32)))
+    return out[:self.n_constraints]
+
+
+def _plan_features(self, r, r_u, mass, feat, w, stream=None):
+    import torch
+    check(self._L.ilves_features(self._h, _dev(r, torch.float64, (3, self.n_atoms)),
+                                 _dev(r_u, torch.float64, (3, self.n_atoms)), _dev(mass, torch.float64),
+                                 _dev(feat, torch.float32, (self.n_constraints, 16)),
+                                 _dev(w, torch.float32, (self.n_constraints,)), _stream(stream)))
+
+
+def _plan_predict(self, r, r_u, mass, lam, stream=None):
+    import torch
+    check(self._L.ilves_mlp_predict(self._h, _dev(r, torch.float64, (3, self.n_atoms)),
+                                    _dev(r_u, torch.float64, (3, self.n_atoms)), _dev(mass, torch.float64),
+                                    _dev(lam, torch.float64, (self.n_constraints,)), _stream(stream)))
+
+
+def _plan_solve_learned(self, r, r_u, mass, tol, r_out, lam, iters, status, fallback=None, precision=PREC_MIXED,
+                        variant=VARIANT_NEWTON, max_iter=0, stream=None):
+    import torch
+    fb = 0 if fallback is None else _dev(fallback, torch.int32)
+    check(self._L.ilves_solve_learned(self._h, _dev(r, torch.float64, (3, self.n_atoms)),
+                                      _dev(r_u, torch.float64, (3, self.n_atoms)), _dev(mass, torch.float64),
+                                      float(tol), precision, variant, max_iter,
+                                      _dev(r_out, torch.float64, (3, self.n_atoms)),
+                                      _dev(lam, torch.float64, (self.n_constraints,)), _dev(iters, torch.int32),
+                                      _dev(status, torch.int32), fb, _stream(stream)))
+
+
+Plan.load_mlp = _plan_load_mlp
+Plan.row_constraints = _plan_row_constraints
+Plan.features = _plan_features
+Plan.predict = _plan_predict
+Plan.solve_learned = _plan_solve_learned

@@ -46,7 +46,11 @@
 #include <vector>
 
 #include "../../include/ilves.h"
+#include "device_plan.hpp"
 #include "plan.hpp"
+#include "warmstart.hpp"
+
+using namespace ilves_dev;
 
 namespace {
 
@@ -65,49 +69,7 @@ ilves_status_t fail(ilves_status_t s, const std::string& msg) {
   } while (0)
 
 // ---------------------------------------------------------------------------
-// device plan layout
-
-// Placement of a molecule's per-level data:
-//   ALL_LDS:    slot structure and factor values in LDS
-//   STRUCT_LDS: slot structure in LDS, factor values in the workspace
-//   GLOBAL:     both read from global memory (molecules too large for LDS)
-enum { ALL_LDS = 0, STRUCT_LDS = 1, GLOBAL = 2 };
-
-struct MolDesc {
-  int32_t n, s, n_up, n_l, n_upd, n_levels, n_pl;
-  int32_t wide;       // 0: 16-bit structure indices, 1: 32-bit
-  int32_t ix_off;     // structure block in the index pool of its width
-  int32_t coef_off;   // ucoef then lcoef
-  int32_t row_off;    // ra, rb, cid, d2
-  int32_t atom_off;   // atom_gid
-  int32_t incp_off;   // inc_ptr, s + 1 entries
-  int32_t inc_off;    // inc
-  int64_t ws_off;     // byte offset of the molecule's workspace
-};
-
-// Structure block of one molecule, in this order:
-//   up_start[n+1] l_start[n+1] lvl_row[H+1] pl_start[H+1] ustart[n_up+1]
-//   ucol[n_up] utr[n_up] lcol[n_l] ltr[n_l] upd_a[n_upd] upd_b[n_upd]
-//   plist[n_pl]
-__host__ __device__ inline int64_t struct_elems(int32_t n, int32_t H, int32_t n_up, int32_t n_l, int32_t n_upd,
-                                                int32_t n_pl) {
-  return 2 * (static_cast<int64_t>(n) + 1) + 2 * (static_cast<int64_t>(H) + 1) + 3 * static_cast<int64_t>(n_up) + 1 +
-         2 * static_cast<int64_t>(n_l) + 2 * static_cast<int64_t>(n_upd) + n_pl;
-}
-
-struct DevPlan {
-  const MolDesc* mol;
-  const uint16_t* ix16;
-  const int32_t* ix32;
-  const int32_t* coef;
-  const int32_t* ra;
-  const int32_t* rb;
-  const int32_t* cid;
-  const double* d2;
-  const int32_t* atom_gid;
-  const int32_t* inc_ptr;
-  const int32_t* inc;
-};
+// device plan layout: see device_plan.hpp
 
 struct SolveArgs {
   const double* r;
@@ -117,15 +79,14 @@ struct SolveArgs {
   double* lambda;
   int32_t* iters;
   int32_t* status;
+  int32_t* fallback;  // per molecule (learned warm start), may be null
   unsigned char* ws;
   double tol;
   int32_t n_atoms;
   int32_t max_iter;
-  int32_t warm;      // 0: lambda_0 = 0, 1: read lambda
+  int32_t warm;      // 0: lambda_0 = 0, 1: read lambda, 2: read the network's lambda (with fallback)
   int32_t chord;     // 0: Newton, 1: chord
 };
-
-__host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~static_cast<size_t>(15); }
 
 // FP64 workspace of a molecule: e, u (3n each), lambda, C_kk (n each), the
 // couplings of every off-diagonal slot, 1/m (s + 1)
@@ -150,6 +111,7 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(const DevPlan P, const int
                                                       const SolveArgs A) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ double red[BLOCK / 64];
+  __shared__ double red0[BLOCK / 64];
   __shared__ int32_t singular;
 
   const int tid = threadIdx.x;
@@ -230,19 +192,28 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(const DevPlan P, const int
     invm[s] = 0.0;  // fill entries point here: zero coupling
     singular = 0;
   }
+  double v0 = 0.0;  // max relative violation at lambda = 0 (learned start fallback test)
   for (int32_t k = tid; k < n; k += BLOCK) {
     const int32_t ga = atom_gid[ra[k]], gb = atom_gid[rb[k]];
     ex[k] = rx[ga] - rx[gb];
     ey[k] = rx[S + ga] - rx[S + gb];
     ez[k] = rx[2 * S + ga] - rx[2 * S + gb];
-    u_x[k] = ux[ga] - ux[gb];
-    u_y[k] = ux[S + ga] - ux[S + gb];
-    u_z[k] = ux[2 * S + ga] - ux[2 * S + gb];
+    const double a0 = ux[ga] - ux[gb], a1 = ux[S + ga] - ux[S + gb], a2 = ux[2 * S + ga] - ux[2 * S + gb];
+    u_x[k] = a0;
+    u_y[k] = a1;
+    u_z[k] = a2;
+    v0 = fmax(v0, fabs(a0 * a0 + a1 * a1 + a2 * a2 - d2[k]) / (2.0 * d2[k]));
     lam[k] = A.warm ? A.lambda[cid[k]] : 0.0;
   }
 #pragma unroll
-  for (int off = 32; off > 0; off >>= 1) rmax = fmax(rmax, __shfl_xor(rmax, off, 64));
-  if ((tid & 63) == 0) red[tid >> 6] = rmax;
+  for (int off = 32; off > 0; off >>= 1) {
+    rmax = fmax(rmax, __shfl_xor(rmax, off, 64));
+    v0 = fmax(v0, __shfl_xor(v0, off, 64));
+  }
+  if ((tid & 63) == 0) {
+    red[tid >> 6] = rmax;
+    red0[tid >> 6] = v0;
+  }
   __syncthreads();
   for (int32_t k = tid; k < n; k += BLOCK) cd[k] = invm[ra[k]] + invm[rb[k]];
   for (int32_t q = tid; q < n_up + n_l; q += BLOCK) {
@@ -255,9 +226,12 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(const DevPlan P, const int
   // from the one iterated here by at most delta = sqrt(3) rmax 2^-52.  The
   // convergence test adds the resulting bound on |g| so that the returned
   // positions themselves satisfy the tolerance.
-  double gr = red[0];
+  double gr = red[0], rel_zero = red0[0];
 #pragma unroll
-  for (int w = 1; w < BLOCK / 64; ++w) gr = fmax(gr, red[w]);
+  for (int w = 1; w < BLOCK / 64; ++w) {
+    gr = fmax(gr, red[w]);
+    rel_zero = fmax(rel_zero, red0[w]);
+  }
   const double delta = 1.7320508075688772 * gr * 0x1.0p-52;
   const double delta2 = 0.5 * delta * delta;
   __syncthreads();
@@ -334,6 +308,8 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(const DevPlan P, const int
 
   int32_t it = 0;
   int32_t st_code = ILVES_ERR_NOT_CONVERGED;
+  int32_t fell_back = 0, rises = 0;
+  double prev_gmax = INFINITY;
   const bool chord_singular = A.chord && singular;
   if (chord_singular) st_code = ILVES_ERR_SINGULAR;
   while (!chord_singular) {
@@ -374,6 +350,19 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(const DevPlan P, const int
     double gmax = red[0];
 #pragma unroll
     for (int w = 1; w < BLOCK / 64; ++w) gmax = fmax(gmax, red[w]);
+    if (A.warm == 2 && !fell_back) {
+      // learned start: keep it only while it beats lambda = 0 and the
+      // residual does not rise twice in a row; otherwise restart from 0
+      rises = (it > 0 && gmax > prev_gmax) ? rises + 1 : 0;
+      if ((it == 0 && !(gmax < rel_zero)) || rises >= 2) {
+        fell_back = 1;
+        prev_gmax = INFINITY;
+        for (int32_t k = tid; k < n; k += BLOCK) lam[k] = 0.0;
+        __syncthreads();
+        continue;
+      }
+      prev_gmax = gmax;
+    }
     if (gmax == INFINITY) { st_code = ILVES_ERR_NONFINITE; break; }
     if (gmax <= A.tol) { st_code = ILVES_OK; break; }
     if (it >= A.max_iter) { st_code = ILVES_ERR_NOT_CONVERGED; break; }
@@ -423,6 +412,7 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(const DevPlan P, const int
   if (tid == 0) {
     A.iters[m_idx] = it;
     A.status[m_idx] = st_code;
+    if (A.fallback) A.fallback[m_idx] = fell_back;
   }
 }
 
@@ -493,6 +483,11 @@ struct ilves_plan {
   int32_t n_free = 0;
   int32_t* d_lists = nullptr;          // molecule lists of every group, both precisions
   std::vector<Group> groups[2];        // [0] FP64, [1] mixed
+  int32_t width_first[2] = {0, 0};     // molecule lists by index width (features kernel)
+  int32_t width_count[2] = {0, 0};
+  float* d_mlp = nullptr;              // network parameters then normalisation block
+  float* d_feat = nullptr;             // [n_constraints][16] features (plan row order)
+  float* d_w = nullptr;                // [n_constraints] 1/m_a + 1/m_b
   hipStream_t streams[kStreams] = {};
   hipEvent_t ev_fork = nullptr;
   hipEvent_t ev_join[kStreams] = {};
@@ -648,6 +643,12 @@ ilves_status_t build_device_plan(ilves_plan* P) {
       P->groups[prec].push_back(g);
     }
   }
+  for (int wdt = 0; wdt < 2; ++wdt) {
+    P->width_first[wdt] = static_cast<int32_t>(lists.size());
+    for (int32_t i : ord)
+      if (wide[i] == wdt) lists.push_back(i);
+    P->width_count[wdt] = static_cast<int32_t>(lists.size()) - P->width_first[wdt];
+  }
   if (ix16.empty()) ix16.push_back(0);
   if (ix32.empty()) ix32.push_back(0);
   std::vector<unsigned char> blob;
@@ -797,6 +798,9 @@ ilves_status_t ilves_plan_destroy(ilves_plan_t P) {
   if (P->d_buf) (void)hipFree(P->d_buf);
   if (P->d_ws) (void)hipFree(P->d_ws);
   if (P->d_free) (void)hipFree(P->d_free);
+  if (P->d_mlp) (void)hipFree(P->d_mlp);
+  if (P->d_feat) (void)hipFree(P->d_feat);
+  if (P->d_w) (void)hipFree(P->d_w);
   delete P;
   return ILVES_OK;
 }
@@ -822,22 +826,40 @@ ilves_status_t ilves_plan_molecules(ilves_plan_t P, int32_t* n_con, int32_t* n_a
   return ILVES_OK;
 }
 
-ilves_status_t ilves_solve_ex(ilves_plan_t P, const double* r, const double* r_u, const double* mass, double tol,
-                              int32_t precision, int32_t variant, int32_t warm_start, int32_t max_iter,
-                              double* r_out, double* lambda, int32_t* iters, int32_t* status, void* hip_stream) {
+}  // extern "C"
+
+namespace {
+
+ilves_status_t check_solve_args(ilves_plan_t P, const double* r, const double* r_u, const double* mass, double tol,
+                                int32_t precision, int32_t variant, double* r_out, double* lambda, int32_t* iters,
+                                int32_t* status) {
   if (!P) return fail(ILVES_ERR_ARG, "plan must not be NULL");
   if (!r || !r_u || !mass || !r_out) return fail(ILVES_ERR_ARG, "position and mass pointers must not be NULL");
   if (P->n_con > 0 && (!lambda || !iters || !status)) return fail(ILVES_ERR_ARG, "lambda/iters/status must not be NULL");
   if (!(tol >= 0.0)) return fail(ILVES_ERR_ARG, "tol must be >= 0");
   if (precision != ILVES_PREC_FP64 && precision != ILVES_PREC_MIXED) return fail(ILVES_ERR_ARG, "bad precision");
   if (variant != ILVES_VARIANT_NEWTON && variant != ILVES_VARIANT_CHORD) return fail(ILVES_ERR_ARG, "bad variant");
-  if (warm_start == ILVES_WARM_MLP) return fail(ILVES_ERR_UNSUPPORTED, "no network loaded for the learned warm start");
-  if (warm_start != ILVES_WARM_ZERO && warm_start != ILVES_WARM_CALLER) return fail(ILVES_ERR_ARG, "bad warm_start");
   if (r_out == r || r_out == r_u) return fail(ILVES_ERR_ARG, "r_out must not alias r or r_u");
   int dev = 0;
   HIP_TRY(hipGetDevice(&dev));
   if (dev != P->device) return fail(ILVES_ERR_ARG, "plan was created on another device");
-  hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+  return ILVES_OK;
+}
+
+// features of every row into the plan's buffers (or the given ones)
+ilves_status_t run_features(ilves_plan_t P, const double* r, const double* r_u, const double* mass, float* feat,
+                            float* w, hipStream_t stream) {
+  for (int wdt = 0; wdt < 2; ++wdt) {
+    hipError_t e = ilves_ws::launch_features(P->dp, P->d_lists + P->width_first[wdt], P->width_count[wdt], wdt == 1,
+                                             r, r_u, mass, P->n_atoms, P->d_ws, feat, w, stream);
+    if (e != hipSuccess) return fail(ILVES_ERR_HIP, std::string("features kernel: ") + hipGetErrorString(e));
+  }
+  return ILVES_OK;
+}
+
+ilves_status_t solve_impl(ilves_plan_t P, const double* r, const double* r_u, const double* mass, double tol,
+                          int32_t precision, int32_t variant, int32_t warm, int32_t max_iter, double* r_out,
+                          double* lambda, int32_t* iters, int32_t* status, int32_t* fallback, hipStream_t stream) {
   SolveArgs A;
   A.r = r;
   A.r_u = r_u;
@@ -846,12 +868,13 @@ ilves_status_t ilves_solve_ex(ilves_plan_t P, const double* r, const double* r_u
   A.lambda = lambda;
   A.iters = iters;
   A.status = status;
+  A.fallback = fallback;
   A.ws = P->d_ws;
   A.tol = tol;
   A.n_atoms = P->n_atoms;
   A.max_iter = max_iter > 0 ? max_iter
                             : (precision == ILVES_PREC_FP64 && variant == ILVES_VARIANT_NEWTON ? 20 : 40);
-  A.warm = warm_start == ILVES_WARM_CALLER ? 1 : 0;
+  A.warm = warm;
   A.chord = variant == ILVES_VARIANT_CHORD ? 1 : 0;
   if (P->n_free > 0) {
     const int tb = 256;
@@ -882,6 +905,116 @@ ilves_status_t ilves_solve_ex(ilves_plan_t P, const double* r, const double* r_u
     HIP_TRY(hipStreamWaitEvent(stream, P->ev_join[i], 0));
   }
   return ILVES_OK;
+}
+
+ilves_status_t predict_impl(ilves_plan_t P, const double* r, const double* r_u, const double* mass, double* lambda,
+                            hipStream_t stream) {
+  if (!P->d_mlp) return fail(ILVES_ERR_UNSUPPORTED, "no network loaded: call ilves_mlp_load first");
+  ilves_status_t st = run_features(P, r, r_u, mass, P->d_feat, P->d_w, stream);
+  if (st != ILVES_OK) return st;
+  hipError_t e = ilves_ws::launch_mlp_infer(P->d_mlp, P->d_mlp + ilves_ws::N_PARAMS, P->d_feat, P->d_w, P->dp.cid,
+                                            P->n_con, lambda, stream);
+  if (e != hipSuccess) return fail(ILVES_ERR_HIP, std::string("network kernel: ") + hipGetErrorString(e));
+  return ILVES_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+ilves_status_t ilves_solve_ex(ilves_plan_t P, const double* r, const double* r_u, const double* mass, double tol,
+                              int32_t precision, int32_t variant, int32_t warm_start, int32_t max_iter,
+                              double* r_out, double* lambda, int32_t* iters, int32_t* status, void* hip_stream) {
+  ilves_status_t st = check_solve_args(P, r, r_u, mass, tol, precision, variant, r_out, lambda, iters, status);
+  if (st != ILVES_OK) return st;
+  hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+  if (warm_start == ILVES_WARM_MLP)
+    return ilves_solve_learned(P, r, r_u, mass, tol, precision, variant, max_iter, r_out, lambda, iters, status,
+                               nullptr, hip_stream);
+  if (warm_start != ILVES_WARM_ZERO && warm_start != ILVES_WARM_CALLER) return fail(ILVES_ERR_ARG, "bad warm_start");
+  return solve_impl(P, r, r_u, mass, tol, precision, variant, warm_start == ILVES_WARM_CALLER ? 1 : 0, max_iter,
+                    r_out, lambda, iters, status, nullptr, stream);
+}
+
+ilves_status_t ilves_solve_learned(ilves_plan_t P, const double* r, const double* r_u, const double* mass, double tol,
+                                   int32_t precision, int32_t variant, int32_t max_iter, double* r_out,
+                                   double* lambda, int32_t* iters, int32_t* status, int32_t* fallback,
+                                   void* hip_stream) {
+  ilves_status_t st = check_solve_args(P, r, r_u, mass, tol, precision, variant, r_out, lambda, iters, status);
+  if (st != ILVES_OK) return st;
+  hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+  if (P->n_con == 0) return solve_impl(P, r, r_u, mass, tol, precision, variant, 0, max_iter, r_out, lambda, iters,
+                                       status, fallback, stream);
+  st = predict_impl(P, r, r_u, mass, lambda, stream);
+  if (st != ILVES_OK) return st;
+  return solve_impl(P, r, r_u, mass, tol, precision, variant, 2, max_iter, r_out, lambda, iters, status, fallback,
+                    stream);
+}
+
+ilves_status_t ilves_mlp_predict(ilves_plan_t P, const double* r, const double* r_u, const double* mass,
+                                 double* lambda, void* hip_stream) {
+  if (!P || !r || !r_u || !mass || (P->n_con > 0 && !lambda)) return fail(ILVES_ERR_ARG, "null argument");
+  if (P->n_con == 0) return ILVES_OK;
+  return predict_impl(P, r, r_u, mass, lambda, static_cast<hipStream_t>(hip_stream));
+}
+
+ilves_status_t ilves_features(ilves_plan_t P, const double* r, const double* r_u, const double* mass, float* feat,
+                              float* w, void* hip_stream) {
+  if (!P || !r || !r_u || !mass || (P->n_con > 0 && (!feat || !w))) return fail(ILVES_ERR_ARG, "null argument");
+  return run_features(P, r, r_u, mass, feat, w, static_cast<hipStream_t>(hip_stream));
+}
+
+ilves_status_t ilves_plan_row_constraints(ilves_plan_t P, int32_t* cid) {
+  if (!P || (P->n_con > 0 && !cid)) return fail(ILVES_ERR_ARG, "null argument");
+  int64_t off = 0;
+  for (const auto& M : P->mols) {
+    std::memcpy(cid + off, M.cid.data(), M.cid.size() * sizeof(int32_t));
+    off += static_cast<int64_t>(M.cid.size());
+  }
+  return ILVES_OK;
+}
+
+int32_t ilves_mlp_param_count(void) { return ilves_ws::N_PARAMS; }
+int32_t ilves_mlp_norm_count(void) { return ilves_ws::N_NORM; }
+
+ilves_status_t ilves_mlp_load(ilves_plan_t P, const float* params, const float* norm) {
+  if (!P || !params || !norm) return fail(ILVES_ERR_ARG, "null argument");
+  for (int i = 0; i < ilves_ws::N_FEAT; ++i)
+    if (!(norm[ilves_ws::N_FEAT + i] > 0.0f)) return fail(ILVES_ERR_ARG, "feature scales must be positive");
+  if (!P->d_mlp) HIP_TRY(hipMalloc(&P->d_mlp, sizeof(float) * (ilves_ws::N_PARAMS + ilves_ws::N_NORM)));
+  if (!P->d_feat && P->n_con > 0) {
+    HIP_TRY(hipMalloc(&P->d_feat, sizeof(float) * ilves_ws::N_FEAT * static_cast<size_t>(P->n_con)));
+    HIP_TRY(hipMalloc(&P->d_w, sizeof(float) * static_cast<size_t>(P->n_con)));
+  }
+  HIP_TRY(hipMemcpy(P->d_mlp, params, sizeof(float) * ilves_ws::N_PARAMS, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(P->d_mlp + ilves_ws::N_PARAMS, norm, sizeof(float) * ilves_ws::N_NORM, hipMemcpyHostToDevice));
+  return ILVES_OK;
+}
+
+ilves_status_t ilves_mlp_forward_f32(const float* params, const float* x, int32_t n, float* out, void* hip_stream) {
+  if (!params || (n > 0 && (!x || !out)) || n < 0) return fail(ILVES_ERR_ARG, "bad argument");
+  hipError_t e = ilves_ws::launch_mlp_forward_f32(params, x, n, out, static_cast<hipStream_t>(hip_stream));
+  return e == hipSuccess ? ILVES_OK : fail(ILVES_ERR_HIP, hipGetErrorString(e));
+}
+
+int64_t ilves_mlp_grad_workspace(int32_t n) {
+  return n <= 0 ? 0 : static_cast<int64_t>((n + ilves_ws::TRAIN_BS - 1) / ilves_ws::TRAIN_BS) * (ilves_ws::N_PARAMS + 1);
+}
+
+ilves_status_t ilves_mlp_grad_f32(const float* params, const float* x, const float* y, int32_t n, float* grad,
+                                  float* loss, float* work, int64_t work_floats, void* hip_stream) {
+  if (!params || !x || !y || !grad || !loss || !work || n <= 0) return fail(ILVES_ERR_ARG, "bad argument");
+  if (work_floats < ilves_mlp_grad_workspace(n)) return fail(ILVES_ERR_ARG, "workspace too small");
+  hipError_t e = ilves_ws::launch_mlp_grad_f32(params, x, y, n, grad, loss, work, static_cast<hipStream_t>(hip_stream));
+  return e == hipSuccess ? ILVES_OK : fail(ILVES_ERR_HIP, hipGetErrorString(e));
+}
+
+ilves_status_t ilves_mlp_adam_f32(float* params, const float* grad, float* m, float* v, int32_t n, float lr,
+                                  float beta1, float beta2, float eps, int32_t step, void* hip_stream) {
+  if (!params || !grad || !m || !v || n <= 0 || step < 1) return fail(ILVES_ERR_ARG, "bad argument");
+  hipError_t e = ilves_ws::launch_mlp_adam(params, grad, m, v, n, lr, beta1, beta2, eps, step,
+                                           static_cast<hipStream_t>(hip_stream));
+  return e == hipSuccess ? ILVES_OK : fail(ILVES_ERR_HIP, hipGetErrorString(e));
 }
 
 ilves_status_t ilves_solve(ilves_plan_t P, const double* r, const double* r_u, const double* mass, double tol,

@@ -1,0 +1,407 @@
+// Learned warm start for the Newton iteration (gfx950).
+//
+// The Newton iteration of Supplement section 2.3 starts from lambda_0 = 0.
+// Here a small network predicts lambda_0 from local constraint geometry:
+// per constraint k a 16-feature vector (rotation, translation and
+// mass-scale invariant: the decoupled diatomic solution t0_k, the initial
+// violation, geometry of old vs unconstrained bond vector, valences, and
+// sums over the constraints sharing an atom weighted by the normalised
+// coupling rho_kj = A_kj(r, r) / A_kk(r, r) of Eq. defA) feeds an MLP
+// [16 -> 64 -> 64 -> 1] with exact GELU whose output corrects t0:
+//   lambda_0 = (t0 + scale * MLP((f - mean) / std)) / w,  w = 1/m_a + 1/m_b.
+//
+// Inference runs in BF16 on the matrix cores (v_mfma_f32_16x16x16_bf16,
+// FP32 accumulation).  Every layer is computed transposed (hidden x rows),
+// so the accumulator tile of one layer is already the B operand of the
+// next: no LDS round trip between layers.  Training kernels are FP32
+// VALU: a 64-sample workgroup computes forward and backward passes with
+// activations in LDS and writes one partial gradient; a second kernel sums
+// the partials in a fixed order (deterministic), then Adam updates.
+#include "warmstart.hpp"
+
+#include <cmath>
+
+namespace ilves_ws {
+
+using namespace ilves_dev;
+
+namespace {
+
+__device__ inline float gelu(float x) { return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f)); }
+__device__ inline float gelu_grad(float x) {
+  return 0.5f * (1.0f + erff(x * 0.70710678118654752f)) + x * expf(-0.5f * x * x) * 0.39894228040143268f;
+}
+
+// float -> bfloat16 bits, round to nearest even
+__device__ inline short to_bf16(float f) {
+  unsigned int u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return static_cast<short>(u >> 16);
+}
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// ---------------------------------------------------------------------------
+// features: one workgroup per molecule, structure read from global memory
+
+template <typename Idx>
+__global__ void __launch_bounds__(256) features_kernel(const DevPlan P, const int32_t* __restrict__ mols,
+                                                       const double* __restrict__ r, const double* __restrict__ ru,
+                                                       const double* __restrict__ mass, int32_t S,
+                                                       unsigned char* __restrict__ ws, float* __restrict__ feat,
+                                                       float* __restrict__ wout) {
+  const int tid = threadIdx.x;
+  const MolDesc md = P.mol[mols[blockIdx.x]];
+  const int32_t n = md.n, s = md.s, n_up = md.n_up, n_l = md.n_l, H = md.n_levels;
+  const Idx* st = reinterpret_cast<const Idx*>(sizeof(Idx) == 2 ? static_cast<const void*>(P.ix16)
+                                                                 : static_cast<const void*>(P.ix32)) +
+                  md.ix_off;
+  const Idx* up_start = st;
+  const Idx* l_start = up_start + n + 1;
+  const Idx* ustart = l_start + n + 1 + 2 * (H + 1);
+  const Idx* ucol = ustart + n_up + 1;
+  const Idx* lcol = (ucol + 2 * n_up) - n_up;  // indexed by F index t in [n_up, n_up + n_l)
+  const int32_t* coef = P.coef + md.coef_off;
+  const int32_t* atom_gid = P.atom_gid + md.atom_off;
+  const int32_t* ra = P.ra + md.row_off;
+  const int32_t* rb = P.rb + md.row_off;
+  const double* d2 = P.d2 + md.row_off;
+  const int32_t* inc_ptr = P.inc_ptr + md.incp_off;
+  double* ex = reinterpret_cast<double*>(ws + md.ws_off);
+  double* ey = ex + n;
+  double* ez = ey + n;
+  const int64_t R0 = md.row_off;
+  (void)n_l;
+
+  // own quantities
+  for (int32_t k = tid; k < n; k += 256) {
+    const int32_t la = ra[k], lb = rb[k];
+    const int32_t ga = atom_gid[la], gb = atom_gid[lb];
+    const double e0 = r[ga] - r[gb], e1 = r[S + ga] - r[S + gb], e2 = r[2 * S + ga] - r[2 * S + gb];
+    const double u0 = ru[ga] - ru[gb], u1 = ru[S + ga] - ru[S + gb], u2 = ru[2 * S + ga] - ru[2 * S + gb];
+    const double ia = 1.0 / mass[ga], ib = 1.0 / mass[gb];
+    const double w = ia + ib;
+    const double ee = e0 * e0 + e1 * e1 + e2 * e2;
+    const double bb = u0 * e0 + u1 * e1 + u2 * e2;
+    const double c = u0 * u0 + u1 * u1 + u2 * u2 - d2[k];
+    const double disc = fmax(bb * bb - ee * c, 0.0);
+    const double cx = u1 * e2 - u2 * e1, cy = u2 * e0 - u0 * e2, cz = u0 * e1 - u1 * e0;
+    const int32_t dega = inc_ptr[la + 1] - inc_ptr[la], degb = inc_ptr[lb + 1] - inc_ptr[lb];
+    float* f = feat + (R0 + k) * N_FEAT;
+    f[0] = static_cast<float>(c / (bb + sqrt(disc)));
+    f[1] = static_cast<float>(c / (2.0 * d2[k]));
+    f[2] = static_cast<float>(bb / d2[k] - 1.0);
+    f[3] = static_cast<float>(sqrt(cx * cx + cy * cy + cz * cz) / d2[k]);
+    f[4] = static_cast<float>(fabs(ia - ib) / w);
+    f[5] = static_cast<float>((dega + degb - 2) * 0.25);
+    f[6] = static_cast<float>(abs(dega - degb) * 0.25);
+    wout[R0 + k] = static_cast<float>(w);
+    ex[k] = e0;
+    ey[k] = e1;
+    ez[k] = e2;
+  }
+  __syncthreads();
+  // sums over the constraints sharing an atom (original entries only)
+  for (int32_t k = tid; k < n; k += 256) {
+    const double e0 = ex[k], e1 = ey[k], e2 = ez[k];
+    const double ee = e0 * e0 + e1 * e1 + e2 * e2;
+    const double wk = static_cast<double>(wout[R0 + k]);
+    double s7 = 0, s8 = 0, s9 = 0, s10 = 0, s11 = 0, s12 = 0, s14 = 0, s15 = 0, cnt = 0;
+    auto visit = [&](int32_t t, int32_t j) {
+      const int32_t cf = coef[t];
+      const int32_t x = cf >> 1;
+      if (x >= s) return;  // fill entry
+      const double sg = (cf & 1) ? -1.0 : 1.0;
+      const double dot = e0 * ex[j] + e1 * ey[j] + e2 * ez[j];
+      const double rho = sg * dot / (mass[atom_gid[x]] * wk * ee);
+      const double q = wk / static_cast<double>(wout[R0 + j]);
+      const float* fj = feat + (R0 + j) * N_FEAT;
+      s7 += rho * q * fj[0];
+      s8 += fabs(rho);
+      s9 = fmax(s9, fabs(rho));
+      s10 += rho * q * fj[1];
+      s11 += rho * rho;
+      s12 += sg * dot / sqrt(ee * (ex[j] * ex[j] + ey[j] * ey[j] + ez[j] * ez[j]));
+      s14 += rho * q * fj[2];
+      s15 += rho * q * fj[3];
+      cnt += 1.0;
+    };
+    for (int32_t q = up_start[k]; q < up_start[k + 1]; ++q) visit(q, ucol[q]);
+    for (int32_t t = l_start[k]; t < l_start[k + 1]; ++t) visit(t, lcol[t]);
+    float* f = feat + (R0 + k) * N_FEAT;
+    f[7] = static_cast<float>(s7);
+    f[8] = static_cast<float>(s8);
+    f[9] = static_cast<float>(s9);
+    f[10] = static_cast<float>(s10);
+    f[11] = static_cast<float>(s11);
+    f[12] = static_cast<float>(s12 / fmax(cnt, 1.0));
+    f[13] = static_cast<float>(cnt / 6.0);
+    f[14] = static_cast<float>(s14);
+    f[15] = static_cast<float>(s15);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// BF16 MFMA inference.  Tile = 16 rows per wave.  Operand layouts of
+// v_mfma_f32_16x16x16_bf16 (lane l, i = 0..3):
+//   A (16 x 16, M x K): A[l % 16][4 (l / 16) + i]
+//   B (16 x 16, K x N): B[4 (l / 16) + i][l % 16]
+//   C (16 x 16):        C[4 (l / 16) + i][l % 16]
+// Layers are computed transposed, H^T = W^T X^T: A = W^T blocks, B = the
+// transposed activations (K = features or hidden units, N = rows).
+
+__global__ void __launch_bounds__(256) mlp_infer_kernel(const float* __restrict__ params,
+                                                        const float* __restrict__ norm,
+                                                        const float* __restrict__ feat, const float* __restrict__ w,
+                                                        const int32_t* __restrict__ cid, int32_t n_rows,
+                                                        double* __restrict__ lambda) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int col = lane & 15;   // row of the tile (N index)
+  const int kq = lane >> 4;    // which group of 4 along K / M
+  const float* W1 = params;
+  const float* b1 = W1 + N_FEAT * N_HID;
+  const float* W2 = b1 + N_HID;
+  const float* b2 = W2 + N_HID * N_HID;
+  const float* W3 = b2 + N_HID;
+  const float b3 = W3[N_HID];
+  const float* mean = norm;
+  const float* sdev = norm + N_FEAT;
+  const float scale = norm[2 * N_FEAT];
+
+  // weights as A operands: A1[hb] = W1^T block, A2[ob][kb] = W2^T block
+  bf16x4 A1[4], A2[4][4];
+  float bias1[4][4], bias2[4][4], w3[4][4];
+#pragma unroll
+  for (int hb = 0; hb < 4; ++hb) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      A1[hb][i] = to_bf16(W1[(4 * kq + i) * N_HID + 16 * hb + col]);
+      bias1[hb][i] = b1[16 * hb + 4 * kq + i];
+      bias2[hb][i] = b2[16 * hb + 4 * kq + i];
+      w3[hb][i] = W3[16 * hb + 4 * kq + i];
+    }
+  }
+#pragma unroll
+  for (int ob = 0; ob < 4; ++ob)
+#pragma unroll
+    for (int kb = 0; kb < 4; ++kb)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) A2[ob][kb][i] = to_bf16(W2[(16 * kb + 4 * kq + i) * N_HID + 16 * ob + col]);
+
+  const int n_tiles = (n_rows + 15) / 16;
+  for (int tile = blockIdx.x * 4 + wave; tile < n_tiles; tile += gridDim.x * 4) {
+    const int row = tile * 16 + col;
+    const bool valid = row < n_rows;
+    bf16x4 xb;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int f = 4 * kq + i;
+      const float v = valid ? (feat[static_cast<int64_t>(row) * N_FEAT + f] - mean[f]) / sdev[f] : 0.0f;
+      xb[i] = to_bf16(v);
+    }
+    bf16x4 h1[4];
+#pragma unroll
+    for (int hb = 0; hb < 4; ++hb) {
+      f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A1[hb], xb, acc, 0, 0, 0);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) h1[hb][i] = to_bf16(gelu(acc[i] + bias1[hb][i]));
+    }
+    float part = 0.0f;
+#pragma unroll
+    for (int ob = 0; ob < 4; ++ob) {
+      f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+      for (int kb = 0; kb < 4; ++kb) acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A2[ob][kb], h1[kb], acc, 0, 0, 0);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) part += w3[ob][i] * gelu(acc[i] + bias2[ob][i]);
+    }
+    // lanes l, l+16, l+32, l+48 hold partial sums of the same row
+    part += __shfl_xor(part, 16, 64);
+    part += __shfl_xor(part, 32, 64);
+    if (kq == 0 && valid) {
+      const float o = part + b3;
+      const float t = feat[static_cast<int64_t>(row) * N_FEAT] + scale * o;
+      lambda[cid[row]] = static_cast<double>(t) / static_cast<double>(w[row]);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// FP32 training kernels
+
+__global__ void __launch_bounds__(256) mlp_block_kernel(const float* __restrict__ params,
+                                                        const float* __restrict__ x, const float* __restrict__ y,
+                                                        int32_t n, float inv_n, float* __restrict__ part,
+                                                        float* __restrict__ out, int grad) {
+  __shared__ float X[TRAIN_BS][N_FEAT];
+  __shared__ float Z1[TRAIN_BS][N_HID + 1];
+  __shared__ float H1[TRAIN_BS][N_HID + 1];
+  __shared__ float Z2[TRAIN_BS][N_HID + 1];
+  __shared__ float H2[TRAIN_BS][N_HID + 1];
+  __shared__ float dO[TRAIN_BS];
+  __shared__ float sq[TRAIN_BS];
+  const int tid = threadIdx.x;
+  const float* W1 = params;
+  const float* b1 = W1 + N_FEAT * N_HID;
+  const float* W2 = b1 + N_HID;
+  const float* b2 = W2 + N_HID * N_HID;
+  const float* W3 = b2 + N_HID;
+  const float b3 = W3[N_HID];
+  const int64_t s0 = static_cast<int64_t>(blockIdx.x) * TRAIN_BS;
+  const int nb = static_cast<int>(min<int64_t>(TRAIN_BS, n - s0));
+
+  for (int e = tid; e < TRAIN_BS * N_FEAT; e += 256) {
+    const int s = e / N_FEAT, f = e % N_FEAT;
+    X[s][f] = s < nb ? x[(s0 + s) * N_FEAT + f] : 0.0f;
+  }
+  __syncthreads();
+  for (int e = tid; e < TRAIN_BS * N_HID; e += 256) {
+    const int s = e / N_HID, h = e % N_HID;
+    float z = b1[h];
+    for (int f = 0; f < N_FEAT; ++f) z += X[s][f] * W1[f * N_HID + h];
+    Z1[s][h] = z;
+    H1[s][h] = gelu(z);
+  }
+  __syncthreads();
+  for (int e = tid; e < TRAIN_BS * N_HID; e += 256) {
+    const int s = e / N_HID, h = e % N_HID;
+    float z = b2[h];
+    for (int i = 0; i < N_HID; ++i) z += H1[s][i] * W2[i * N_HID + h];
+    Z2[s][h] = z;
+    H2[s][h] = gelu(z);
+  }
+  __syncthreads();
+  if (tid < TRAIN_BS) {
+    const int s = tid;
+    float o = b3;
+    for (int h = 0; h < N_HID; ++h) o += H2[s][h] * W3[h];
+    if (!grad) {
+      if (s < nb) out[s0 + s] = o;
+    } else {
+      const float r = s < nb ? o - y[s0 + s] : 0.0f;
+      dO[s] = r * inv_n;
+      sq[s] = 0.5f * r * r * inv_n;
+    }
+  }
+  if (!grad) return;
+  __syncthreads();
+  for (int e = tid; e < TRAIN_BS * N_HID; e += 256) {  // dZ2 into Z2
+    const int s = e / N_HID, h = e % N_HID;
+    Z2[s][h] = dO[s] * W3[h] * gelu_grad(Z2[s][h]);
+  }
+  __syncthreads();
+  for (int e = tid; e < TRAIN_BS * N_HID; e += 256) {  // dZ1 into Z1
+    const int s = e / N_HID, i = e % N_HID;
+    float acc = 0.0f;
+    for (int h = 0; h < N_HID; ++h) acc += Z2[s][h] * W2[i * N_HID + h];
+    Z1[s][i] = acc * gelu_grad(Z1[s][i]);
+  }
+  __syncthreads();
+  float* g = part + static_cast<int64_t>(blockIdx.x) * (N_PARAMS + 1);
+  for (int p = tid; p <= N_PARAMS; p += 256) {
+    float acc = 0.0f;
+    int q = p;
+    if (q < N_FEAT * N_HID) {
+      const int f = q / N_HID, h = q % N_HID;
+      for (int s = 0; s < TRAIN_BS; ++s) acc += X[s][f] * Z1[s][h];
+    } else if ((q -= N_FEAT * N_HID) < N_HID) {
+      for (int s = 0; s < TRAIN_BS; ++s) acc += Z1[s][q];
+    } else if ((q -= N_HID) < N_HID * N_HID) {
+      const int i = q / N_HID, h = q % N_HID;
+      for (int s = 0; s < TRAIN_BS; ++s) acc += H1[s][i] * Z2[s][h];
+    } else if ((q -= N_HID * N_HID) < N_HID) {
+      for (int s = 0; s < TRAIN_BS; ++s) acc += Z2[s][q];
+    } else if ((q -= N_HID) < N_HID) {
+      for (int s = 0; s < TRAIN_BS; ++s) acc += dO[s] * H2[s][q];
+    } else if ((q -= N_HID) < 1) {
+      for (int s = 0; s < TRAIN_BS; ++s) acc += dO[s];
+    } else {
+      for (int s = 0; s < TRAIN_BS; ++s) acc += sq[s];  // loss
+    }
+    g[p] = acc;
+  }
+}
+
+__global__ void reduce_partials(const float* __restrict__ part, int32_t nblocks, float* __restrict__ grad,
+                                float* __restrict__ loss) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p > N_PARAMS) return;
+  float acc = 0.0f;
+  for (int b = 0; b < nblocks; ++b) acc += part[static_cast<int64_t>(b) * (N_PARAMS + 1) + p];
+  if (p < N_PARAMS) grad[p] = acc;
+  else *loss = acc;
+}
+
+__global__ void adam_kernel(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
+                            float* __restrict__ v, int32_t n, float lr, float beta1, float beta2, float eps,
+                            float bc1, float bc2) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = beta1 * m[i] + (1.0f - beta1) * gi;
+  const float vi = beta2 * v[i] + (1.0f - beta2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  p[i] -= lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
+}
+
+}  // namespace
+
+hipError_t launch_features(const DevPlan& P, const int32_t* mols, int32_t n_mols, bool wide, const double* r,
+                           const double* r_u, const double* mass, int32_t n_atoms, unsigned char* ws, float* feat,
+                           float* w, hipStream_t stream) {
+  if (n_mols <= 0) return hipSuccess;
+  if (wide)
+    hipLaunchKernelGGL(features_kernel<int32_t>, dim3(n_mols), dim3(256), 0, stream, P, mols, r, r_u, mass,
+                       n_atoms, ws, feat, w);
+  else
+    hipLaunchKernelGGL(features_kernel<uint16_t>, dim3(n_mols), dim3(256), 0, stream, P, mols, r, r_u, mass,
+                       n_atoms, ws, feat, w);
+  return hipGetLastError();
+}
+
+hipError_t launch_mlp_infer(const float* params, const float* norm, const float* feat, const float* w,
+                            const int32_t* cid, int32_t n_rows, double* lambda, hipStream_t stream) {
+  if (n_rows <= 0) return hipSuccess;
+  const int tiles = (n_rows + 15) / 16;
+  const int blocks = (tiles + 3) / 4 < 2048 ? (tiles + 3) / 4 : 2048;
+  hipLaunchKernelGGL(mlp_infer_kernel, dim3(blocks), dim3(256), 0, stream, params, norm, feat, w, cid, n_rows,
+                     lambda);
+  return hipGetLastError();
+}
+
+hipError_t launch_mlp_forward_f32(const float* params, const float* x, int32_t n, float* out, hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  const int blocks = (n + TRAIN_BS - 1) / TRAIN_BS;
+  hipLaunchKernelGGL(mlp_block_kernel, dim3(blocks), dim3(256), 0, stream, params, x, nullptr, n, 0.0f, nullptr,
+                     out, 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_mlp_grad_f32(const float* params, const float* x, const float* y, int32_t n, float* grad,
+                               float* loss, float* work, hipStream_t stream) {
+  if (n <= 0) return hipErrorInvalidValue;
+  const int blocks = (n + TRAIN_BS - 1) / TRAIN_BS;
+  hipLaunchKernelGGL(mlp_block_kernel, dim3(blocks), dim3(256), 0, stream, params, x, y, n, 1.0f / n, work,
+                     nullptr, 1);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(reduce_partials, dim3((N_PARAMS + 1 + 255) / 256), dim3(256), 0, stream, work, blocks, grad,
+                     loss);
+  return hipGetLastError();
+}
+
+hipError_t launch_mlp_adam(float* params, const float* grad, float* m, float* v, int32_t n, float lr, float beta1,
+                           float beta2, float eps, int32_t step, hipStream_t stream) {
+  if (n <= 0 || step < 1) return hipErrorInvalidValue;
+  const float bc1 = 1.0f - powf(beta1, static_cast<float>(step));
+  const float bc2 = 1.0f - powf(beta2, static_cast<float>(step));
+  hipLaunchKernelGGL(adam_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, params, grad, m, v, n, lr, beta1,
+                     beta2, eps, bc1, bc2);
+  return hipGetLastError();
+}
+
+}  // namespace ilves_ws
