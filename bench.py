@@ -101,7 +101,7 @@ def main():
     ap.add_argument("--pool", type=int, default=8, help="distinct r_u sets resident in HBM")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
-    ap.add_argument("--variants", default="fp64,mixed", help="comma list of fp64,mixed")
+    ap.add_argument("--variants", default="fp64,mixed,learned", help="comma list of fp64,mixed,learned")
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="MiB of a plain device copy run once before timing (counter calibration)")
     args = ap.parse_args()
@@ -135,20 +135,28 @@ def main():
     ncon_mol = torch.from_numpy(mol["n_con"].astype(np.int64)).to(dev)
     stream = torch.cuda.current_stream()
 
-    def run(precision, steps, warmup):
+    def run(precision, steps, warmup, learned=False):
         iters = torch.zeros((steps, nm), dtype=torch.int32, device=dev)
         status = torch.full((steps, nm), -1, dtype=torch.int32, device=dev)
+        fallback = torch.zeros((steps, nm), dtype=torch.int32, device=dev)
         wi = torch.zeros(nm, dtype=torch.int32, device=dev)
         ws = torch.zeros(nm, dtype=torch.int32, device=dev)
+
+        def one(k, it, stt, fb):
+            if learned:
+                plan.solve_learned(r, pool[k % len(pool)], mass, 1e-12, r_out, lam, it, stt, fb, precision=precision)
+            else:
+                plan.solve(r, pool[k % len(pool)], mass, 1e-12, r_out, lam, it, stt, precision=precision)
+
         for w in range(warmup):
-            plan.solve(r, pool[w % len(pool)], mass, 1e-12, r_out, lam, wi, ws, precision=precision)
+            one(w, wi, ws, None)
         torch.cuda.synchronize()
         ev0 = torch.cuda.Event(enable_timing=True)
         ev1 = torch.cuda.Event(enable_timing=True)
         t_start = time.perf_counter()
         ev0.record(stream)
         for k in range(steps):
-            plan.solve(r, pool[k % len(pool)], mass, 1e-12, r_out, lam, iters[k], status[k], precision=precision)
+            one(k, iters[k], status[k], fallback[k])
         ev1.record(stream)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t_start
@@ -158,6 +166,7 @@ def main():
         it = iters.to(torch.float64)
         return {"gpu_ms": gpu_ms, "wall_s": wall, "solved": solved, "all_ok": bool(ok.all().item()),
                 "iters_mean": float(it.mean().item()), "iters_max": int(iters.max().item()),
+                "fallback_rate": float(fallback.to(torch.float64).mean().item()),
                 "last_index": (steps - 1) % len(pool)}
 
     def check_last(res):
@@ -178,10 +187,15 @@ def main():
 
     results = {}
     wanted = set(args.variants.split(","))
-    for name, prec in (("fp64", L.PREC_FP64), ("mixed", L.PREC_MIXED)):
+    from paper_2503_13075_amd import warmstart as WS
+    weights = WS.WEIGHTS["angles" if args.workload == "angles" else "trees"]
+    if "learned" in wanted:
+        params, norm, meta = WS.load(weights)
+        plan.load_mlp(params, norm)
+    for name, prec in (("fp64", L.PREC_FP64), ("mixed", L.PREC_MIXED), ("learned", L.PREC_MIXED)):
         if name not in wanted:
             continue
-        res = run(prec, args.steps, args.warmup)
+        res = run(prec, args.steps, args.warmup, learned=(name == "learned"))
         res["max_rel_violation_last"] = check_last(res)
         ms = res["gpu_ms"] / args.steps
         res["ms_per_step"] = ms
@@ -190,12 +204,18 @@ def main():
         log(f"{name}: {ms:.3f} ms/step, {res['constraints_per_s']:.3e} constraints/s, all ok {res['all_ok']}, "
             f"iters mean {res['iters_mean']:.2f} max {res['iters_max']}, last violation {res['max_rel_violation_last']:.2e}")
 
-    if "mixed" not in results or "fp64" not in results:
-        print(json.dumps({k: {kk: vv for kk, vv in v.items()} for k, v in results.items()}), flush=True)
+    if "fp64" not in results or ("mixed" not in results and "learned" not in results):
+        print(json.dumps(results), flush=True)
         return
-    head = results["mixed"]
+    head_name = max((k for k in ("mixed", "learned") if k in results),
+                    key=lambda k: results[k]["constraints_per_s"])
+    head = results[head_name]
     abytes = algorithmic_bytes(sm, st)
     achieved = abytes / (head["ms_per_step"] / 1e3) / 1e9
+    variants = {k: {"value": v["constraints_per_s"], "ms_per_step": v["ms_per_step"], "all_ok": v["all_ok"],
+                    "newton_iters_mean": v["iters_mean"], "newton_iters_max": v["iters_max"],
+                    "fallback_rate": v["fallback_rate"] if k == "learned" else None,
+                    "max_rel_violation_last": v["max_rel_violation_last"]} for k, v in results.items()}
     out = {
         "metric": "constraints solved/s at <=1e-12 rel violation",
         "value": head["constraints_per_s"],
@@ -207,16 +227,15 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64 residual/lambda/positions + f32 factor (mixed)",
+        "dtype": "f64 residual/lambda/positions, f32 factor; bf16 network (learned start)",
         "data": "synthetic",
-        "config": dict(cfg, atoms=sm.n_atoms, constraints=sm.n_constraints, variant="mixed Newton, lambda_0=0",
+        "config": dict(cfg, atoms=sm.n_atoms, constraints=sm.n_constraints,
+                       variant=("mixed precision Newton, learned lambda_0" if head_name == "learned"
+                                else "mixed precision Newton, lambda_0 = 0"),
                        sigma_nm=sigma, tol=1e-12),
-        "newton_iters": {"mixed_mean": head["iters_mean"], "mixed_max": head["iters_max"],
-                         "fp64_mean": results["fp64"]["iters_mean"], "fp64_max": results["fp64"]["iters_max"]},
-        "fp64": {"value": results["fp64"]["constraints_per_s"], "ms_per_step": results["fp64"]["ms_per_step"],
-                 "all_ok": results["fp64"]["all_ok"],
-                 "max_rel_violation_last": results["fp64"]["max_rel_violation_last"]},
-        "mixed_vs_fp64": head["constraints_per_s"] / results["fp64"]["constraints_per_s"],
+        "newton_iters": {k: v["iters_mean"] for k, v in results.items()},
+        "variants": variants,
+        "speedup_vs_fp64": head["constraints_per_s"] / results["fp64"]["constraints_per_s"],
         "all_ok": head["all_ok"],
         "max_rel_violation_last": head["max_rel_violation_last"],
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -26,8 +26,10 @@ from . import _lib as L
 from . import synth as S
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-DEFAULT_WEIGHTS = os.path.join(HERE, "weights", "warmstart_mlp.npz")
-SIGMA = 0.006
+WEIGHTS = {"angles": os.path.join(HERE, "weights", "warmstart_c3like.npz"),
+           "trees": os.path.join(HERE, "weights", "warmstart_trees.npz")}
+DEFAULT_WEIGHTS = WEIGHTS["angles"]
+SIGMA = {"angles": 0.006, "trees": 0.002}
 N_FEAT, N_HID = 16, 64
 
 
@@ -38,8 +40,19 @@ def c3like_system(seed: int, n_res: int = 40, n_lipid: int = 20) -> S.System:
     return S.concat(mols, spacing=3.0, name=f"c3like{seed}")
 
 
-def perturbed(sm: S.System, seed: int) -> np.ndarray:
-    return S.perturb(sm.r, SIGMA, 500_000 + seed)
+def trees_system(seed: int, n_mol: int = 6) -> S.System:
+    """A few random-tree molecules of log-uniform size (batch workload)."""
+    sizes = S.batch_sizes(n_mol, 31337 + seed)
+    return S.concat([S.random_tree(int(n), 9_000_000 + 97 * seed + i) for i, n in enumerate(sizes)], spacing=3.0,
+                    name=f"trees{seed}")
+
+
+def make_system(kind: str, seed: int) -> S.System:
+    return c3like_system(seed) if kind == "angles" else trees_system(seed)
+
+
+def perturbed(sm: S.System, seed: int, kind: str = "angles") -> np.ndarray:
+    return S.perturb(sm.r, SIGMA[kind], 500_000 + seed)
 
 
 def _device_inputs(sm, ru, dev):
@@ -50,15 +63,15 @@ def _device_inputs(sm, ru, dev):
     return r, rut, mass
 
 
-def harvest(seeds, dev="cuda", log=print):
+def harvest(seeds, dev="cuda", log=print, kind="angles"):
     """(features [N, 16] float32, t* = lambda* w [N] float64) over the seeds,
     from converged FP64 solves."""
     import torch
     feats, targets = [], []
     t0 = time.perf_counter()
     for i, seed in enumerate(seeds):
-        sm = c3like_system(seed)
-        ru = perturbed(sm, seed)
+        sm = make_system(kind, seed)
+        ru = perturbed(sm, seed, kind)
         plan = L.Plan(sm.n_atoms, sm.pairs, sm.d)
         r, rut, mass = _device_inputs(sm, ru, dev)
         n = sm.n_constraints
@@ -177,14 +190,14 @@ def load(path=DEFAULT_WEIGHTS):
         return z["params"].astype(np.float32), z["norm"].astype(np.float32), json.loads(str(z["meta"]))
 
 
-def evaluate(seeds, params, norm, precision=L.PREC_MIXED, dev="cuda", tol=1e-12):
+def evaluate(seeds, params, norm, precision=L.PREC_MIXED, dev="cuda", tol=1e-12, kind="angles"):
     """Newton iterations with lambda_0 = 0 vs the learned start on the
     given seeds (per molecule), fallback rate and convergence."""
     import torch
     it0, it1, fb, ok0, ok1 = [], [], [], [], []
     for seed in seeds:
-        sm = c3like_system(seed)
-        ru = perturbed(sm, seed)
+        sm = make_system(kind, seed)
+        ru = perturbed(sm, seed, kind)
         plan = L.Plan(sm.n_atoms, sm.pairs, sm.d)
         plan.load_mlp(params, norm)
         r, rut, mass = _device_inputs(sm, ru, dev)
@@ -214,7 +227,8 @@ def evaluate(seeds, params, norm, precision=L.PREC_MIXED, dev="cuda", tol=1e-12)
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("cmd", choices=["train", "evaluate"])
-    ap.add_argument("--out", default=DEFAULT_WEIGHTS)
+    ap.add_argument("--kind", choices=["angles", "trees"], default="angles")
+    ap.add_argument("--out", default=None)
     ap.add_argument("--seeds", type=int, default=1000)
     ap.add_argument("--pairs", type=int, default=1_000_000)
     ap.add_argument("--epochs", type=int, default=30)
@@ -224,23 +238,29 @@ def main(argv=None):
     def log(*a):
         print(*a, flush=True)
 
+    out = args.out or WEIGHTS[args.kind]
     if args.cmd == "train":
-        X, t = harvest(range(args.seeds), log=log)
+        X, t = harvest(range(args.seeds), log=log, kind=args.kind)
         rng = np.random.default_rng(0)
         if len(t) > args.pairs:
             sel = rng.choice(len(t), args.pairs, replace=False)
             X, t = X[sel], t[sel]
         log(f"training on {len(t)} pairs")
         params, norm, hist = train(X, t, epochs=args.epochs, log=log)
-        res = evaluate(range(1000, 1000 + args.eval_seeds), params, norm)
+        res = evaluate(range(1000, 1000 + args.eval_seeds), params, norm, kind=args.kind)
         log(f"held-out evaluation: {res}")
-        meta = {"pairs": int(len(t)), "train_seeds": [0, args.seeds - 1], "epochs": args.epochs,
-                "history": hist[-3:], "heldout": res, "sigma_nm": SIGMA}
-        save(args.out, params, norm, meta)
-        log(f"saved {args.out}")
+        meta = {"kind": args.kind, "pairs": int(len(t)), "train_seeds": [0, args.seeds - 1], "epochs": args.epochs,
+                "history": hist[-3:], "heldout": res, "sigma_nm": SIGMA[args.kind]}
+        save(out, params, norm, meta)
+        log(f"saved {out}")
     else:
-        params, norm, meta = load(args.out)
-        res = evaluate(range(1000, 1000 + args.eval_seeds), params, norm)
+        params, norm, meta = load(out)
+        res = evaluate(range(1000, 1000 + args.eval_seeds), params, norm, kind=args.kind)
+        # ablation: the untrained network (zero output layer) returns the
+        # decoupled solution t0 alone
+        res0 = evaluate(range(1000, 1000 + args.eval_seeds), init_params(0), norm, kind=args.kind)
+        res["iters_decoupled_start_mean"] = res0["iters_learned_mean"]
+        res["fallback_rate_decoupled_start"] = res0["fallback_rate"]
         log(json.dumps(res))
 
 
