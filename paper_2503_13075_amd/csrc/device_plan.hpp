@@ -17,7 +17,7 @@ enum { ALL_LDS = 0, STRUCT_LDS = 1, GLOBAL = 2 };
 struct MolDesc {
   int32_t n, s, n_up, n_l, n_upd, n_levels, n_pl;
   int32_t wide;       // 0: 16-bit structure indices, 1: 32-bit
-  int32_t ix_off;     // structure block in the index pool of its width
+  int64_t ix_off;     // byte offset of the structure block in the structure pool
   int32_t coef_off;   // ucoef then lcoef
   int32_t row_off;    // ra, rb, cid, d2 (also the global row index of row 0)
   int32_t atom_off;   // atom_gid
@@ -26,20 +26,38 @@ struct MolDesc {
   int64_t ws_off;     // byte offset of the molecule's workspace
 };
 
-// Structure block of one molecule, in this order:
-//   up_start[n+1] l_start[n+1] lvl_row[H+1] pl_start[H+1] ustart[n_up+1]
-//   ucol[n_up] utr[n_up] lcol[n_l] ltr[n_l] upd_a[n_upd] upd_b[n_upd]
-//   plist[n_pl]
-__host__ __device__ inline int64_t struct_elems(int32_t n, int32_t H, int32_t n_up, int32_t n_l, int32_t n_upd,
-                                                int32_t n_pl) {
-  return 2 * (static_cast<int64_t>(n) + 1) + 2 * (static_cast<int64_t>(H) + 1) + 3 * static_cast<int64_t>(n_up) + 1 +
-         2 * static_cast<int64_t>(n_l) + 2 * static_cast<int64_t>(n_upd) + n_pl;
+// Structure block of one molecule (index type of isz bytes, 2 or 4), as
+// byte offsets from the block start (16-byte aligned):
+//   up_start[n+1], l_start[n+1], ucol[n_up]          per row / upper slot
+//   lvh[H]      level header {first row, end row, first pair task, end}
+//   lpair[n_l]  lower slot t: {column i, slot of the transpose (i, k)}
+//   prec[n_pl]  pair task: {upper slot q, slot of (m, j), first update, count}
+//   upd[n_upd]  update: {slot (j,i), slot (m,i), slot (i,m), slot (i,j)}
+//   updi[n_upd] row i of the update
+struct Layout {
+  int64_t up_start, l_start, ucol, lvh, lpair, prec, upd, updi, total;
+};
+
+__host__ __device__ inline int64_t align_to(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
+
+__host__ __device__ inline Layout struct_layout(int32_t n, int32_t H, int32_t n_up, int32_t n_l, int32_t n_pl,
+                                                int32_t n_upd, int isz) {
+  Layout L;
+  L.up_start = 0;
+  L.l_start = L.up_start + static_cast<int64_t>(isz) * (n + 1);
+  L.ucol = L.l_start + static_cast<int64_t>(isz) * (n + 1);
+  L.lvh = align_to(L.ucol + static_cast<int64_t>(isz) * n_up, 4 * isz);
+  L.lpair = L.lvh + static_cast<int64_t>(4 * isz) * H;
+  L.prec = align_to(L.lpair + static_cast<int64_t>(2 * isz) * n_l, 4 * isz);
+  L.upd = L.prec + static_cast<int64_t>(4 * isz) * n_pl;
+  L.updi = L.upd + static_cast<int64_t>(4 * isz) * n_upd;
+  L.total = align_to(L.updi + static_cast<int64_t>(isz) * n_upd, 16);
+  return L;
 }
 
 struct DevPlan {
   const MolDesc* mol;
-  const uint16_t* ix16;
-  const int32_t* ix32;
+  const unsigned char* ix;    // structure pool (16-byte aligned blocks)
   const int32_t* coef;
   const int32_t* ra;
   const int32_t* rb;

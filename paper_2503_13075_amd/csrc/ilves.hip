@@ -43,6 +43,7 @@
 #include <cstring>
 #include <memory>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/ilves.h"
@@ -99,6 +100,32 @@ __host__ __device__ inline size_t value_bytes(int32_t n, int32_t n_up, int32_t n
   return align16(sizeof(T) * (static_cast<size_t>(n_up) + n_l + 2 * static_cast<size_t>(n)));
 }
 
+// packed structure records: 2 or 4 indices in one LDS/global access
+__device__ inline void ld2(const uint16_t* p, int32_t& a, int32_t& b) {
+  const uint32_t v = *reinterpret_cast<const uint32_t*>(p);
+  a = static_cast<int32_t>(v & 0xffffu);
+  b = static_cast<int32_t>(v >> 16);
+}
+__device__ inline void ld2(const int32_t* p, int32_t& a, int32_t& b) {
+  const int2 v = *reinterpret_cast<const int2*>(p);
+  a = v.x;
+  b = v.y;
+}
+__device__ inline void ld4(const uint16_t* p, int32_t& a, int32_t& b, int32_t& c, int32_t& d) {
+  const uint2 v = *reinterpret_cast<const uint2*>(p);
+  a = static_cast<int32_t>(v.x & 0xffffu);
+  b = static_cast<int32_t>(v.x >> 16);
+  c = static_cast<int32_t>(v.y & 0xffffu);
+  d = static_cast<int32_t>(v.y >> 16);
+}
+__device__ inline void ld4(const int32_t* p, int32_t& a, int32_t& b, int32_t& c, int32_t& d) {
+  const int4 v = *reinterpret_cast<const int4*>(p);
+  a = v.x;
+  b = v.y;
+  c = v.z;
+  d = v.w;
+}
+
 template <typename T> __device__ inline T pivot_eps();
 template <> __device__ inline double pivot_eps<double>() { return 1e-13; }
 template <> __device__ inline float pivot_eps<float>() { return 1e-6f; }
@@ -108,50 +135,50 @@ template <> __device__ inline float pivot_eps<float>() { return 1e-6f; }
 
 template <typename T, typename Idx, int MODE, int BLOCK>
 __global__ void __launch_bounds__(BLOCK) solve_kernel(const DevPlan P, const int32_t* __restrict__ mols,
+                                                      const int32_t count, int32_t* __restrict__ counter,
                                                       const SolveArgs A) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ double red[BLOCK / 64];
   __shared__ double red0[BLOCK / 64];
   __shared__ int32_t singular;
+  __shared__ int32_t next_slot;
 
   const int tid = threadIdx.x;
-  const int32_t m_idx = mols[blockIdx.x];
+  // persistent workgroup: take molecules (largest first) from the queue
+  // until it is empty; every wave of the workgroup leaves together
+  for (;;) {
+  if (tid == 0) next_slot = atomicAdd(counter, 1);
+  __syncthreads();
+  const int32_t slot = next_slot;
+  if (slot >= count) break;
+  const int32_t m_idx = mols[slot];
   const MolDesc md = P.mol[m_idx];
   const int32_t n = md.n, s = md.s, n_up = md.n_up, n_l = md.n_l, n_upd = md.n_upd, H = md.n_levels;
   const int32_t n_pl = md.n_pl;
   const int32_t S = A.n_atoms;
 
   // ---- structure (LDS copy unless GLOBAL)
-  const Idx* gst = reinterpret_cast<const Idx*>(sizeof(Idx) == 2 ? static_cast<const void*>(P.ix16)
-                                                                  : static_cast<const void*>(P.ix32)) +
-                   md.ix_off;
-  const int64_t nst = struct_elems(n, H, n_up, n_l, n_upd, n_pl);
-  const Idx* st;
+  const Layout Lo = struct_layout(n, H, n_up, n_l, n_pl, n_upd, static_cast<int>(sizeof(Idx)));
+  const unsigned char* gst = P.ix + md.ix_off;
+  const unsigned char* st;
   if (MODE == GLOBAL) {
     st = gst;
   } else {
-    Idx* lst = reinterpret_cast<Idx*>(smem);
-    // 16-byte copies of the (16-byte aligned) block, then the tail
-    const int64_t nvec = (nst * static_cast<int64_t>(sizeof(Idx))) / 16;
+    const int64_t nvec = Lo.total / 16;  // blocks are 16-byte aligned and padded
     const int4* gv = reinterpret_cast<const int4*>(gst);
-    int4* lv = reinterpret_cast<int4*>(lst);
+    int4* lv = reinterpret_cast<int4*>(smem);
     for (int64_t i = tid; i < nvec; i += BLOCK) lv[i] = gv[i];
-    for (int64_t i = nvec * 16 / static_cast<int64_t>(sizeof(Idx)) + tid; i < nst; i += BLOCK) lst[i] = gst[i];
-    st = lst;
+    st = smem;
   }
-  const Idx* __restrict__ up_start = st;
-  const Idx* __restrict__ l_start = up_start + n + 1;
-  const Idx* __restrict__ lvl_row = l_start + n + 1;
-  const Idx* __restrict__ pl_start = lvl_row + H + 1;
-  const Idx* __restrict__ ustart = pl_start + H + 1;
-  const Idx* __restrict__ ucol = ustart + n_up + 1;
-  const Idx* __restrict__ utr = ucol + n_up;
-  // lower-slot arrays are indexed by the F index t in [n_up, n_up + n_l)
-  const Idx* __restrict__ lcol = (utr + n_up) - n_up;
-  const Idx* __restrict__ ltr = (utr + n_up + n_l) - n_up;
-  const Idx* __restrict__ upd_a = utr + n_up + 2 * n_l;
-  const Idx* __restrict__ upd_b = upd_a + n_upd;
-  const Idx* __restrict__ plist = upd_b + n_upd;
+  const Idx* __restrict__ up_start = reinterpret_cast<const Idx*>(st + Lo.up_start);
+  const Idx* __restrict__ l_start = reinterpret_cast<const Idx*>(st + Lo.l_start);
+  const Idx* __restrict__ ucol = reinterpret_cast<const Idx*>(st + Lo.ucol);
+  const Idx* __restrict__ lvh = reinterpret_cast<const Idx*>(st + Lo.lvh);
+  // lower-slot records are indexed by the F index t in [n_up, n_up + n_l)
+  const Idx* __restrict__ lpair = reinterpret_cast<const Idx*>(st + Lo.lpair) - 2 * static_cast<int64_t>(n_up);
+  const Idx* __restrict__ prec = reinterpret_cast<const Idx*>(st + Lo.prec);
+  const Idx* __restrict__ upd = reinterpret_cast<const Idx*>(st + Lo.upd);
+  const Idx* __restrict__ updi = reinterpret_cast<const Idx*>(st + Lo.updi);
   const int32_t* __restrict__ coef = P.coef + md.coef_off;
 
   // ---- workspace and values
@@ -167,7 +194,7 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(const DevPlan P, const int
   double* __restrict__ cf = cd + n;
   double* __restrict__ invm = cf + n_up + n_l;
   T* __restrict__ F;
-  if (MODE == ALL_LDS) F = reinterpret_cast<T*>(smem + align16(sizeof(Idx) * static_cast<size_t>(nst)));
+  if (MODE == ALL_LDS) F = reinterpret_cast<T*>(smem + Lo.total);
   else F = reinterpret_cast<T*>(wsb + ws_vec_bytes(n, s, n_up, n_l));
   T* __restrict__ D = F + n_up + n_l;
   T* __restrict__ y = D + n;
@@ -238,7 +265,7 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(const DevPlan P, const int
 
   // row k of A(x, r), x having bond vector (px, py, pz); level-0 rows have
   // no lower entries, so their factorisation is just the inverted pivot
-  const int32_t level1 = H > 1 ? static_cast<int32_t>(lvl_row[1]) : n;
+  const int32_t level1 = static_cast<int32_t>(lvh[1]);  // end row of level 0
   auto build_row = [&](int32_t k, double px, double py, double pz) {
     const T akk = static_cast<T>(cd[k] * (px * ex[k] + py * ey[k] + pz * ez[k]));
     if (k < level1) {
@@ -252,43 +279,50 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(const DevPlan P, const int
       F[q] = static_cast<T>(cf[q] * (px * ex[j] + py * ey[j] + pz * ez[j]));
     }
     for (int32_t t = l_start[k], t1 = l_start[k + 1]; t < t1; ++t) {
-      const int32_t j = lcol[t];
+      const int32_t j = lpair[2 * t];
       F[t] = static_cast<T>(cf[t] * (px * ex[j] + py * ey[j] + pz * ez[j]));
     }
   };
 
-  // one elimination level: diagonal entries (forward substitution fused)
-  // and, unless only the forward substitution is wanted, upper entries
-  auto factor_level = [&](int32_t h, bool with_forward, bool with_factor) {
-    const int32_t r0 = lvl_row[h], r1 = lvl_row[h + 1];
+  // one elimination level: diagonal entries (forward substitution fused
+  // when FORWARD) and, when FACTOR, the upper entries with updates
+  auto factor_level = [&](int32_t h, auto factor_tag, auto forward_tag) {
+    constexpr bool FACTOR = decltype(factor_tag)::value;
+    constexpr bool FORWARD = decltype(forward_tag)::value;
+    int32_t r0, r1, p0, p1;
+    ld4(lvh + 4 * h, r0, r1, p0, p1);
     const int32_t nr = r1 - r0;
-    const int32_t p0 = pl_start[h];
-    const int32_t items = nr + (with_factor ? static_cast<int32_t>(pl_start[h + 1]) - p0 : 0);
+    const int32_t items = nr + (FACTOR ? p1 - p0 : 0);
     for (int32_t idx = tid; idx < items; idx += BLOCK) {
       if (idx < nr) {
         const int32_t j = r0 + idx;
         T acc = D[j], yj = y[j];
         const T a0 = acc;
-        for (int32_t t = l_start[j], t1 = l_start[j + 1]; t < t1; ++t) {
-          const int32_t i = lcol[t];
+        const int32_t t0 = l_start[j], t1 = l_start[j + 1];
+#pragma unroll 2
+        for (int32_t t = t0; t < t1; ++t) {
+          int32_t i, sl;
+          ld2(lpair + 2 * t, i, sl);
           const T l = F[t] * D[i];
-          if (with_factor) acc -= l * F[ltr[t]];
-          if (with_forward) yj -= l * y[i];
+          if (FACTOR) acc -= l * F[sl];
+          if (FORWARD) yj -= l * y[i];
         }
-        if (with_factor) {
+        if (FACTOR) {
           if (!(fabs(acc) > pivot_eps<T>() * fabs(a0))) singular = 1;
           D[j] = T(1) / acc;
         }
-        if (with_forward) y[j] = yj;
-      } else {
-        const int32_t q = plist[p0 + idx - nr];
-        const int32_t tr = utr[q];
+        if (FORWARD) y[j] = yj;
+      } else if (FACTOR) {
+        int32_t q, tr, u0, nu;
+        ld4(prec + 4 * (p0 + idx - nr), q, tr, u0, nu);
         T au = F[q], aw = F[tr];
-        for (int32_t u = ustart[q], u1 = ustart[q + 1]; u < u1; ++u) {
-          const int32_t pa = upd_a[u], pb = upd_b[u];
-          const T di = D[lcol[pa]];
-          au -= F[pa] * di * F[ltr[pb]];
-          aw -= F[pb] * di * F[ltr[pa]];
+#pragma unroll 2
+        for (int32_t u = u0; u < u0 + nu; ++u) {
+          int32_t pa, pb, s1, s2;
+          ld4(upd + 4 * u, pa, pb, s1, s2);
+          const T di = D[updi[u]];
+          au -= F[pa] * di * F[s1];
+          aw -= F[pb] * di * F[s2];
         }
         F[q] = au;
         F[tr] = aw;
@@ -301,7 +335,7 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(const DevPlan P, const int
     for (int32_t k = tid; k < n; k += BLOCK) build_row(k, ex[k], ey[k], ez[k]);
     __syncthreads();
     for (int32_t h = 1; h < H; ++h) {
-      factor_level(h, false, true);
+      factor_level(h, std::true_type{}, std::false_type{});
       __syncthreads();
     }
   }
@@ -328,7 +362,7 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(const DevPlan P, const int
         pz -= c * ez[j];
       }
       for (int32_t t = l_start[k], t1 = l_start[k + 1]; t < t1; ++t) {
-        const int32_t j = lcol[t];
+        const int32_t j = lpair[2 * t];
         const double c = cf[t] * lam[j];
         px -= c * ex[j];
         py -= c * ey[j];
@@ -369,15 +403,23 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(const DevPlan P, const int
 
     // ---- factorisation fused with the forward substitution (Newton), or
     //      the forward substitution alone (chord)
-    for (int32_t h = 1; h < H; ++h) {
-      factor_level(h, true, !A.chord);
-      __syncthreads();
+    if (A.chord) {
+      for (int32_t h = 1; h < H; ++h) {
+        factor_level(h, std::false_type{}, std::true_type{});
+        __syncthreads();
+      }
+    } else {
+      for (int32_t h = 1; h < H; ++h) {
+        factor_level(h, std::true_type{}, std::true_type{});
+        __syncthreads();
+      }
     }
     if (singular) { st_code = ILVES_ERR_SINGULAR; break; }
 
     // ---- backward substitution and lambda update
     for (int32_t h = H - 1; h >= 0; --h) {
-      for (int32_t k = lvl_row[h] + tid, k1 = lvl_row[h + 1]; k < k1; k += BLOCK) {
+      const int32_t k0 = lvh[4 * h], k1 = lvh[4 * h + 1];
+      for (int32_t k = k0 + tid; k < k1; k += BLOCK) {
         T acc = y[k];
         for (int32_t q = up_start[k], q1 = up_start[k + 1]; q < q1; ++q) acc -= F[q] * y[ucol[q]];
         const T z = acc * D[k];
@@ -414,6 +456,13 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(const DevPlan P, const int
     A.status[m_idx] = st_code;
     if (A.fallback) A.fallback[m_idx] = fell_back;
   }
+  __syncthreads();  // LDS and next_slot are reused by the next molecule
+  }
+}
+
+__global__ void reset_counters(int32_t* __restrict__ c, int32_t n) {
+  const int i = threadIdx.x;
+  if (i < n) c[i] = 0;
 }
 
 __global__ void copy_free_atoms(const int32_t* __restrict__ idx, int32_t n_free, int32_t S,
@@ -427,7 +476,7 @@ __global__ void copy_free_atoms(const int32_t* __restrict__ idx, int32_t n_free,
   }
 }
 
-using KernelFn = void (*)(DevPlan, const int32_t*, SolveArgs);
+using KernelFn = void (*)(DevPlan, const int32_t*, int32_t, int32_t*, SolveArgs);
 
 template <typename T, typename Idx, int MODE>
 KernelFn pick_block(int block) {
@@ -462,7 +511,10 @@ struct Group {
   int lds_bytes = 0;
   int32_t first = 0;  // into the device molecule-list array
   int32_t count = 0;
+  int32_t grid = 0;   // persistent workgroups
+  int32_t counter = 0;  // index of the group's queue counter
 };
+constexpr int kMaxGroups = 64;
 
 }  // namespace
 
@@ -482,6 +534,8 @@ struct ilves_plan {
   int32_t* d_free = nullptr;
   int32_t n_free = 0;
   int32_t* d_lists = nullptr;          // molecule lists of every group, both precisions
+  int32_t* d_counters = nullptr;       // queue counters of the groups (kMaxGroups per precision)
+  int n_cu = 0;
   std::vector<Group> groups[2];        // [0] FP64, [1] mixed
   int32_t width_first[2] = {0, 0};     // molecule lists by index width (features kernel)
   int32_t width_count[2] = {0, 0};
@@ -496,11 +550,6 @@ struct ilves_plan {
 
 namespace {
 
-int auto_block(int32_t n, int32_t cap) {
-  int b = n <= 64 ? 64 : n <= 256 ? 128 : n <= 1024 ? 256 : n <= 4096 ? 512 : 1024;
-  return std::min(b, cap);
-}
-
 template <typename V>
 size_t push_array(std::vector<unsigned char>& blob, const std::vector<V>& v) {
   size_t off = (blob.size() + 255) & ~static_cast<size_t>(255);
@@ -514,12 +563,57 @@ void append(std::vector<V>& dst, const std::vector<int32_t>& src) {
   for (int32_t x : src) dst.push_back(static_cast<V>(x));
 }
 
+// Appends a molecule's structure block (see struct_layout) to the pool and
+// returns its byte offset.
+template <typename Idx>
+int64_t pack_struct(const ilves::MolPlan& M, std::vector<unsigned char>& pool) {
+  const int32_t n_pl = static_cast<int32_t>(M.plist.size());
+  const Layout Lo = struct_layout(M.n, M.n_levels, M.n_up, M.n_l, n_pl, M.n_upd, static_cast<int>(sizeof(Idx)));
+  const int64_t off = align_to(static_cast<int64_t>(pool.size()), 16);
+  pool.resize(static_cast<size_t>(off + Lo.total), 0);
+  auto put = [&](int64_t sec, int64_t idx, int32_t v) {
+    const Idx x = static_cast<Idx>(v);
+    std::memcpy(pool.data() + off + sec + idx * static_cast<int64_t>(sizeof(Idx)), &x, sizeof(Idx));
+  };
+  for (int32_t k = 0; k <= M.n; ++k) {
+    put(Lo.up_start, k, M.up_start[k]);
+    put(Lo.l_start, k, M.l_start[k]);
+  }
+  for (int32_t q = 0; q < M.n_up; ++q) put(Lo.ucol, q, M.ucol[q]);
+  for (int32_t h = 0; h < M.n_levels; ++h) {
+    put(Lo.lvh, 4 * h + 0, M.lvl_row[h]);
+    put(Lo.lvh, 4 * h + 1, M.lvl_row[h + 1]);
+    put(Lo.lvh, 4 * h + 2, M.pl_start[h]);
+    put(Lo.lvh, 4 * h + 3, M.pl_start[h + 1]);
+  }
+  for (int32_t t = 0; t < M.n_l; ++t) {
+    put(Lo.lpair, 2 * t + 0, M.lcol[t]);
+    put(Lo.lpair, 2 * t + 1, M.ltr[t]);
+  }
+  for (int32_t pi = 0; pi < n_pl; ++pi) {
+    const int32_t q = M.plist[pi];
+    put(Lo.prec, 4 * pi + 0, q);
+    put(Lo.prec, 4 * pi + 1, M.utr[q]);
+    put(Lo.prec, 4 * pi + 2, M.ustart[q]);
+    put(Lo.prec, 4 * pi + 3, M.ustart[q + 1] - M.ustart[q]);
+  }
+  for (int32_t u = 0; u < M.n_upd; ++u) {
+    const int32_t pa = M.upd_a[u], pb = M.upd_b[u];
+    put(Lo.upd, 4 * u + 0, pa);
+    put(Lo.upd, 4 * u + 1, pb);
+    put(Lo.upd, 4 * u + 2, M.ltr[pb - M.n_up]);  // slot (i, m)
+    put(Lo.upd, 4 * u + 3, M.ltr[pa - M.n_up]);  // slot (i, j)
+    put(Lo.updi, u, M.lcol[pa - M.n_up]);        // row i
+  }
+  return off;
+}
+
 // placement of one molecule for value type T: mode and LDS bytes
 template <typename T>
 std::pair<int, int> placement(const ilves::MolPlan& M, bool wide, int64_t lds_limit) {
   if (wide) return {GLOBAL, 0};
-  const size_t sb = align16(2 * static_cast<size_t>(
-      struct_elems(M.n, M.n_levels, M.n_up, M.n_l, M.n_upd, static_cast<int32_t>(M.plist.size()))));
+  const size_t sb = static_cast<size_t>(struct_layout(M.n, M.n_levels, M.n_up, M.n_l,
+                                                      static_cast<int32_t>(M.plist.size()), M.n_upd, 2).total);
   const size_t vb = value_bytes<T>(M.n, M.n_up, M.n_l);
   if (static_cast<int64_t>(sb + vb) <= lds_limit) return {ALL_LDS, static_cast<int>(sb + vb)};
   if (static_cast<int64_t>(sb) <= lds_limit) return {STRUCT_LDS, static_cast<int>(sb)};
@@ -529,8 +623,8 @@ std::pair<int, int> placement(const ilves::MolPlan& M, bool wide, int64_t lds_li
 ilves_status_t build_device_plan(ilves_plan* P) {
   const int32_t nm = static_cast<int32_t>(P->mols.size());
   std::vector<MolDesc> desc(nm);
-  std::vector<uint16_t> ix16;
-  std::vector<int32_t> ix32, coef, ra, rb, cid, atom_gid, inc_ptr, inc;
+  std::vector<unsigned char> pool;
+  std::vector<int32_t> coef, ra, rb, cid, atom_gid, inc_ptr, inc;
   std::vector<double> d2;
   std::vector<char> wide(nm, 0);
   int64_t fill = 0, work = 0, maxlev = 0, sumlev = 0, nslots = 0, natoms = 0, ncon = 0;
@@ -548,22 +642,7 @@ ilves_status_t build_device_plan(ilves_plan* P) {
     const int64_t total = static_cast<int64_t>(M.n_up) + M.n_l;
     wide[i] = (total >= 65535 || M.n >= 65535 || M.n_upd >= 65535) ? 1 : 0;
     D.wide = wide[i];
-    std::vector<int32_t> blockv;
-    blockv.reserve(static_cast<size_t>(struct_elems(M.n, M.n_levels, M.n_up, M.n_l, M.n_upd, D.n_pl)));
-    for (const auto* v : {&M.up_start, &M.l_start, &M.lvl_row, &M.pl_start, &M.ustart, &M.ucol, &M.utr, &M.lcol,
-                          &M.ltr, &M.upd_a, &M.upd_b, &M.plist})
-      blockv.insert(blockv.end(), v->begin(), v->end());
-    if (static_cast<int64_t>(blockv.size()) != struct_elems(M.n, M.n_levels, M.n_up, M.n_l, M.n_upd, D.n_pl))
-      return fail(ILVES_ERR_ARG, "internal: structure block size mismatch");
-    if (wide[i]) {
-      while (ix32.size() % 4) ix32.push_back(0);
-      D.ix_off = static_cast<int32_t>(ix32.size());
-      append(ix32, blockv);
-    } else {
-      while (ix16.size() % 8) ix16.push_back(0);  // 16-byte aligned blocks
-      D.ix_off = static_cast<int32_t>(ix16.size());
-      append(ix16, blockv);
-    }
+    D.ix_off = wide[i] ? pack_struct<int32_t>(M, pool) : pack_struct<uint16_t>(M, pool);
     D.coef_off = static_cast<int32_t>(coef.size());
     coef.insert(coef.end(), M.ucoef.begin(), M.ucoef.end());
     coef.insert(coef.end(), M.lcoef.begin(), M.lcoef.end());
@@ -600,7 +679,9 @@ ilves_status_t build_device_plan(ilves_plan* P) {
   int64_t in_lds = 0, in_ws = 0;
   for (int prec = 0; prec < 2; ++prec) {
     P->groups[prec].clear();
-    struct Key { int mode; bool wide; int block; int bucket; };
+    // launch groups: LDS-resident molecules in bands of LDS size (block
+    // size grows with the band), structure-only and global molecules apart
+    struct Key { int mode; bool wide; int band; };
     std::vector<std::pair<Key, std::vector<int32_t>>> buckets;
     std::vector<int> lds_of(nm, 0);
     for (int32_t i : ord) {
@@ -611,27 +692,25 @@ ilves_status_t build_device_plan(ilves_plan* P) {
       if (prec == 1) {
         if (pl.first == ALL_LDS) ++in_lds; else ++in_ws;
       }
-      const int cap = P->opt.block_threads > 0 ? P->opt.block_threads : 1024;
-      const int block = auto_block(M.n, cap);
-      int bucket = 0;
-      if (pl.second > 0) {
-        size_t lim = 1024;
-        while (static_cast<int>(lim) < pl.second) { lim <<= 1; ++bucket; }
-      }
-      Key key{pl.first, wide[i] != 0, block, bucket};
+      int band = 0;
+      if (pl.first == ALL_LDS) band = pl.second <= 8192 ? 0 : pl.second <= 24576 ? 1 : pl.second <= 65536 ? 2 : 3;
+      else band = M.n <= 4096 ? 3 : 4;
+      Key key{pl.first, wide[i] != 0, band};
       bool found = false;
       for (auto& b : buckets)
-        if (b.first.mode == key.mode && b.first.wide == key.wide && b.first.block == key.block &&
-            b.first.bucket == key.bucket) {
+        if (b.first.mode == key.mode && b.first.wide == key.wide && b.first.band == key.band) {
           b.second.push_back(i);
           found = true;
           break;
         }
       if (!found) buckets.push_back({key, std::vector<int32_t>{i}});
     }
+    if (buckets.size() > static_cast<size_t>(kMaxGroups)) return fail(ILVES_ERR_ARG, "internal: too many launch groups");
+    static const int band_block[5] = {64, 128, 256, 512, 1024};
+    const int cap = P->opt.block_threads > 0 ? P->opt.block_threads : 1024;
     for (auto& b : buckets) {
       Group g;
-      g.block = b.first.block;
+      g.block = std::min(band_block[b.first.band], cap);
       g.mode = b.first.mode;
       g.wide = b.first.wide;
       int mx = 0;
@@ -639,6 +718,8 @@ ilves_status_t build_device_plan(ilves_plan* P) {
       g.lds_bytes = mx;
       g.first = static_cast<int32_t>(lists.size());
       g.count = static_cast<int32_t>(b.second.size());
+      g.counter = prec * kMaxGroups + static_cast<int32_t>(P->groups[prec].size());
+      g.grid = g.count;  // refined from the occupancy once the kernels are known
       lists.insert(lists.end(), b.second.begin(), b.second.end());
       P->groups[prec].push_back(g);
     }
@@ -649,12 +730,10 @@ ilves_status_t build_device_plan(ilves_plan* P) {
       if (wide[i] == wdt) lists.push_back(i);
     P->width_count[wdt] = static_cast<int32_t>(lists.size()) - P->width_first[wdt];
   }
-  if (ix16.empty()) ix16.push_back(0);
-  if (ix32.empty()) ix32.push_back(0);
+  if (pool.empty()) pool.resize(16, 0);
   std::vector<unsigned char> blob;
   const size_t o_desc = push_array(blob, desc);
-  const size_t o_ix16 = push_array(blob, ix16);
-  const size_t o_ix32 = push_array(blob, ix32);
+  const size_t o_pool = push_array(blob, pool);
   const size_t o_coef = push_array(blob, coef);
   const size_t o_ra = push_array(blob, ra);
   const size_t o_rb = push_array(blob, rb);
@@ -671,8 +750,7 @@ ilves_status_t build_device_plan(ilves_plan* P) {
   P->buf_bytes = blob.size();
   unsigned char* b = static_cast<unsigned char*>(P->d_buf);
   P->dp.mol = reinterpret_cast<const MolDesc*>(b + o_desc);
-  P->dp.ix16 = reinterpret_cast<const uint16_t*>(b + o_ix16);
-  P->dp.ix32 = reinterpret_cast<const int32_t*>(b + o_ix32);
+  P->dp.ix = b + o_pool;
   P->dp.coef = reinterpret_cast<const int32_t*>(b + o_coef);
   P->dp.ra = reinterpret_cast<const int32_t*>(b + o_ra);
   P->dp.rb = reinterpret_cast<const int32_t*>(b + o_rb);
@@ -779,6 +857,19 @@ ilves_status_t ilves_plan_create(int32_t n_atoms, int32_t n_constraints, const i
       if (g.lds_bytes > 0)
         HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(pick_kernel(prec == 1, g.mode, g.wide, g.block)),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, g.lds_bytes));
+  // persistent grids: as many workgroups as fit on the device at once
+  HIP_TRY(hipDeviceGetAttribute(&P->n_cu, hipDeviceAttributeMultiprocessorCount, P->device));
+  for (int prec = 0; prec < 2; ++prec)
+    for (Group& g : P->groups[prec]) {
+      int per_cu = 0;
+      HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &per_cu, reinterpret_cast<const void*>(pick_kernel(prec == 1, g.mode, g.wide, g.block)), g.block,
+          static_cast<size_t>(g.lds_bytes)));
+      if (per_cu < 1) return fail(ILVES_ERR_HIP, "a solve kernel cannot be resident on a compute unit");
+      g.grid = std::min<int64_t>(g.count, static_cast<int64_t>(per_cu) * P->n_cu);
+    }
+  HIP_TRY(hipMalloc(&P->d_counters, sizeof(int32_t) * 2 * kMaxGroups));
+  HIP_TRY(hipMemset(P->d_counters, 0, sizeof(int32_t) * 2 * kMaxGroups));
   for (int i = 0; i < kStreams; ++i) {
     HIP_TRY(hipStreamCreateWithFlags(&P->streams[i], hipStreamNonBlocking));
     HIP_TRY(hipEventCreateWithFlags(&P->ev_join[i], hipEventDisableTiming));
@@ -798,6 +889,7 @@ ilves_status_t ilves_plan_destroy(ilves_plan_t P) {
   if (P->d_buf) (void)hipFree(P->d_buf);
   if (P->d_ws) (void)hipFree(P->d_ws);
   if (P->d_free) (void)hipFree(P->d_free);
+  if (P->d_counters) (void)hipFree(P->d_counters);
   if (P->d_mlp) (void)hipFree(P->d_mlp);
   if (P->d_feat) (void)hipFree(P->d_feat);
   if (P->d_w) (void)hipFree(P->d_w);
@@ -886,6 +978,9 @@ ilves_status_t solve_impl(ilves_plan_t P, const double* r, const double* r_u, co
   if (groups.empty()) return ILVES_OK;
   // fork: the groups run concurrently on the plan's streams, joined back
   // into the caller's stream (also valid under graph capture)
+  int32_t* counters = P->d_counters + (precision == ILVES_PREC_MIXED ? kMaxGroups : 0);
+  hipLaunchKernelGGL(reset_counters, dim3(1), dim3(kMaxGroups), 0, stream, counters, kMaxGroups);
+  HIP_TRY(hipGetLastError());
   HIP_TRY(hipEventRecord(P->ev_fork, stream));
   const int ns = std::min<int>(kStreams, static_cast<int>(groups.size()));
   for (int i = 0; i < ns; ++i) HIP_TRY(hipStreamWaitEvent(P->streams[i], P->ev_fork, 0));
@@ -895,9 +990,11 @@ ilves_status_t solve_impl(ilves_plan_t P, const double* r, const double* r_u, co
     hipStream_t s = P->streams[gi % ns];
     DevPlan dp = P->dp;
     const int32_t* list = P->d_lists + g.first;
+    int32_t count = g.count;
+    int32_t* counter = P->d_counters + g.counter;
     SolveArgs a = A;
-    void* args[] = {&dp, &list, &a};
-    HIP_TRY(hipLaunchKernel(reinterpret_cast<const void*>(k), dim3(g.count), dim3(g.block), args,
+    void* args[] = {&dp, &list, &count, &counter, &a};
+    HIP_TRY(hipLaunchKernel(reinterpret_cast<const void*>(k), dim3(g.grid), dim3(g.block), args,
                             static_cast<size_t>(g.lds_bytes), s));
   }
   for (int i = 0; i < ns; ++i) {

@@ -54,14 +54,13 @@ __global__ void __launch_bounds__(256) features_kernel(const DevPlan P, const in
   const int tid = threadIdx.x;
   const MolDesc md = P.mol[mols[blockIdx.x]];
   const int32_t n = md.n, s = md.s, n_up = md.n_up, n_l = md.n_l, H = md.n_levels;
-  const Idx* st = reinterpret_cast<const Idx*>(sizeof(Idx) == 2 ? static_cast<const void*>(P.ix16)
-                                                                 : static_cast<const void*>(P.ix32)) +
-                  md.ix_off;
-  const Idx* up_start = st;
-  const Idx* l_start = up_start + n + 1;
-  const Idx* ustart = l_start + n + 1 + 2 * (H + 1);
-  const Idx* ucol = ustart + n_up + 1;
-  const Idx* lcol = (ucol + 2 * n_up) - n_up;  // indexed by F index t in [n_up, n_up + n_l)
+  const Layout Lo = struct_layout(n, H, n_up, n_l, md.n_pl, md.n_upd, static_cast<int>(sizeof(Idx)));
+  const unsigned char* st = P.ix + md.ix_off;
+  const Idx* up_start = reinterpret_cast<const Idx*>(st + Lo.up_start);
+  const Idx* l_start = reinterpret_cast<const Idx*>(st + Lo.l_start);
+  const Idx* ucol = reinterpret_cast<const Idx*>(st + Lo.ucol);
+  // lower-slot records {column, transpose}, indexed by F index t
+  const Idx* lpair = reinterpret_cast<const Idx*>(st + Lo.lpair) - 2 * static_cast<int64_t>(n_up);
   const int32_t* coef = P.coef + md.coef_off;
   const int32_t* atom_gid = P.atom_gid + md.atom_off;
   const int32_t* ra = P.ra + md.row_off;
@@ -72,7 +71,6 @@ __global__ void __launch_bounds__(256) features_kernel(const DevPlan P, const in
   double* ey = ex + n;
   double* ez = ey + n;
   const int64_t R0 = md.row_off;
-  (void)n_l;
 
   // own quantities
   for (int32_t k = tid; k < n; k += 256) {
@@ -128,7 +126,7 @@ __global__ void __launch_bounds__(256) features_kernel(const DevPlan P, const in
       cnt += 1.0;
     };
     for (int32_t q = up_start[k]; q < up_start[k + 1]; ++q) visit(q, ucol[q]);
-    for (int32_t t = l_start[k]; t < l_start[k + 1]; ++t) visit(t, lcol[t]);
+    for (int32_t t = l_start[k]; t < l_start[k + 1]; ++t) visit(t, lpair[2 * t]);
     float* f = feat + (R0 + k) * N_FEAT;
     f[7] = static_cast<float>(s7);
     f[8] = static_cast<float>(s8);
