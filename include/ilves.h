@@ -72,7 +72,9 @@ typedef struct {
                             lambda_0 read from the lambda argument;
                             ILVES_WARM_MLP: lambda_0 from the loaded network
                             (see ilves_solve_learned)                           */
-  int32_t block_threads; /* threads per workgroup for large molecules; 0 = auto  */
+  int32_t block_threads; /* cap on the threads per workgroup of molecules kept in
+                            LDS (64..1024); 0 = automatic; molecules that do not
+                            fit in LDS always use 512 or 1024                   */
   int32_t lds_limit;     /* bytes of LDS a molecule may use; 0 = auto            */
   int32_t ordering;      /* 0 auto, 1 minimum degree, 2 nested dissection        */
   int32_t reserved;

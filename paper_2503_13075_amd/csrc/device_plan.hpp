@@ -11,8 +11,9 @@ namespace ilves_dev {
 // Placement of a molecule's per-level data:
 //   ALL_LDS:    slot structure and factor values in LDS
 //   STRUCT_LDS: slot structure in LDS, factor values in the workspace
+//   VALUES_LDS: factor values in LDS, slot structure read from global memory
 //   GLOBAL:     both read from global memory (molecules too large for LDS)
-enum { ALL_LDS = 0, STRUCT_LDS = 1, GLOBAL = 2 };
+enum { ALL_LDS = 0, STRUCT_LDS = 1, GLOBAL = 2, VALUES_LDS = 3 };
 
 struct MolDesc {
   int32_t n, s, n_up, n_l, n_upd, n_levels, n_pl;

@@ -161,7 +161,7 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(const DevPlan P, const int
   const Layout Lo = struct_layout(n, H, n_up, n_l, n_pl, n_upd, static_cast<int>(sizeof(Idx)));
   const unsigned char* gst = P.ix + md.ix_off;
   const unsigned char* st;
-  if (MODE == GLOBAL) {
+  if (MODE == GLOBAL || MODE == VALUES_LDS) {
     st = gst;
   } else {
     const int64_t nvec = Lo.total / 16;  // blocks are 16-byte aligned and padded
@@ -195,6 +195,7 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(const DevPlan P, const int
   double* __restrict__ invm = cf + n_up + n_l;
   T* __restrict__ F;
   if (MODE == ALL_LDS) F = reinterpret_cast<T*>(smem + Lo.total);
+  else if (MODE == VALUES_LDS) F = reinterpret_cast<T*>(smem);
   else F = reinterpret_cast<T*>(wsb + ws_vec_bytes(n, s, n_up, n_l));
   T* __restrict__ D = F + n_up + n_l;
   T* __restrict__ y = D + n;
@@ -489,12 +490,24 @@ KernelFn pick_block(int block) {
   }
 }
 
+template <typename T, typename Idx, int MODE>
+KernelFn pick_big(int block) {
+  return block <= 512 ? solve_kernel<T, Idx, MODE, 512> : solve_kernel<T, Idx, MODE, 1024>;
+}
+
+// Block size a kernel is compiled for: every launch uses exactly this.
+int kernel_block(int mode, bool wide, int block) {
+  if (mode == ALL_LDS && !wide) return block <= 64 ? 64 : block <= 128 ? 128 : block <= 256 ? 256 : block <= 512 ? 512 : 1024;
+  return block <= 512 ? 512 : 1024;
+}
+
 template <typename T>
 KernelFn pick_mode(int mode, bool wide, int block) {
-  if (wide) return pick_block<T, int32_t, GLOBAL>(block);
+  if (wide) return mode == VALUES_LDS ? pick_big<T, int32_t, VALUES_LDS>(block) : pick_big<T, int32_t, GLOBAL>(block);
   if (mode == ALL_LDS) return pick_block<T, uint16_t, ALL_LDS>(block);
-  if (mode == STRUCT_LDS) return pick_block<T, uint16_t, STRUCT_LDS>(block);
-  return pick_block<T, uint16_t, GLOBAL>(block);
+  if (mode == STRUCT_LDS) return pick_big<T, uint16_t, STRUCT_LDS>(block);
+  if (mode == VALUES_LDS) return pick_big<T, uint16_t, VALUES_LDS>(block);
+  return pick_big<T, uint16_t, GLOBAL>(block);
 }
 
 KernelFn pick_kernel(bool fp32, int mode, bool wide, int block) {
@@ -609,13 +622,17 @@ int64_t pack_struct(const ilves::MolPlan& M, std::vector<unsigned char>& pool) {
 }
 
 // placement of one molecule for value type T: mode and LDS bytes
+// (prefer everything in LDS; else the factor values, whose accesses form
+// the dependent chain of each level; else the structure; else nothing)
 template <typename T>
 std::pair<int, int> placement(const ilves::MolPlan& M, bool wide, int64_t lds_limit) {
-  if (wide) return {GLOBAL, 0};
+  const size_t vb = value_bytes<T>(M.n, M.n_up, M.n_l);
+  if (wide) return static_cast<int64_t>(vb) <= lds_limit ? std::make_pair(static_cast<int>(VALUES_LDS), static_cast<int>(vb))
+                                                        : std::make_pair(static_cast<int>(GLOBAL), 0);
   const size_t sb = static_cast<size_t>(struct_layout(M.n, M.n_levels, M.n_up, M.n_l,
                                                       static_cast<int32_t>(M.plist.size()), M.n_upd, 2).total);
-  const size_t vb = value_bytes<T>(M.n, M.n_up, M.n_l);
   if (static_cast<int64_t>(sb + vb) <= lds_limit) return {ALL_LDS, static_cast<int>(sb + vb)};
+  if (static_cast<int64_t>(vb) <= lds_limit) return {VALUES_LDS, static_cast<int>(vb)};
   if (static_cast<int64_t>(sb) <= lds_limit) return {STRUCT_LDS, static_cast<int>(sb)};
   return {GLOBAL, 0};
 }
@@ -710,9 +727,10 @@ ilves_status_t build_device_plan(ilves_plan* P) {
     const int cap = P->opt.block_threads > 0 ? P->opt.block_threads : 1024;
     for (auto& b : buckets) {
       Group g;
-      g.block = std::min(band_block[b.first.band], cap);
       g.mode = b.first.mode;
       g.wide = b.first.wide;
+      // large molecules run with 512 or 1024 threads whatever the cap
+      g.block = kernel_block(g.mode, g.wide, std::min(band_block[b.first.band], cap));
       int mx = 0;
       for (int32_t i : b.second) mx = std::max(mx, lds_of[i]);
       g.lds_bytes = mx;

