@@ -60,6 +60,21 @@ def algorithmic_bytes(sm, plan_stats):
     return 80 * s + 24 * n + 4 * nnz_l + 8 * n
 
 
+def measured_traffic(workload, variant):
+    """HBM bytes per solve from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE runs, if they were taken from the current kernel sources
+    (otherwise None)."""
+    path = os.path.join(ROOT, "profiles", f"solve_kernel_{workload}_traffic.json")
+    if variant != "mixed" or not os.path.exists(path):
+        return None
+    from paper_2503_13075_amd.build import kernel_source_hash
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    return rec["traffic_bytes_per_solve"]
+
+
 def cpu_baseline(sm, ru, budget_s=20.0):
     """The CPU oracle on a bounded sample of the same workload's molecules."""
     from oracle import newton_dense as O
@@ -233,6 +248,7 @@ def main():
     head = results[head_name]
     abytes = algorithmic_bytes(sm, st)
     achieved = abytes / (head["ms_per_step"] / 1e3) / 1e9
+    traffic = measured_traffic(args.workload, head_name)
     variants = {k: {"value": v["constraints_per_s"], "ms_per_step": v["ms_per_step"], "all_ok": v["all_ok"],
                     "newton_iters_mean": v["iters_mean"], "newton_iters_max": v["iters_max"],
                     "fallback_rate": v["fallback_rate"] if k == "learned" else None,
@@ -261,7 +277,7 @@ def main():
         "all_ok": head["all_ok"],
         "max_rel_violation_last": head["max_rel_violation_last"],
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "algorithmic_bytes_per_step": abytes, "kernel": "solve_kernel (all launch groups of one solve)"},
     }
     if not args.no_cpu_baseline:

@@ -25,6 +25,19 @@ FLAGS = [
 ]
 
 
+def kernel_source_hash() -> str:
+    """First 16 hex digits of the sha256 of the library sources (names and
+    contents, sorted): identifies the kernels a profile was taken from."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(CSRC, "*"))):
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
 def build(verbose: bool = False) -> str:
     srcs = [os.path.join(CSRC, s) for s in SOURCES]
     tmp = LIB + ".tmp"
