@@ -60,10 +60,10 @@ def algorithmic_bytes(sm, plan_stats):
     return 80 * s + 24 * n + 4 * nnz_l + 8 * n
 
 
-def measured_traffic(workload, variant):
+def measured_traffic(workload, variant, tuning):
     """HBM bytes per solve from the committed rocprofv3 FETCH_SIZE /
-    WRITE_SIZE runs, if they were taken from the current kernel sources
-    (otherwise None)."""
+    WRITE_SIZE runs, if they were taken from the current kernel sources with
+    the same launch tuning (otherwise None)."""
     path = os.path.join(ROOT, "profiles", f"solve_kernel_{workload}_traffic.json")
     if variant != "mixed" or not os.path.exists(path):
         return None
@@ -71,6 +71,10 @@ def measured_traffic(workload, variant):
     with open(path) as f:
         rec = json.load(f)
     if rec.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    t = rec.get("tuning")
+    if t is None or tuning is None or t["band_block"] != list(tuning["band_block"]) or \
+            t["lds_limit"] != tuning["lds_limit"]:
         return None
     return rec["traffic_bytes_per_solve"]
 
@@ -118,6 +122,9 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--variants", default="fp64,mixed,learned", help="comma list of fp64,mixed,learned")
     ap.add_argument("--eager", action="store_true", help="launch every step instead of replaying HIP graphs")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default launch tuning")
+    ap.add_argument("--tuning", default=None,
+                    help='apply this launch tuning instead of autotuning, JSON: {"band_block": [5 ints], "lds_limit": n}')
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="MiB of a plain device copy run once before timing (counter calibration)")
     args = ap.parse_args()
@@ -228,10 +235,32 @@ def main():
     if "learned" in wanted:
         params, norm, meta = WS.load(weights)
         plan.load_mlp(params, norm)
+    tunings = {}
+
+    def tune(prec):
+        """Autotunes the launch of this precision once (untimed)."""
+        if args.tuning or args.no_autotune:
+            t = json.loads(args.tuning) if args.tuning else {"band_block": [64, 128, 256, 512, 1024], "lds_limit": 0}
+            plan.tune(band_block=t["band_block"], lds_limit=t["lds_limit"])
+            return {"band_block": t["band_block"], "lds_limit": t["lds_limit"], "autotuned": False}
+        if prec in tunings:
+            plan.tune(band_block=tunings[prec]["band_block"], lds_limit=tunings[prec]["lds_limit"])
+            return tunings[prec]
+        from paper_2503_13075_amd import autotune as AT
+        it = torch.zeros(nm, dtype=torch.int32, device=dev)
+        stt = torch.zeros(nm, dtype=torch.int32, device=dev)
+        t = AT.autotune(plan, lambda: plan.solve(r, pool[0], mass, 1e-12, r_out, lam, it, stt, precision=prec),
+                        reps=10)
+        log(f"autotune precision {prec}: {t}")
+        tunings[prec] = t
+        return t
+
     for name, prec in (("fp64", L.PREC_FP64), ("mixed", L.PREC_MIXED), ("learned", L.PREC_MIXED)):
         if name not in wanted:
             continue
+        tuning = tune(prec)
         res = run(prec, args.steps, args.warmup, learned=(name == "learned"))
+        res["tuning"] = tuning
         res["max_rel_violation_last"] = check_last(res)
         ms = res["gpu_ms"] / args.steps
         res["ms_per_step"] = ms
@@ -248,11 +277,12 @@ def main():
     head = results[head_name]
     abytes = algorithmic_bytes(sm, st)
     achieved = abytes / (head["ms_per_step"] / 1e3) / 1e9
-    traffic = measured_traffic(args.workload, head_name)
+    traffic = measured_traffic(args.workload, head_name, head["tuning"])
     variants = {k: {"value": v["constraints_per_s"], "ms_per_step": v["ms_per_step"], "all_ok": v["all_ok"],
                     "newton_iters_mean": v["iters_mean"], "newton_iters_max": v["iters_max"],
                     "fallback_rate": v["fallback_rate"] if k == "learned" else None,
-                    "max_rel_violation_last": v["max_rel_violation_last"]} for k, v in results.items()}
+                    "max_rel_violation_last": v["max_rel_violation_last"],
+                    "tuning": v["tuning"]} for k, v in results.items()}
     out = {
         "metric": "constraints solved/s at <=1e-12 rel violation",
         "value": head["constraints_per_s"],

@@ -126,6 +126,32 @@ ilves_status_t ilves_plan_molecules(ilves_plan_t plan, int32_t* n_con, int32_t* 
                                     int32_t* n_levels, int32_t* first_constraint);
 
 /*
+ * Launch tuning of a plan (a performance knob; results agree to rounding).
+ * band_block[b] is the threads per workgroup of launch band b.  Molecules
+ * held wholly in LDS fall in bands 0..3 by their LDS size (<= 8 KB, <= 24 KB,
+ * <= 64 KB, larger); molecules with only part (or none) of their data in LDS
+ * fall in band 3 up to 4096 constraints and in band 4 above.  The partly-LDS
+ * kernels exist with 512 and 1024 threads only; smaller requests round up to
+ * 512.  lds_limit caps the LDS one molecule may use (0 = all of it); lowering
+ * it moves molecules out of LDS.
+ */
+typedef struct {
+  int32_t band_block[5];   /* 64, 128, 256, 512 or 1024 */
+  int32_t lds_limit;       /* bytes, 0 = maximum */
+  int32_t reserved[2];
+} ilves_tuning_t;
+
+/* Current tuning of the plan. */
+ilves_status_t ilves_plan_get_tuning(ilves_plan_t plan, ilves_tuning_t* t);
+
+/* Re-derives the placement and launch groups of the plan from a tuning
+ * (the ordering and symbolic factorisation are kept).  Synchronises the
+ * device; no solve on this plan may be in flight, and HIP graphs that
+ * captured solves of this plan before the call hold freed addresses and must
+ * be captured again.  Errors: ILVES_ERR_ARG, ILVES_ERR_HIP, ILVES_ERR_NOMEM. */
+ilves_status_t ilves_plan_tune(ilves_plan_t plan, const ilves_tuning_t* t);
+
+/*
  * One constraint solve (the hot path), asynchronous on hip_stream.
  *   r, r_u     device double [3][n_atoms]  old and unconstrained positions (nm)
  *   mass       device double [n_atoms]     masses (amu, > 0)

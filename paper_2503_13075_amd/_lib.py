@@ -37,6 +37,10 @@ class Options(ctypes.Structure):
                 ("ordering", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
+class Tuning(ctypes.Structure):
+    _fields_ = [("band_block", ctypes.c_int32 * 5), ("lds_limit", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
+
+
 _lib = None
 _P = ctypes.c_void_p
 _I32P = ctypes.POINTER(ctypes.c_int32)
@@ -111,6 +115,10 @@ def lib() -> ctypes.CDLL:
     L.ilves_mlp_adam_f32.argtypes = [_P, _P, _P, _P, ctypes.c_int32, ctypes.c_float, ctypes.c_float,
                                      ctypes.c_float, ctypes.c_float, ctypes.c_int32, _P]
     L.ilves_mlp_adam_f32.restype = ctypes.c_int
+    L.ilves_plan_get_tuning.argtypes = [_P, ctypes.POINTER(Tuning)]
+    L.ilves_plan_get_tuning.restype = ctypes.c_int
+    L.ilves_plan_tune.argtypes = [_P, ctypes.POINTER(Tuning)]
+    L.ilves_plan_tune.restype = ctypes.c_int
     _lib = L
     return L
 
@@ -324,6 +332,26 @@ def _plan_solve_learned(self, r, r_u, mass, tol, r_out, lam, iters, status, fall
                                       _dev(status, torch.int32), fb, _stream(stream)))
 
 
+def _plan_get_tuning(self) -> dict:
+    t = Tuning()
+    check(self._L.ilves_plan_get_tuning(self._h, ctypes.byref(t)))
+    return {"band_block": list(t.band_block), "lds_limit": int(t.lds_limit)}
+
+
+def _plan_tune(self, band_block=None, lds_limit=None):
+    """Re-derives placement and launch groups (block size per LDS band, LDS
+    limit per molecule).  Synchronises the device; graphs captured before
+    must be captured again."""
+    cur = self.get_tuning()
+    t = Tuning()
+    for i, b in enumerate(cur["band_block"] if band_block is None else band_block):
+        t.band_block[i] = int(b)
+    t.lds_limit = int(cur["lds_limit"] if lds_limit is None else lds_limit)
+    check(self._L.ilves_plan_tune(self._h, ctypes.byref(t)))
+
+
+Plan.get_tuning = _plan_get_tuning
+Plan.tune = _plan_tune
 Plan.load_mlp = _plan_load_mlp
 Plan.row_constraints = _plan_row_constraints
 Plan.features = _plan_features

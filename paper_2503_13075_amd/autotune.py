@@ -1,0 +1,119 @@
+"""Launch autotuner of the batched solve.
+
+The plan's launch groups have two kinds of knobs that change speed but not
+the arithmetic: the threads per workgroup of each LDS band and the LDS a
+molecule may use (which moves molecules between the all-in-LDS kernel and the
+partly-in-LDS ones).  ``autotune`` times the solve of a representative input
+for each candidate by coordinate descent over the bands, then over the LDS
+limit, keeps the fastest and records it in a JSON cache keyed by the device,
+the plan's shape and the solve options, so that later runs on the same
+workload apply it without timing again.
+"""
+from __future__ import annotations
+
+import hashlib
+import json
+import os
+
+from . import _lib as L
+
+BAND_CANDIDATES = [[64, 128, 256, 512, 1024]] * 3 + [[512, 1024]] * 2
+LDS_CANDIDATES = [0, 96 * 1024, 64 * 1024, 32 * 1024]
+DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "ilves_tuning.json")
+
+
+def plan_key(plan: L.Plan, precision: int, variant: int, warm: str = "zero") -> str:
+    import torch
+    st = plan.stats()
+    shape = [st[k] for k in ("molecules", "constraints", "atoms", "factor_entries", "updates", "sum_levels")]
+    dev = torch.cuda.get_device_name(torch.cuda.current_device())
+    text = json.dumps([dev, shape, int(precision), int(variant), warm])
+    return hashlib.sha256(text.encode()).hexdigest()[:20]
+
+
+def _timer(run, reps):
+    import torch
+    run()
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    best = float("inf")
+    for _ in range(2):
+        a.record()
+        for _ in range(reps):
+            run()
+        b.record()
+        b.synchronize()
+        best = min(best, a.elapsed_time(b) / reps)
+    return best
+
+
+def autotune(plan: L.Plan, run, reps: int = 10, log=None) -> dict:
+    """Coordinate descent over the plan's tuning.  ``run()`` enqueues one
+    solve on torch's current stream with the plan; it is timed ``reps`` times
+    per candidate (best of two rounds).  Leaves the plan on the fastest
+    tuning and returns it with the default and tuned times (ms)."""
+    cur = plan.get_tuning()
+    cur = {"band_block": list(cur["band_block"]), "lds_limit": 0}
+    plan.tune(**cur)
+    base = best = _timer(run, reps)
+    if log:
+        log(f"autotune: default {cur} {base:.4f} ms")
+    for band, cands in enumerate(BAND_CANDIDATES):
+        for c in cands:
+            if c == cur["band_block"][band]:
+                continue
+            trial = {"band_block": list(cur["band_block"]), "lds_limit": cur["lds_limit"]}
+            trial["band_block"][band] = c
+            plan.tune(**trial)
+            t = _timer(run, reps)
+            if log:
+                log(f"autotune: band {band} block {c}: {t:.4f} ms")
+            if t < best * 0.99:
+                best, cur = t, trial
+    for lim in LDS_CANDIDATES:
+        if lim == cur["lds_limit"]:
+            continue
+        trial = {"band_block": list(cur["band_block"]), "lds_limit": lim}
+        plan.tune(**trial)
+        t = _timer(run, reps)
+        if log:
+            log(f"autotune: lds_limit {lim}: {t:.4f} ms")
+        if t < best * 0.99:
+            best, cur = t, trial
+    plan.tune(**cur)
+    return {"band_block": cur["band_block"], "lds_limit": cur["lds_limit"], "ms_default": base, "ms_tuned": best}
+
+
+def load_cached(key: str, path: str = DEFAULT_CACHE):
+    try:
+        with open(path) as f:
+            return json.load(f).get(key)
+    except (OSError, ValueError):
+        return None
+
+
+def store(key: str, tuning: dict, path: str = DEFAULT_CACHE) -> None:
+    try:
+        with open(path) as f:
+            db = json.load(f)
+    except (OSError, ValueError):
+        db = {}
+    db[key] = tuning
+    os.makedirs(os.path.dirname(path) or ".", exist_ok=True)
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(db, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def tuned(plan: L.Plan, run, key: str, path: str = DEFAULT_CACHE, reps: int = 10, log=None) -> dict:
+    """Applies the cached tuning for ``key`` or runs ``autotune`` and caches
+    its result."""
+    hit = load_cached(key, path)
+    if hit is not None:
+        plan.tune(band_block=hit["band_block"], lds_limit=hit["lds_limit"])
+        return dict(hit, cached=True)
+    res = autotune(plan, run, reps=reps, log=log)
+    store(key, res, path)
+    return dict(res, cached=False)

@@ -549,6 +549,7 @@ struct ilves_plan {
   int32_t* d_lists = nullptr;          // molecule lists of every group, both precisions
   int32_t* d_counters = nullptr;       // queue counters of the groups (kMaxGroups per precision)
   int n_cu = 0;
+  int32_t band_block[5] = {64, 128, 256, 512, 1024};  // block size per LDS band (tunable)
   std::vector<Group> groups[2];        // [0] FP64, [1] mixed
   int32_t width_first[2] = {0, 0};     // molecule lists by index width (features kernel)
   int32_t width_count[2] = {0, 0};
@@ -723,7 +724,7 @@ ilves_status_t build_device_plan(ilves_plan* P) {
       if (!found) buckets.push_back({key, std::vector<int32_t>{i}});
     }
     if (buckets.size() > static_cast<size_t>(kMaxGroups)) return fail(ILVES_ERR_ARG, "internal: too many launch groups");
-    static const int band_block[5] = {64, 128, 256, 512, 1024};
+    const int32_t* band_block = P->band_block;
     const int cap = P->opt.block_threads > 0 ? P->opt.block_threads : 1024;
     for (auto& b : buckets) {
       Group g;
@@ -797,6 +798,31 @@ ilves_status_t build_device_plan(ilves_plan* P) {
   return ILVES_OK;
 }
 
+// Kernel attributes and persistent grid sizes of the launch groups.
+ilves_status_t finalize_groups(ilves_plan* P) {
+  for (int prec = 0; prec < 2; ++prec)
+    for (Group& g : P->groups[prec]) {
+      const void* k = reinterpret_cast<const void*>(pick_kernel(prec == 1, g.mode, g.wide, g.block));
+      // the attribute is per kernel and process-wide: always raise it to the
+      // largest size any plan may use, never lower it
+      if (g.lds_bytes > 0) HIP_TRY(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsMax));
+      int per_cu = 0;
+      HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, g.block, static_cast<size_t>(g.lds_bytes)));
+      if (per_cu < 1) return fail(ILVES_ERR_HIP, "a solve kernel cannot be resident on a compute unit");
+      g.grid = static_cast<int32_t>(std::min<int64_t>(g.count, static_cast<int64_t>(per_cu) * P->n_cu));
+    }
+  return ILVES_OK;
+}
+
+void release_device_plan(ilves_plan* P) {
+  if (P->d_buf) (void)hipFree(P->d_buf);
+  if (P->d_ws) (void)hipFree(P->d_ws);
+  P->d_buf = nullptr;
+  P->d_ws = nullptr;
+  P->dp = DevPlan{};
+  P->d_lists = nullptr;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -862,30 +888,16 @@ ilves_status_t ilves_plan_create(int32_t n_atoms, int32_t n_constraints, const i
   } catch (const std::bad_alloc&) {
     return fail(ILVES_ERR_NOMEM, "host allocation failed while planning");
   }
+  HIP_TRY(hipDeviceGetAttribute(&P->n_cu, hipDeviceAttributeMultiprocessorCount, P->device));
   ilves_status_t st = build_device_plan(P.get());
+  if (st != ILVES_OK) return st;
+  st = finalize_groups(P.get());
   if (st != ILVES_OK) return st;
   P->n_free = static_cast<int32_t>(free_atoms.size());
   if (P->n_free > 0) {
     HIP_TRY(hipMalloc(&P->d_free, free_atoms.size() * sizeof(int32_t)));
     HIP_TRY(hipMemcpy(P->d_free, free_atoms.data(), free_atoms.size() * sizeof(int32_t), hipMemcpyHostToDevice));
   }
-  // allow every kernel this plan launches its dynamic LDS size
-  for (int prec = 0; prec < 2; ++prec)
-    for (const Group& g : P->groups[prec])
-      if (g.lds_bytes > 0)
-        HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(pick_kernel(prec == 1, g.mode, g.wide, g.block)),
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, g.lds_bytes));
-  // persistent grids: as many workgroups as fit on the device at once
-  HIP_TRY(hipDeviceGetAttribute(&P->n_cu, hipDeviceAttributeMultiprocessorCount, P->device));
-  for (int prec = 0; prec < 2; ++prec)
-    for (Group& g : P->groups[prec]) {
-      int per_cu = 0;
-      HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-          &per_cu, reinterpret_cast<const void*>(pick_kernel(prec == 1, g.mode, g.wide, g.block)), g.block,
-          static_cast<size_t>(g.lds_bytes)));
-      if (per_cu < 1) return fail(ILVES_ERR_HIP, "a solve kernel cannot be resident on a compute unit");
-      g.grid = std::min<int64_t>(g.count, static_cast<int64_t>(per_cu) * P->n_cu);
-    }
   HIP_TRY(hipMalloc(&P->d_counters, sizeof(int32_t) * 2 * kMaxGroups));
   HIP_TRY(hipMemset(P->d_counters, 0, sizeof(int32_t) * 2 * kMaxGroups));
   for (int i = 0; i < kStreams; ++i) {
@@ -904,8 +916,7 @@ ilves_status_t ilves_plan_destroy(ilves_plan_t P) {
     if (P->ev_join[i]) (void)hipEventDestroy(P->ev_join[i]);
   }
   if (P->ev_fork) (void)hipEventDestroy(P->ev_fork);
-  if (P->d_buf) (void)hipFree(P->d_buf);
-  if (P->d_ws) (void)hipFree(P->d_ws);
+  release_device_plan(P);
   if (P->d_free) (void)hipFree(P->d_free);
   if (P->d_counters) (void)hipFree(P->d_counters);
   if (P->d_mlp) (void)hipFree(P->d_mlp);
@@ -913,6 +924,31 @@ ilves_status_t ilves_plan_destroy(ilves_plan_t P) {
   if (P->d_w) (void)hipFree(P->d_w);
   delete P;
   return ILVES_OK;
+}
+
+ilves_status_t ilves_plan_get_tuning(ilves_plan_t P, ilves_tuning_t* t) {
+  if (!P || !t) return fail(ILVES_ERR_ARG, "null argument");
+  std::memset(t, 0, sizeof(*t));
+  for (int b = 0; b < 5; ++b) t->band_block[b] = P->band_block[b];
+  t->lds_limit = P->opt.lds_limit;
+  return ILVES_OK;
+}
+
+ilves_status_t ilves_plan_tune(ilves_plan_t P, const ilves_tuning_t* t) {
+  if (!P || !t) return fail(ILVES_ERR_ARG, "null argument");
+  for (int b = 0; b < 5; ++b) {
+    const int v = t->band_block[b];
+    if (v != 64 && v != 128 && v != 256 && v != 512 && v != 1024)
+      return fail(ILVES_ERR_ARG, "band block sizes must be 64, 128, 256, 512 or 1024");
+  }
+  if (t->lds_limit < 0) return fail(ILVES_ERR_ARG, "lds_limit must be >= 0");
+  HIP_TRY(hipDeviceSynchronize());
+  for (int b = 0; b < 5; ++b) P->band_block[b] = t->band_block[b];
+  P->opt.lds_limit = (t->lds_limit <= 0 || t->lds_limit > kLdsMax) ? kLdsMax : t->lds_limit;
+  release_device_plan(P);
+  ilves_status_t st = build_device_plan(P);
+  if (st != ILVES_OK) return st;
+  return finalize_groups(P);
 }
 
 int32_t ilves_plan_num_molecules(ilves_plan_t P) { return P ? static_cast<int32_t>(P->mols.size()) : -1; }

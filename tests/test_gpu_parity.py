@@ -121,6 +121,34 @@ def test_placements_and_lane_mappings_agree(batch_case):
         assert np.max(np.abs(a["lam"] - other["lam"])) <= 1e-10 * scale
 
 
+def test_retuned_plan_agrees(batch_case):
+    """Re-tuning a plan (block size per band, LDS limit) moves molecules
+    between kernels and lane mappings; results stay at the oracle's bar and
+    agree with the untuned plan to rounding.  Bad tunings are rejected."""
+    sm, ru, ref = batch_case
+    plan = L.Plan(sm.n_atoms, sm.pairs, sm.d)
+    base = solve_once(sm, ru, TOL, L.PREC_MIXED, plan=plan)
+    assert plan.get_tuning()["band_block"] == [64, 128, 256, 512, 1024]
+    scale = np.max(np.abs(base["lam"]))
+    for bb, lim in (([1024, 1024, 1024, 1024, 1024], 0), ([128, 64, 512, 512, 512], 0),
+                    ([256, 256, 256, 512, 1024], 4096), ([64, 128, 256, 512, 1024], 1)):
+        plan.tune(band_block=bb, lds_limit=lim)
+        t = plan.get_tuning()
+        assert t["band_block"] == bb
+        out = solve_once(sm, ru, TOL, L.PREC_MIXED, plan=plan)
+        _check(sm, ru, out, ref, f"batch16/tuned {bb} {lim}")
+        assert np.max(np.abs(base["r_out"] - out["r_out"])) <= 1e-13
+        assert np.max(np.abs(base["lam"] - out["lam"])) <= 1e-10 * scale
+    assert plan.stats()["mol_workspace"] == plan.n_molecules      # lds_limit 1: nothing in LDS
+    for bad in (dict(band_block=[32, 128, 256, 512, 1024]), dict(band_block=[64, 128, 256, 512, 100]),
+                dict(lds_limit=-1)):
+        with pytest.raises(L.IlvesError) as e:
+            plan.tune(**bad)
+        assert e.value.code == L.ERR_ARG
+    out = solve_once(sm, ru, TOL, L.PREC_MIXED, plan=plan)        # a rejected tuning leaves the plan usable
+    _check(sm, ru, out, ref, "batch16/after rejected tuning")
+
+
 def test_deterministic_repeat(batch_case):
     sm, ru, _ = batch_case
     plan = L.Plan(sm.n_atoms, sm.pairs, sm.d)
