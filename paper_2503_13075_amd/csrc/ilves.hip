@@ -89,8 +89,8 @@ struct SolveArgs {
   int32_t chord;     // 0: Newton, 1: chord
 };
 
-// FP64 workspace of a molecule: e, u (3n each), lambda, C_kk (n each), the
-// couplings of every off-diagonal slot, 1/m (s + 1)
+// FP64 workspace of a molecule: per row {e, lambda} (4n), u (3n), C_kk (n),
+// the couplings of every off-diagonal slot, 1/m (s + 1)
 __host__ __device__ inline size_t ws_vec_bytes(int32_t n, int32_t s, int32_t n_up, int32_t n_l) {
   return align16(8 * (8 * static_cast<size_t>(n) + n_up + n_l + s + 1));
 }
@@ -126,6 +126,79 @@ __device__ inline void ld4(const int32_t* p, int32_t& a, int32_t& b, int32_t& c,
   d = v.w;
 }
 
+// Values that are the same in every lane (read from LDS or from a
+// wave-uniform address) made explicit to the compiler: they move to scalar
+// registers, so indexing, loop bounds and branches on them run on the scalar
+// unit and free vector registers (occupancy).
+__device__ __forceinline__ int32_t uni(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ int64_t uni(int64_t v) {
+  const uint64_t u = static_cast<uint64_t>(v);
+  const uint32_t lo = static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<int32_t>(u)));
+  const uint32_t hi = static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<int32_t>(u >> 32)));
+  return static_cast<int64_t>((static_cast<uint64_t>(hi) << 32) | lo);
+}
+__device__ __forceinline__ double uni(double v) {
+  return __longlong_as_double(static_cast<long long>(uni(static_cast<int64_t>(__double_as_longlong(v)))));
+}
+__device__ __forceinline__ MolDesc uni(const MolDesc& m) {
+  MolDesc r;
+  r.n = uni(m.n);
+  r.s = uni(m.s);
+  r.n_up = uni(m.n_up);
+  r.n_l = uni(m.n_l);
+  r.n_upd = uni(m.n_upd);
+  r.n_levels = uni(m.n_levels);
+  r.n_pl = uni(m.n_pl);
+  r.wide = uni(m.wide);
+  r.ix_off = uni(m.ix_off);
+  r.coef_off = uni(m.coef_off);
+  r.row_off = uni(m.row_off);
+  r.atom_off = uni(m.atom_off);
+  r.incp_off = uni(m.incp_off);
+  r.inc_off = uni(m.inc_off);
+  r.ws_off = uni(m.ws_off);
+  return r;
+}
+
+// per-row record of the workspace: old bond vector and lambda, read with
+// two 16-byte loads
+struct Rec {
+  double x, y, z, l;
+};
+__device__ __forceinline__ Rec ld_rec(const double* p) {
+  const double2 a = *reinterpret_cast<const double2*>(p);
+  const double2 b = *reinterpret_cast<const double2*>(p + 2);
+  return Rec{a.x, a.y, b.x, b.y};
+}
+__device__ __forceinline__ void st_rec(double* p, double x, double y, double z, double l) {
+  *reinterpret_cast<double2*>(p) = make_double2(x, y);
+  *reinterpret_cast<double2*>(p + 2) = make_double2(z, l);
+}
+// entries gathered per batch: row neighbours (global memory, FP64),
+// lower / upper entries of the factor, factor updates
+constexpr int kBatchN = 2;
+constexpr int kBatch = 2;
+constexpr int kBatchU = 1;
+// 1/a from the hardware reciprocal refined by Newton steps (one in FP32,
+// two in FP64): a few dependent operations instead of a full division; the
+// result is within an ulp or two, which the factorisation does not notice
+// (Newton on the constraints converges the same with a slightly perturbed
+// Jacobian).
+__device__ __forceinline__ float recip(float a) {
+  const float r = __builtin_amdgcn_rcpf(a);
+  return __builtin_fmaf(__builtin_fmaf(-a, r, 1.0f), r, r);
+}
+__device__ __forceinline__ double recip(double a) {
+  double r = __builtin_amdgcn_rcp(a);
+  r = __builtin_fma(__builtin_fma(-a, r, 1.0), r, r);
+  return __builtin_fma(__builtin_fma(-a, r, 1.0), r, r);
+}
+
+// integer min / max by value (no references to temporaries, which would
+// keep small arrays out of registers)
+__device__ __forceinline__ int32_t imin(int32_t a, int32_t b) { return a < b ? a : b; }
+__device__ __forceinline__ int32_t imax(int32_t a, int32_t b) { return a > b ? a : b; }
+
 template <typename T> __device__ inline T pivot_eps();
 template <> __device__ inline double pivot_eps<double>() { return 1e-13; }
 template <> __device__ inline float pivot_eps<float>() { return 1e-6f; }
@@ -149,10 +222,10 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(const DevPlan P, const int
   for (;;) {
   if (tid == 0) next_slot = atomicAdd(counter, 1);
   __syncthreads();
-  const int32_t slot = next_slot;
+  const int32_t slot = uni(next_slot);
   if (slot >= count) break;
-  const int32_t m_idx = mols[slot];
-  const MolDesc md = P.mol[m_idx];
+  const int32_t m_idx = uni(mols[slot]);
+  const MolDesc md = uni(P.mol[m_idx]);
   const int32_t n = md.n, s = md.s, n_up = md.n_up, n_l = md.n_l, n_upd = md.n_upd, H = md.n_levels;
   const int32_t n_pl = md.n_pl;
   const int32_t S = A.n_atoms;
@@ -183,14 +256,11 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(const DevPlan P, const int
 
   // ---- workspace and values
   unsigned char* wsb = A.ws + md.ws_off;
-  double* __restrict__ ex = reinterpret_cast<double*>(wsb);
-  double* __restrict__ ey = ex + n;
-  double* __restrict__ ez = ey + n;
-  double* __restrict__ u_x = ez + n;
+  double* __restrict__ er = reinterpret_cast<double*>(wsb);  // per row {e_x, e_y, e_z, lambda}
+  double* __restrict__ u_x = er + 4 * static_cast<int64_t>(n);
   double* __restrict__ u_y = u_x + n;
   double* __restrict__ u_z = u_y + n;
-  double* __restrict__ lam = u_z + n;
-  double* __restrict__ cd = lam + n;
+  double* __restrict__ cd = u_z + n;
   double* __restrict__ cf = cd + n;
   double* __restrict__ invm = cf + n_up + n_l;
   T* __restrict__ F;
@@ -223,15 +293,13 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(const DevPlan P, const int
   double v0 = 0.0;  // max relative violation at lambda = 0 (learned start fallback test)
   for (int32_t k = tid; k < n; k += BLOCK) {
     const int32_t ga = atom_gid[ra[k]], gb = atom_gid[rb[k]];
-    ex[k] = rx[ga] - rx[gb];
-    ey[k] = rx[S + ga] - rx[S + gb];
-    ez[k] = rx[2 * S + ga] - rx[2 * S + gb];
     const double a0 = ux[ga] - ux[gb], a1 = ux[S + ga] - ux[S + gb], a2 = ux[2 * S + ga] - ux[2 * S + gb];
+    st_rec(er + 4 * k, rx[ga] - rx[gb], rx[S + ga] - rx[S + gb], rx[2 * S + ga] - rx[2 * S + gb],
+           A.warm ? A.lambda[cid[k]] : 0.0);
     u_x[k] = a0;
     u_y[k] = a1;
     u_z[k] = a2;
     v0 = fmax(v0, fabs(a0 * a0 + a1 * a1 + a2 * a2 - d2[k]) / (2.0 * d2[k]));
-    lam[k] = A.warm ? A.lambda[cid[k]] : 0.0;
   }
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {
@@ -260,38 +328,73 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(const DevPlan P, const int
     gr = fmax(gr, red[w]);
     rel_zero = fmax(rel_zero, red0[w]);
   }
+  gr = uni(gr);
+  rel_zero = uni(rel_zero);
   const double delta = 1.7320508075688772 * gr * 0x1.0p-52;
   const double delta2 = 0.5 * delta * delta;
   __syncthreads();
 
-  // row k of A(x, r), x having bond vector (px, py, pz); level-0 rows have
-  // no lower entries, so their factorisation is just the inverted pivot
-  const int32_t level1 = static_cast<int32_t>(lvh[1]);  // end row of level 0
-  auto build_row = [&](int32_t k, double px, double py, double pz) {
-    const T akk = static_cast<T>(cd[k] * (px * ex[k] + py * ey[k] + pz * ez[k]));
+  const int32_t level1 = uni(static_cast<int32_t>(lvh[1]));  // end row of level 0
+  // diagonal of row k from the bond-vector product: level-0 rows have no
+  // lower entries, so their factorisation is just the inverted pivot
+  auto set_diag = [&](int32_t k, T akk) {
     if (k < level1) {
       if (!(fabs(akk) > T(0))) singular = 1;
-      D[k] = T(1) / akk;
+      D[k] = recip(akk);
     } else {
       D[k] = akk;
     }
-    for (int32_t q = up_start[k], q1 = up_start[k + 1]; q < q1; ++q) {
-      const int32_t j = ucol[q];
-      F[q] = static_cast<T>(cf[q] * (px * ex[j] + py * ey[j] + pz * ez[j]));
+  };
+  // the off-diagonal slots of a row, upper ones then lower ones: entry idx
+  // -> slot and column
+  auto slot_of = [&](int32_t idx, int32_t q0, int32_t nq, int32_t t0, int32_t& sl, int32_t& j) {
+    if (idx < nq) {
+      sl = q0 + idx;
+      j = ucol[sl];
+    } else {
+      sl = t0 + (idx - nq);
+      j = lpair[2 * sl];
     }
-    for (int32_t t = l_start[k], t1 = l_start[k + 1]; t < t1; ++t) {
-      const int32_t j = lpair[2 * t];
-      F[t] = static_cast<T>(cf[t] * (px * ex[j] + py * ey[j] + pz * ez[j]));
+  };
+  // row k of A(x, r), x having bond vector (px, py, pz).  Entries are taken
+  // kBatchN at a time (indices clamped to the last entry, extra lanes of a
+  // batch discarded) so that their loads are issued together.
+  auto build_row = [&](int32_t k, double px, double py, double pz) {
+    const Rec ek = ld_rec(er + 4 * k);
+    set_diag(k, static_cast<T>(cd[k] * (px * ek.x + py * ek.y + pz * ek.z)));
+    const int32_t q0 = up_start[k], nq = up_start[k + 1] - q0;
+    const int32_t t0 = l_start[k], tot = nq + (l_start[k + 1] - t0);
+    for (int32_t b = 0; b < tot; b += kBatchN) {
+      int32_t sb[kBatchN];
+      Rec nb[kBatchN];
+      double cb[kBatchN];
+#pragma unroll
+      for (int i = 0; i < kBatchN; ++i) {
+        int32_t j;
+        slot_of(imin(b + i, tot - 1), q0, nq, t0, sb[i], j);
+        nb[i] = ld_rec(er + 4 * j);
+        cb[i] = cf[sb[i]];
+      }
+#pragma unroll
+      for (int i = 0; i < kBatchN; ++i)
+        if (b + i < tot) F[sb[i]] = static_cast<T>(cb[i] * (px * nb[i].x + py * nb[i].y + pz * nb[i].z));
     }
   };
 
   // one elimination level: diagonal entries (forward substitution fused
-  // when FORWARD) and, when FACTOR, the upper entries with updates
+  // when FORWARD) and, when FACTOR, the upper entries with updates.  The
+  // entries of an item are taken kBatch (updates kBatchU) at a time, indices
+  // clamped to the last entry and the extra lanes of a batch discarded, so
+  // that the loads of a batch are issued together.
   auto factor_level = [&](int32_t h, auto factor_tag, auto forward_tag) {
     constexpr bool FACTOR = decltype(factor_tag)::value;
     constexpr bool FORWARD = decltype(forward_tag)::value;
     int32_t r0, r1, p0, p1;
     ld4(lvh + 4 * h, r0, r1, p0, p1);
+    r0 = uni(r0);
+    r1 = uni(r1);
+    p0 = uni(p0);
+    p1 = uni(p1);
     const int32_t nr = r1 - r0;
     const int32_t items = nr + (FACTOR ? p1 - p0 : 0);
     for (int32_t idx = tid; idx < items; idx += BLOCK) {
@@ -299,75 +402,150 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(const DevPlan P, const int
         const int32_t j = r0 + idx;
         T acc = D[j], yj = y[j];
         const T a0 = acc;
-        const int32_t t0 = l_start[j], t1 = l_start[j + 1];
-#pragma unroll 2
-        for (int32_t t = t0; t < t1; ++t) {
-          int32_t i, sl;
-          ld2(lpair + 2 * t, i, sl);
-          const T l = F[t] * D[i];
-          if (FACTOR) acc -= l * F[sl];
-          if (FORWARD) yj -= l * y[i];
+        const int32_t t0 = l_start[j], nt = l_start[j + 1] - t0;
+        for (int32_t b = 0; b < nt; b += kBatch) {
+          int32_t ii[kBatch], ss[kBatch];
+          T f[kBatch], di[kBatch], fs[kBatch], yi[kBatch];
+#pragma unroll
+          for (int i = 0; i < kBatch; ++i) ld2(lpair + 2 * (t0 + imin(b + i, nt - 1)), ii[i], ss[i]);
+#pragma unroll
+          for (int i = 0; i < kBatch; ++i) {
+            f[i] = F[t0 + imin(b + i, nt - 1)];
+            di[i] = D[ii[i]];
+            if (FACTOR) fs[i] = F[ss[i]];
+            if (FORWARD) yi[i] = y[ii[i]];
+          }
+#pragma unroll
+          for (int i = 0; i < kBatch; ++i) {
+            if (b + i < nt) {
+              const T l = f[i] * di[i];
+              if (FACTOR) acc -= l * fs[i];
+              if (FORWARD) yj -= l * yi[i];
+            }
+          }
         }
         if (FACTOR) {
           if (!(fabs(acc) > pivot_eps<T>() * fabs(a0))) singular = 1;
-          D[j] = T(1) / acc;
+          D[j] = recip(acc);
         }
         if (FORWARD) y[j] = yj;
       } else if (FACTOR) {
         int32_t q, tr, u0, nu;
         ld4(prec + 4 * (p0 + idx - nr), q, tr, u0, nu);
         T au = F[q], aw = F[tr];
-#pragma unroll 2
-        for (int32_t u = u0; u < u0 + nu; ++u) {
-          int32_t pa, pb, s1, s2;
-          ld4(upd + 4 * u, pa, pb, s1, s2);
-          const T di = D[updi[u]];
-          au -= F[pa] * di * F[s1];
-          aw -= F[pb] * di * F[s2];
+        for (int32_t b = 0; b < nu; b += kBatchU) {
+          int32_t pa[kBatchU], pb[kBatchU], s1[kBatchU], s2[kBatchU], ui[kBatchU];
+#pragma unroll
+          for (int i = 0; i < kBatchU; ++i) {
+            const int32_t u = u0 + imin(b + i, nu - 1);
+            ld4(upd + 4 * u, pa[i], pb[i], s1[i], s2[i]);
+            ui[i] = updi[u];
+          }
+          T fa[kBatchU], fb[kBatchU], f1[kBatchU], f2[kBatchU], di[kBatchU];
+#pragma unroll
+          for (int i = 0; i < kBatchU; ++i) {
+            fa[i] = F[pa[i]];
+            fb[i] = F[pb[i]];
+            f1[i] = F[s1[i]];
+            f2[i] = F[s2[i]];
+            di[i] = D[ui[i]];
+          }
+#pragma unroll
+          for (int i = 0; i < kBatchU; ++i) {
+            if (b + i < nu) {
+              au -= fa[i] * di[i] * f1[i];
+              aw -= fb[i] * di[i] * f2[i];
+            }
+          }
         }
         F[q] = au;
         F[tr] = aw;
       }
     }
   };
+  auto factor_sweep = [&](auto factor_tag, auto forward_tag) {
+    for (int32_t h = 1; h < H; ++h) {
+      factor_level(h, factor_tag, forward_tag);
+      __syncthreads();
+    }
+  };
+  // backward substitution, levels H-1 .. 0
+  auto back_sweep = [&]() {
+    for (int32_t h = H - 1; h >= 0; --h) {
+      const int32_t k0 = uni(static_cast<int32_t>(lvh[4 * h])), k1 = uni(static_cast<int32_t>(lvh[4 * h + 1]));
+      for (int32_t k = k0 + tid; k < k1; k += BLOCK) {
+        T acc = y[k];
+        const T dk = D[k];
+        const int32_t q0 = up_start[k], nq = up_start[k + 1] - q0;
+        for (int32_t b = 0; b < nq; b += kBatch) {
+          int32_t c[kBatch];
+          T f[kBatch], yc[kBatch];
+#pragma unroll
+          for (int i = 0; i < kBatch; ++i) c[i] = ucol[q0 + imin(b + i, nq - 1)];
+#pragma unroll
+          for (int i = 0; i < kBatch; ++i) {
+            f[i] = F[q0 + imin(b + i, nq - 1)];
+            yc[i] = y[c[i]];
+          }
+#pragma unroll
+          for (int i = 0; i < kBatch; ++i)
+            if (b + i < nq) acc -= f[i] * yc[i];
+        }
+        y[k] = acc * dk;
+      }
+      __syncthreads();
+    }
+  };
 
   // ---- chord: factor A(r, r) once
   if (A.chord) {
-    for (int32_t k = tid; k < n; k += BLOCK) build_row(k, ex[k], ey[k], ez[k]);
-    __syncthreads();
-    for (int32_t h = 1; h < H; ++h) {
-      factor_level(h, std::true_type{}, std::false_type{});
-      __syncthreads();
+    for (int32_t k = tid; k < n; k += BLOCK) {
+      const Rec ek = ld_rec(er + 4 * k);
+      build_row(k, ek.x, ek.y, ek.z);
     }
+    __syncthreads();
+    factor_sweep(std::true_type{}, std::false_type{});
   }
 
   int32_t it = 0;
   int32_t st_code = ILVES_ERR_NOT_CONVERGED;
   int32_t fell_back = 0, rises = 0;
   double prev_gmax = INFINITY;
-  const bool chord_singular = A.chord && singular;
+  const bool chord_singular = A.chord && uni(singular);
   if (chord_singular) st_code = ILVES_ERR_SINGULAR;
   while (!chord_singular) {
-    // ---- residual at the current lambda; Newton: rebuild the matrix rows
+    // ---- residual at the current lambda; Newton: rebuild the matrix rows.
+    //      The neighbour entries are gathered kBatchN at a time; when a row
+    //      has at most kBatchN of them they stay in registers for the build.
     double vmax = 0.0;
     for (int32_t k = tid; k < n; k += BLOCK) {
-      const double lk = lam[k] * cd[k];
-      double px = u_x[k] - lk * ex[k];
-      double py = u_y[k] - lk * ey[k];
-      double pz = u_z[k] - lk * ez[k];
-      for (int32_t q = up_start[k], q1 = up_start[k + 1]; q < q1; ++q) {
-        const int32_t j = ucol[q];
-        const double c = cf[q] * lam[j];
-        px -= c * ex[j];
-        py -= c * ey[j];
-        pz -= c * ez[j];
-      }
-      for (int32_t t = l_start[k], t1 = l_start[k + 1]; t < t1; ++t) {
-        const int32_t j = lpair[2 * t];
-        const double c = cf[t] * lam[j];
-        px -= c * ex[j];
-        py -= c * ey[j];
-        pz -= c * ez[j];
+      const Rec ek = ld_rec(er + 4 * k);
+      const double lk = ek.l * cd[k];
+      double px = u_x[k] - lk * ek.x;
+      double py = u_y[k] - lk * ek.y;
+      double pz = u_z[k] - lk * ek.z;
+      const int32_t q0 = up_start[k], nq = up_start[k + 1] - q0;
+      const int32_t t0 = l_start[k], tot = nq + (l_start[k + 1] - t0);
+      int32_t sb[kBatchN];
+      Rec nb[kBatchN];
+      double cb[kBatchN];
+      for (int32_t b = 0; b < tot; b += kBatchN) {
+#pragma unroll
+        for (int i = 0; i < kBatchN; ++i) {
+          int32_t j;
+          slot_of(imin(b + i, tot - 1), q0, nq, t0, sb[i], j);
+          nb[i] = ld_rec(er + 4 * j);
+          cb[i] = cf[sb[i]];
+        }
+#pragma unroll
+        for (int i = 0; i < kBatchN; ++i) {
+          if (b + i < tot) {
+            const double c = cb[i] * nb[i].l;
+            px -= c * nb[i].x;
+            py -= c * nb[i].y;
+            pz -= c * nb[i].z;
+          }
+        }
       }
       const double pp = px * px + py * py + pz * pz;
       const double g = 0.5 * (pp - d2[k]);
@@ -375,7 +553,16 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(const DevPlan P, const int
       if (!(rel <= DBL_MAX)) rel = INFINITY;  // NaN or Inf
       vmax = fmax(vmax, rel);
       y[k] = static_cast<T>(g);
-      if (!A.chord) build_row(k, px, py, pz);
+      if (!A.chord) {
+        if (tot <= kBatchN) {
+          set_diag(k, static_cast<T>(cd[k] * (px * ek.x + py * ek.y + pz * ek.z)));
+#pragma unroll
+          for (int i = 0; i < kBatchN; ++i)
+            if (i < tot) F[sb[i]] = static_cast<T>(cb[i] * (px * nb[i].x + py * nb[i].y + pz * nb[i].z));
+        } else {
+          build_row(k, px, py, pz);
+        }
+      }
     }
     // workgroup max of the relative violation
 #pragma unroll
@@ -385,6 +572,7 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(const DevPlan P, const int
     double gmax = red[0];
 #pragma unroll
     for (int w = 1; w < BLOCK / 64; ++w) gmax = fmax(gmax, red[w]);
+    gmax = uni(gmax);
     if (A.warm == 2 && !fell_back) {
       // learned start: keep it only while it beats lambda = 0 and the
       // residual does not rise twice in a row; otherwise restart from 0
@@ -392,7 +580,7 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(const DevPlan P, const int
       if ((it == 0 && !(gmax < rel_zero)) || rises >= 2) {
         fell_back = 1;
         prev_gmax = INFINITY;
-        for (int32_t k = tid; k < n; k += BLOCK) lam[k] = 0.0;
+        for (int32_t k = tid; k < n; k += BLOCK) er[4 * k + 3] = 0.0;
         __syncthreads();
         continue;
       }
@@ -404,47 +592,31 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(const DevPlan P, const int
 
     // ---- factorisation fused with the forward substitution (Newton), or
     //      the forward substitution alone (chord)
-    if (A.chord) {
-      for (int32_t h = 1; h < H; ++h) {
-        factor_level(h, std::false_type{}, std::true_type{});
-        __syncthreads();
-      }
-    } else {
-      for (int32_t h = 1; h < H; ++h) {
-        factor_level(h, std::true_type{}, std::true_type{});
-        __syncthreads();
-      }
-    }
-    if (singular) { st_code = ILVES_ERR_SINGULAR; break; }
+    if (A.chord) factor_sweep(std::false_type{}, std::true_type{});
+    else factor_sweep(std::true_type{}, std::true_type{});
+    if (uni(singular)) { st_code = ILVES_ERR_SINGULAR; break; }
 
-    // ---- backward substitution and lambda update
-    for (int32_t h = H - 1; h >= 0; --h) {
-      const int32_t k0 = lvh[4 * h], k1 = lvh[4 * h + 1];
-      for (int32_t k = k0 + tid; k < k1; k += BLOCK) {
-        T acc = y[k];
-        for (int32_t q = up_start[k], q1 = up_start[k + 1]; q < q1; ++q) acc -= F[q] * y[ucol[q]];
-        const T z = acc * D[k];
-        y[k] = z;
-        lam[k] += static_cast<double>(z);
-      }
-      __syncthreads();
-    }
+    // ---- backward substitution, then the lambda update
+    back_sweep();
+    // lambda update after the sweep: keeps global traffic out of the levels
+    for (int32_t k = tid; k < n; k += BLOCK) er[4 * k + 3] += static_cast<double>(y[k]);
+    __syncthreads();
     ++it;
   }
 
   // ---- outputs: lambda in input order and r' = r_u - M^{-1} G(r)^T lambda
-  for (int32_t k = tid; k < n; k += BLOCK) A.lambda[cid[k]] = lam[k];
+  for (int32_t k = tid; k < n; k += BLOCK) A.lambda[cid[k]] = er[4 * k + 3];
   const int32_t* __restrict__ inc_ptr = P.inc_ptr + md.incp_off;
   const int32_t* __restrict__ inc = P.inc + md.inc_off;
   for (int32_t a = tid; a < s; a += BLOCK) {
     double dx = 0.0, dy = 0.0, dz = 0.0;
     for (int32_t q = inc_ptr[a]; q < inc_ptr[a + 1]; ++q) {
       const int32_t e = inc[q];
-      const int32_t k = e >> 1;
-      const double l = (e & 1) ? -lam[k] : lam[k];
-      dx += l * ex[k];
-      dy += l * ey[k];
-      dz += l * ez[k];
+      const Rec ek = ld_rec(er + 4 * (e >> 1));
+      const double l = (e & 1) ? -ek.l : ek.l;
+      dx += l * ek.x;
+      dy += l * ek.y;
+      dz += l * ek.z;
     }
     const int32_t g = atom_gid[a];
     const double im = invm[a];
@@ -526,6 +698,8 @@ struct Group {
   int32_t count = 0;
   int32_t grid = 0;   // persistent workgroups
   int32_t counter = 0;  // index of the group's queue counter
+  int stream = 0;       // index into the plan's streams
+  int64_t work = 0;     // sum over its molecules of rows + off-diagonal slots
 };
 constexpr int kMaxGroups = 64;
 
@@ -739,8 +913,22 @@ ilves_status_t build_device_plan(ilves_plan* P) {
       g.count = static_cast<int32_t>(b.second.size());
       g.counter = prec * kMaxGroups + static_cast<int32_t>(P->groups[prec].size());
       g.grid = g.count;  // refined from the occupancy once the kernels are known
+      for (int32_t i : b.second) g.work += static_cast<int64_t>(desc[i].n) + desc[i].n_up + desc[i].n_l;
       lists.insert(lists.end(), b.second.begin(), b.second.end());
       P->groups[prec].push_back(g);
+    }
+    // streams: longest processing time first -- each group, by decreasing
+    // work, joins the stream with the least work so far (launch order is
+    // the group order, so within a stream larger groups go first)
+    std::vector<Group>& gs = P->groups[prec];
+    std::stable_sort(gs.begin(), gs.end(), [](const Group& a, const Group& b) { return a.work > b.work; });
+    int64_t load[kStreams] = {};
+    for (Group& g : gs) {
+      int best = 0;
+      for (int i = 1; i < kStreams; ++i)
+        if (load[i] < load[best]) best = i;
+      g.stream = best;
+      load[best] += g.work;
     }
   }
   for (int wdt = 0; wdt < 2; ++wdt) {
@@ -1036,12 +1224,13 @@ ilves_status_t solve_impl(ilves_plan_t P, const double* r, const double* r_u, co
   hipLaunchKernelGGL(reset_counters, dim3(1), dim3(kMaxGroups), 0, stream, counters, kMaxGroups);
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipEventRecord(P->ev_fork, stream));
-  const int ns = std::min<int>(kStreams, static_cast<int>(groups.size()));
+  int ns = 1;
+  for (const Group& g : groups) ns = std::max(ns, g.stream + 1);
   for (int i = 0; i < ns; ++i) HIP_TRY(hipStreamWaitEvent(P->streams[i], P->ev_fork, 0));
   for (size_t gi = 0; gi < groups.size(); ++gi) {
     const Group& g = groups[gi];
     KernelFn k = pick_kernel(precision == ILVES_PREC_MIXED, g.mode, g.wide, g.block);
-    hipStream_t s = P->streams[gi % ns];
+    hipStream_t s = P->streams[g.stream];
     DevPlan dp = P->dp;
     const int32_t* list = P->d_lists + g.first;
     int32_t count = g.count;

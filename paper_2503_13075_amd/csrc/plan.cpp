@@ -6,12 +6,12 @@
 // has the sparsity pattern of the Newton matrix A (Eq. defA); a fill-reducing
 // ordering is computed once and the factorisation is then reused every step.
 //
-// The GPU cost of a sparse LU on one workgroup is set by the number of
-// dependent elimination levels as much as by the fill, so the planner
-// compares a minimum-degree ordering (zero fill on trees, but one level per
-// bond along a chain) with a nested-dissection ordering (logarithmic depth
-// along chains, some fill) under a simple latency/work model and keeps the
-// cheaper one.
+// The GPU cost of a sparse LU on one workgroup is set by the chain of
+// dependent load-and-update rounds through the elimination levels, so the
+// planner compares a minimum-deficiency ordering (no fill on trees, but one
+// level per bond along a chain) with a nested-dissection ordering (cut-vertex
+// or BFS-level separators: logarithmic depth along chains, some fill) under a
+// critical-path model and keeps the cheaper one.
 #include "plan.hpp"
 
 #include <algorithm>
@@ -170,6 +170,9 @@ std::vector<int32_t> order_nested_dissection(const std::vector<std::vector<int32
   std::vector<int32_t> order;
   order.reserve(n);
   std::vector<int32_t> mark(n, -1), lev(n, -1), local_of(n, -1);
+  // depth-first search state for the cut-vertex separators
+  std::vector<int32_t> disc(n, -1), low(n, 0), sub(n, 0), par(n, -1), sepsum(n, 0), maxc(n, 0), nsep(n, 0);
+  std::vector<std::pair<int32_t, int32_t>> stk;
   int32_t next_id = 0;
   std::vector<int32_t> queue;
   queue.reserve(n);
@@ -199,7 +202,69 @@ std::vector<int32_t> order_nested_dissection(const std::vector<std::vector<int32
     }
     const int32_t id = next_id++;
     for (int32_t v : nodes) mark[v] = id;
-    // pseudo-peripheral start vertex (George-Liu style)
+    std::vector<int32_t> sep;
+    // 1) a single cut vertex that splits the part evenly: on the chains and
+    //    trees of constraints a separator of one row, so the depth of the
+    //    elimination tree grows with log(size) only
+    {
+      const int32_t root = nodes[0];
+      for (int32_t v : nodes) {
+        disc[v] = -1;
+        sepsum[v] = 0;
+        maxc[v] = 0;
+        nsep[v] = 0;
+      }
+      int32_t timer = 0;
+      disc[root] = low[root] = timer++;
+      sub[root] = 1;
+      par[root] = -1;
+      stk.clear();
+      stk.emplace_back(root, 0);
+      while (!stk.empty()) {
+        const int32_t v = stk.back().first;
+        const int32_t it = stk.back().second;
+        if (it < static_cast<int32_t>(adj[v].size())) {
+          stk.back().second = it + 1;
+          const int32_t u = adj[v][it];
+          if (mark[u] != id) continue;
+          if (disc[u] < 0) {
+            par[u] = v;
+            disc[u] = low[u] = timer++;
+            sub[u] = 1;
+            stk.emplace_back(u, 0);
+          } else if (u != par[v]) {
+            low[v] = std::min(low[v], disc[u]);
+          }
+        } else {
+          stk.pop_back();
+          const int32_t pv = par[v];
+          if (pv >= 0) {
+            low[pv] = std::min(low[pv], low[v]);
+            sub[pv] += sub[v];
+            if (low[v] >= disc[pv]) {  // v's subtree is cut off by removing pv
+              sepsum[pv] += sub[v];
+              maxc[pv] = std::max(maxc[pv], sub[v]);
+              nsep[pv]++;
+            }
+          }
+        }
+      }
+      int32_t best = -1, best_max = sz;
+      if (timer == sz) {
+        for (int32_t v : nodes) {
+          const bool cut = v == root ? nsep[v] >= 2 : nsep[v] >= 1;
+          if (!cut) continue;
+          const int32_t mc = std::max(maxc[v], v == root ? 0 : sz - 1 - sepsum[v]);
+          if (mc < best_max) {
+            best_max = mc;
+            best = v;
+          }
+        }
+      }
+      if (best >= 0 && 4 * best_max <= 3 * sz) sep.push_back(best);
+    }
+    if (sep.empty()) {
+    // 2) otherwise a BFS level: pseudo-peripheral start vertex (George-Liu style)
     int32_t start = nodes[0];
     int32_t ecc = -1;
     for (int rep = 0; rep < 4; ++rep) {
@@ -217,7 +282,10 @@ std::vector<int32_t> order_nested_dissection(const std::vector<std::vector<int32
     std::vector<int32_t> vis = bfs(start, id);
     const int32_t d = lev[vis.back()];
     if (d < 2 || static_cast<int32_t>(vis.size()) != sz) {
-      for (int32_t v : nodes) mark[v] = -1;
+      for (int32_t v : nodes) {
+        mark[v] = -1;
+        lev[v] = -1;
+      }
       std::vector<int32_t> o = induced_md(adj, nodes, local_of);
       order.insert(order.end(), o.begin(), o.end());
       return;
@@ -237,7 +305,6 @@ std::vector<int32_t> order_nested_dissection(const std::vector<std::vector<int32
     }
     if (best_l < 0) best_l = d / 2;
     // separator: level best_l vertices that touch level best_l + 1
-    std::vector<int32_t> sep;
     for (int32_t v : nodes)
       if (lev[v] == best_l) {
         bool touches = false;
@@ -245,6 +312,7 @@ std::vector<int32_t> order_nested_dissection(const std::vector<std::vector<int32
           if (mark[u] == id && lev[u] == best_l + 1) { touches = true; break; }
         if (touches) sep.push_back(v);
       }
+    }
     for (int32_t v : sep) mark[v] = -2;  // excluded from the parts
     // connected components of the rest
     std::vector<std::vector<int32_t>> parts;
@@ -322,18 +390,41 @@ Symbolic symbolic(const std::vector<std::vector<int32_t>>& adj) {
     S.n_levels = std::max(S.n_levels, S.level[p] + 1);
     S.nnz_off += static_cast<int64_t>(S.up[p].size());
   }
-  // cost model: every level costs a barrier (SYNC) plus its work spread over
-  // LANES lanes; the backward solve walks the levels again.
-  const double SYNC = 16.0, LANES = 256.0;
-  std::vector<double> work(S.n_levels, 0.0), bwork(S.n_levels, 0.0);
+  // Cost model (critical path of the level-scheduled sweeps, fitted to
+  // measured solve times): a level costs a fixed part LEVEL (barrier and
+  // bookkeeping) plus the longest chain of dependent load-and-update rounds
+  // of any of its items -- a row takes one round per BATCH lower entries, a
+  // pair task one per update, and a wave that holds both kinds runs them one
+  // after the other; levels wider than LANES take several passes.  The
+  // backward sweep walks the levels again with one round per BATCH upper
+  // entries.
+  const double LEVEL = 0.7, BATCH = 2.0, LANES = 256.0;
+  std::vector<int32_t> max_row(S.n_levels, 0), max_pair(S.n_levels, 0), max_back(S.n_levels, 0);
+  std::vector<int64_t> items(S.n_levels, 0);
+  std::vector<int32_t> in_low(n, -1);
   for (int32_t j = 0; j < n; ++j) {
-    double w = 1.0 + static_cast<double>(S.low[j].size());
-    for (int32_t m : S.up[j]) w += 1.0 + static_cast<double>(S.low[j].size() + S.low[m].size());
-    work[S.level[j]] += w;
-    bwork[S.level[j]] += 1.0 + static_cast<double>(S.up[j].size());
+    const int32_t h = S.level[j];
+    if (h > 0) {
+      max_row[h] = std::max(max_row[h], static_cast<int32_t>(std::ceil(S.low[j].size() / BATCH)));
+      for (int32_t i : S.low[j]) in_low[i] = j;
+      for (int32_t m : S.up[j]) {
+        int32_t common = 0;
+        for (int32_t i : S.low[m])
+          if (in_low[i] == j) ++common;
+        if (common > 0) {
+          max_pair[h] = std::max(max_pair[h], common);
+          ++items[h];
+        }
+      }
+      ++items[h];
+    }
+    max_back[h] = std::max(max_back[h], static_cast<int32_t>(std::ceil(S.up[j].size() / BATCH)));
   }
-  for (int32_t h = 0; h < S.n_levels; ++h)
-    S.cost += 2.0 * SYNC + std::ceil(work[h] / LANES) * 4.0 + std::ceil(bwork[h] / LANES) * 2.0;
+  for (int32_t h = 0; h < S.n_levels; ++h) {
+    const double passes = std::max(1.0, std::ceil(static_cast<double>(items[h]) / LANES));
+    if (h > 0) S.cost += LEVEL + passes * (max_row[h] + max_pair[h]);
+    S.cost += LEVEL + max_back[h];
+  }
   return S;
 }
 

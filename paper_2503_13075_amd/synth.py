@@ -495,7 +495,10 @@ def add_h_angles(sysm: System) -> System:
     left free (otherwise a set of H angles would pin the Y-X-Y angle too and
     a ring whose angles are all pinned is over-constrained, making the
     constraint Jacobian rank deficient).  Distances come from the reference
-    geometry.
+    geometry.  Angles that are nearly straight (over 150 degrees) are never
+    constrained: the 1-3 distance then hardly depends on the angle, the
+    constraint is close to a combination of the two bonds, and the Newton
+    matrix close to singular.
     """
     s = sysm.n_atoms
     nbrs = [[] for _ in range(s)]
@@ -520,6 +523,10 @@ def add_h_angles(sysm: System) -> System:
         for h in hs:
             for y in ys:
                 cand.append((h, y))
+        def straight(a, b):
+            u, v = sysm.r[a] - sysm.r[x], sysm.r[b] - sysm.r[x]
+            return np.dot(u, v) < np.cos(np.radians(150.0)) * np.linalg.norm(u) * np.linalg.norm(v)
+        cand = [c for c in cand if not straight(*c)]
         for a, b in cand[:max(0, budget)]:
             new_pairs.append((a, b))
     if not new_pairs:
