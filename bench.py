@@ -125,6 +125,10 @@ def main():
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch tuning")
     ap.add_argument("--tuning", default=None,
                     help='apply this launch tuning instead of autotuning, JSON: {"band_block": [5 ints], "lds_limit": n}')
+    ap.add_argument("--tuning-file", default=os.path.join(ROOT, "paper_2503_13075_amd", "tuning.json"),
+                    help="launch tunings recorded per device and workload; a miss autotunes and records the result "
+                         "in gpurun_out/tuning_new.json")
+    ap.add_argument("--retune", action="store_true", help="autotune even when the tuning file has an entry")
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="MiB of a plain device copy run once before timing (counter calibration)")
     args = ap.parse_args()
@@ -249,9 +253,14 @@ def main():
         from paper_2503_13075_amd import autotune as AT
         it = torch.zeros(nm, dtype=torch.int32, device=dev)
         stt = torch.zeros(nm, dtype=torch.int32, device=dev)
-        t = AT.autotune(plan, lambda: plan.solve(r, pool[0], mass, 1e-12, r_out, lam, it, stt, precision=prec),
-                        reps=10)
-        log(f"autotune precision {prec}: {t}")
+        key = AT.plan_key(plan, prec, L.VARIANT_NEWTON)
+        run_one = lambda: plan.solve(r, pool[0], mass, 1e-12, r_out, lam, it, stt, precision=prec)  # noqa: E731
+        if args.retune:
+            t = dict(AT.autotune(plan, run_one, reps=10), cached=False)
+        else:
+            t = AT.tuned(plan, run_one, key, path=args.tuning_file, reps=10,
+                         store_path=os.path.join(ROOT, "gpurun_out", "tuning_new.json"))
+        log(f"tuning precision {prec} (key {key}): {t}")
         tunings[prec] = t
         return t
 

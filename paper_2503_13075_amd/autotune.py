@@ -107,13 +107,15 @@ def store(key: str, tuning: dict, path: str = DEFAULT_CACHE) -> None:
     os.replace(tmp, path)
 
 
-def tuned(plan: L.Plan, run, key: str, path: str = DEFAULT_CACHE, reps: int = 10, log=None) -> dict:
-    """Applies the cached tuning for ``key`` or runs ``autotune`` and caches
-    its result."""
+def tuned(plan: L.Plan, run, key: str, path: str = DEFAULT_CACHE, reps: int = 10, log=None,
+          store_path: str = None) -> dict:
+    """Applies the cached tuning for ``key`` from ``path`` or runs
+    ``autotune`` and records its result in ``store_path`` (default: the same
+    file)."""
     hit = load_cached(key, path)
     if hit is not None:
         plan.tune(band_block=hit["band_block"], lds_limit=hit["lds_limit"])
         return dict(hit, cached=True)
     res = autotune(plan, run, reps=reps, log=log)
-    store(key, res, path)
+    store(key, res, store_path or path)
     return dict(res, cached=False)

@@ -194,10 +194,9 @@ __device__ __forceinline__ double recip(double a) {
   return __builtin_fma(__builtin_fma(-a, r, 1.0), r, r);
 }
 
-// integer min / max by value (no references to temporaries, which would
-// keep small arrays out of registers)
+// integer min by value (no reference to a temporary, which would keep
+// small arrays out of registers)
 __device__ __forceinline__ int32_t imin(int32_t a, int32_t b) { return a < b ? a : b; }
-__device__ __forceinline__ int32_t imax(int32_t a, int32_t b) { return a > b ? a : b; }
 
 template <typename T> __device__ inline T pivot_eps();
 template <> __device__ inline double pivot_eps<double>() { return 1e-13; }
@@ -725,8 +724,9 @@ struct ilves_plan {
   int n_cu = 0;
   int32_t band_block[5] = {64, 128, 256, 512, 1024};  // block size per LDS band (tunable)
   std::vector<Group> groups[2];        // [0] FP64, [1] mixed
-  int32_t width_first[2] = {0, 0};     // molecule lists by index width (features kernel)
-  int32_t width_count[2] = {0, 0};
+  int32_t chunk_first[2] = {0, 0};     // row chunks of the feature passes, by index width
+  int32_t chunk_count[2] = {0, 0};
+  const int2* d_chunks = nullptr;      // {molecule, first row} pairs in d_buf
   float* d_mlp = nullptr;              // network parameters then normalisation block
   float* d_feat = nullptr;             // [n_constraints][16] features (plan row order)
   float* d_w = nullptr;                // [n_constraints] 1/m_a + 1/m_b
@@ -873,9 +873,18 @@ ilves_status_t build_device_plan(ilves_plan* P) {
     P->groups[prec].clear();
     // launch groups: LDS-resident molecules in bands of LDS size (block
     // size grows with the band), structure-only and global molecules apart
+    // Launch groups.  Every workgroup of a group allocates the group's
+    // largest LDS need, and groups beyond the number of streams run one after
+    // another, so the molecules held wholly in LDS are split, in order of
+    // their LDS need, into at most as many groups as there are streams left,
+    // at the split points that minimise the sum over groups of (allocated
+    // LDS) x (sum of the planner's cost estimates): the LDS-time product that
+    // bounds how many molecules are resident per CU.  Molecules with only
+    // part of their data in LDS form groups of their own by size.
     struct Key { int mode; bool wide; int band; };
     std::vector<std::pair<Key, std::vector<int32_t>>> buckets;
     std::vector<int> lds_of(nm, 0);
+    std::vector<int32_t> in_lds_list;
     for (int32_t i : ord) {
       const ilves::MolPlan& M = P->mols[i];
       auto pl = prec == 0 ? placement<double>(M, wide[i], P->opt.lds_limit)
@@ -884,10 +893,11 @@ ilves_status_t build_device_plan(ilves_plan* P) {
       if (prec == 1) {
         if (pl.first == ALL_LDS) ++in_lds; else ++in_ws;
       }
-      int band = 0;
-      if (pl.first == ALL_LDS) band = pl.second <= 8192 ? 0 : pl.second <= 24576 ? 1 : pl.second <= 65536 ? 2 : 3;
-      else band = M.n <= 4096 ? 3 : 4;
-      Key key{pl.first, wide[i] != 0, band};
+      if (pl.first == ALL_LDS && !wide[i]) {
+        in_lds_list.push_back(i);
+        continue;
+      }
+      Key key{pl.first, wide[i] != 0, M.n <= 4096 ? 3 : 4};
       bool found = false;
       for (auto& b : buckets)
         if (b.first.mode == key.mode && b.first.wide == key.wide && b.first.band == key.band) {
@@ -896,6 +906,63 @@ ilves_status_t build_device_plan(ilves_plan* P) {
           break;
         }
       if (!found) buckets.push_back({key, std::vector<int32_t>{i}});
+    }
+    if (!in_lds_list.empty()) {
+      // classes of LDS need in 256-byte steps (at most kLdsMax / 256 of them)
+      std::stable_sort(in_lds_list.begin(), in_lds_list.end(),
+                       [&](int32_t x, int32_t y) { return lds_of[x] < lds_of[y]; });
+      std::vector<int32_t> cls_end;  // end index (into in_lds_list) of each class
+      std::vector<double> cls_cost;
+      for (size_t t = 0; t < in_lds_list.size(); ++t) {
+        const int32_t q = (lds_of[in_lds_list[t]] + 255) / 256;
+        if (cls_end.empty() || (lds_of[in_lds_list[t - 1]] + 255) / 256 != q) {
+          cls_end.push_back(0);
+          cls_cost.push_back(0.0);
+        }
+        cls_end.back() = static_cast<int32_t>(t + 1);
+        cls_cost.back() += std::max(1.0, P->mols[in_lds_list[t]].cost);
+      }
+      const int32_t C = static_cast<int32_t>(cls_end.size());
+      const int K = std::max(1, std::min<int>(kStreams - static_cast<int>(buckets.size()), C));
+      std::vector<double> pre(C + 1, 0.0);
+      for (int32_t c = 0; c < C; ++c) pre[c + 1] = pre[c] + cls_cost[c];
+      // best[k][e]: least cost of splitting the first e classes into k groups
+      const double INF = 1e300;
+      std::vector<std::vector<double>> best(K + 1, std::vector<double>(C + 1, INF));
+      std::vector<std::vector<int32_t>> from(K + 1, std::vector<int32_t>(C + 1, 0));
+      best[0][0] = 0.0;
+      for (int k = 1; k <= K; ++k)
+        for (int32_t e = 1; e <= C; ++e) {
+          const double alloc = static_cast<double>(lds_of[in_lds_list[cls_end[e - 1] - 1]]);
+          for (int32_t b = k - 1; b < e; ++b) {
+            if (best[k - 1][b] >= INF) continue;
+            const double c = best[k - 1][b] + alloc * (pre[e] - pre[b]);
+            if (c < best[k][e]) {
+              best[k][e] = c;
+              from[k][e] = b;
+            }
+          }
+        }
+      int kb = 1;
+      for (int k = 2; k <= K; ++k)
+        if (best[k][C] < best[kb][C]) kb = k;
+      std::vector<int32_t> cut{C};
+      for (int k = kb, e = C; k > 0; --k) {
+        e = from[k][e];
+        cut.push_back(e);
+      }
+      std::reverse(cut.begin(), cut.end());  // 0 = cut[0] < ... < cut[kb] = C (class indices)
+      for (int k = kb - 1; k >= 0; --k) {     // largest first
+        const int32_t t0 = cut[k] == 0 ? 0 : cls_end[cut[k] - 1], t1 = cls_end[cut[k + 1] - 1];
+        const int mx = lds_of[in_lds_list[t1 - 1]];
+        const int band = mx <= 8192 ? 0 : mx <= 24576 ? 1 : mx <= 65536 ? 2 : 3;
+        std::vector<int32_t> mem(in_lds_list.begin() + t0, in_lds_list.begin() + t1);
+        std::stable_sort(mem.begin(), mem.end(), [&](int32_t x, int32_t y) {
+          return static_cast<int64_t>(desc[x].n_up) + desc[x].n_l + desc[x].n >
+                 static_cast<int64_t>(desc[y].n_up) + desc[y].n_l + desc[y].n;
+        });
+        buckets.push_back({Key{ALL_LDS, false, band}, mem});
+      }
     }
     if (buckets.size() > static_cast<size_t>(kMaxGroups)) return fail(ILVES_ERR_ARG, "internal: too many launch groups");
     const int32_t* band_block = P->band_block;
@@ -931,12 +998,19 @@ ilves_status_t build_device_plan(ilves_plan* P) {
       load[best] += g.work;
     }
   }
+  // row chunks of the feature passes, narrow molecules then wide ones
+  std::vector<int32_t> chunks;
   for (int wdt = 0; wdt < 2; ++wdt) {
-    P->width_first[wdt] = static_cast<int32_t>(lists.size());
+    P->chunk_first[wdt] = static_cast<int32_t>(chunks.size() / 2);
     for (int32_t i : ord)
-      if (wide[i] == wdt) lists.push_back(i);
-    P->width_count[wdt] = static_cast<int32_t>(lists.size()) - P->width_first[wdt];
+      if (wide[i] == wdt)
+        for (int32_t r0 = 0; r0 < P->mols[i].n; r0 += ilves_ws::kChunk) {
+          chunks.push_back(i);
+          chunks.push_back(r0);
+        }
+    P->chunk_count[wdt] = static_cast<int32_t>(chunks.size() / 2) - P->chunk_first[wdt];
   }
+  if (chunks.empty()) chunks.resize(2, 0);
   if (pool.empty()) pool.resize(16, 0);
   std::vector<unsigned char> blob;
   const size_t o_desc = push_array(blob, desc);
@@ -950,6 +1024,7 @@ ilves_status_t build_device_plan(ilves_plan* P) {
   const size_t o_incp = push_array(blob, inc_ptr);
   const size_t o_inc = push_array(blob, inc);
   const size_t o_lists = push_array(blob, lists);
+  const size_t o_chunks = push_array(blob, chunks);
   blob.resize(blob.size() + 256);
 
   HIP_TRY(hipMalloc(&P->d_buf, blob.size()));
@@ -967,6 +1042,7 @@ ilves_status_t build_device_plan(ilves_plan* P) {
   P->dp.inc_ptr = reinterpret_cast<const int32_t*>(b + o_incp);
   P->dp.inc = reinterpret_cast<const int32_t*>(b + o_inc);
   P->d_lists = reinterpret_cast<int32_t*>(b + o_lists);
+  P->d_chunks = reinterpret_cast<const int2*>(b + o_chunks);
   if (ws > 0) {
     HIP_TRY(hipMalloc(&P->d_ws, ws));
     P->ws_bytes = ws;
@@ -1009,6 +1085,7 @@ void release_device_plan(ilves_plan* P) {
   P->d_ws = nullptr;
   P->dp = DevPlan{};
   P->d_lists = nullptr;
+  P->d_chunks = nullptr;
 }
 
 }  // namespace
@@ -1184,7 +1261,7 @@ ilves_status_t check_solve_args(ilves_plan_t P, const double* r, const double* r
 ilves_status_t run_features(ilves_plan_t P, const double* r, const double* r_u, const double* mass, float* feat,
                             float* w, hipStream_t stream) {
   for (int wdt = 0; wdt < 2; ++wdt) {
-    hipError_t e = ilves_ws::launch_features(P->dp, P->d_lists + P->width_first[wdt], P->width_count[wdt], wdt == 1,
+    hipError_t e = ilves_ws::launch_features(P->dp, P->d_chunks + P->chunk_first[wdt], P->chunk_count[wdt], wdt == 1,
                                              r, r_u, mass, P->n_atoms, P->d_ws, feat, w, stream);
     if (e != hipSuccess) return fail(ILVES_ERR_HIP, std::string("features kernel: ") + hipGetErrorString(e));
   }

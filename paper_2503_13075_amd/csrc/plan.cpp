@@ -523,6 +523,7 @@ MolPlan plan_molecule(const std::vector<int32_t>& cons, const int32_t* pairs, co
   for (int32_t p = 0; p < n; ++p) inv[perm[p]] = p;
   P.n_levels = S.n_levels;
   P.fill = S.nnz_off - n_edges;
+  P.cost = S.cost;
 
   P.cid.resize(n);
   P.ra.resize(n);

@@ -45,6 +45,7 @@ struct MolPlan {
   std::vector<int32_t> inc;        // (row << 1) | (atom is b_k)
   int64_t fill = 0;
   int ordering = 0;                // 1 minimum fill, 2 nested dissection
+  double cost = 0.0;               // critical-path estimate of one Newton iteration (planner units)
 };
 
 struct PlanOptions {

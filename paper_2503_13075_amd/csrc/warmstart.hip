@@ -32,6 +32,18 @@ __device__ inline float gelu_grad(float x) {
   return 0.5f * (1.0f + erff(x * 0.70710678118654752f)) + x * expf(-0.5f * x * x) * 0.39894228040143268f;
 }
 
+// GELU for BF16 inference: x Phi(x) with erf from Abramowitz & Stegun
+// 7.1.26 (absolute error below 1.5e-7, far under the BF16 rounding of the
+// activations that follows); training keeps the library erf.
+__device__ inline float gelu_fast(float x) {
+  const float z = fabsf(x) * 0.70710678118654752f;
+  const float t = __builtin_amdgcn_rcpf(1.0f + 0.3275911f * z);
+  const float poly = t * (0.254829592f + t * (-0.284496736f + t * (1.421413741f + t * (-1.453152027f + t * 1.061405429f))));
+  const float erf_abs = 1.0f - poly * __expf(-z * z);
+  const float e = x < 0.0f ? -erf_abs : erf_abs;
+  return 0.5f * x * (1.0f + e);
+}
+
 // float -> bfloat16 bits, round to nearest even
 __device__ inline short to_bf16(float f) {
   unsigned int u = __float_as_uint(f);
@@ -43,101 +55,123 @@ typedef short bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 // ---------------------------------------------------------------------------
-// features: one workgroup per molecule, structure read from global memory
+// features: two passes over all rows, one thread per row.  A workgroup takes
+// one chunk of up to kChunk consecutive rows of one molecule (the chunk list
+// is built with the plan), so the rows of all molecules run in parallel
+// whatever the molecule sizes.  Pass 1 computes the row's own quantities and
+// keeps its old bond vector in the molecule's workspace; pass 2 sums over
+// the constraints sharing an atom.
+
+struct RowCtx {
+  MolDesc md;
+  int32_t k;
+};
 
 template <typename Idx>
-__global__ void __launch_bounds__(256) features_kernel(const DevPlan P, const int32_t* __restrict__ mols,
-                                                       const double* __restrict__ r, const double* __restrict__ ru,
-                                                       const double* __restrict__ mass, int32_t S,
-                                                       unsigned char* __restrict__ ws, float* __restrict__ feat,
-                                                       float* __restrict__ wout) {
-  const int tid = threadIdx.x;
-  const MolDesc md = P.mol[mols[blockIdx.x]];
-  const int32_t n = md.n, s = md.s, n_up = md.n_up, n_l = md.n_l, H = md.n_levels;
-  const Layout Lo = struct_layout(n, H, n_up, n_l, md.n_pl, md.n_upd, static_cast<int>(sizeof(Idx)));
+__device__ inline RowCtx row_ctx(const DevPlan& P, const int2* __restrict__ chunks) {
+  const int2 ch = chunks[blockIdx.x];
+  RowCtx c;
+  c.md = P.mol[__builtin_amdgcn_readfirstlane(ch.x)];
+  c.k = __builtin_amdgcn_readfirstlane(ch.y) + static_cast<int32_t>(threadIdx.x);
+  return c;
+}
+
+template <typename Idx>
+__global__ void __launch_bounds__(kChunk) features_own_kernel(const DevPlan P, const int2* __restrict__ chunks,
+                                                            const double* __restrict__ r,
+                                                            const double* __restrict__ ru,
+                                                            const double* __restrict__ mass, int32_t S,
+                                                            unsigned char* __restrict__ ws, float* __restrict__ feat,
+                                                            float* __restrict__ wout) {
+  const RowCtx c = row_ctx<Idx>(P, chunks);
+  const MolDesc& md = c.md;
+  const int32_t k = c.k, n = md.n;
+  if (k >= n) return;
+  const int32_t* atom_gid = P.atom_gid + md.atom_off;
+  const int32_t* inc_ptr = P.inc_ptr + md.incp_off;
+  const int64_t R0 = md.row_off;
+  double* ex = reinterpret_cast<double*>(ws + md.ws_off);
+  const int32_t la = P.ra[R0 + k], lb = P.rb[R0 + k];
+  const int32_t ga = atom_gid[la], gb = atom_gid[lb];
+  const double d2 = P.d2[R0 + k];
+  const double e0 = r[ga] - r[gb], e1 = r[S + ga] - r[S + gb], e2 = r[2 * S + ga] - r[2 * S + gb];
+  const double u0 = ru[ga] - ru[gb], u1 = ru[S + ga] - ru[S + gb], u2 = ru[2 * S + ga] - ru[2 * S + gb];
+  const double ia = 1.0 / mass[ga], ib = 1.0 / mass[gb];
+  const double w = ia + ib;
+  const double ee = e0 * e0 + e1 * e1 + e2 * e2;
+  const double bb = u0 * e0 + u1 * e1 + u2 * e2;
+  const double cc = u0 * u0 + u1 * u1 + u2 * u2 - d2;
+  const double disc = fmax(bb * bb - ee * cc, 0.0);
+  const double cx = u1 * e2 - u2 * e1, cy = u2 * e0 - u0 * e2, cz = u0 * e1 - u1 * e0;
+  const int32_t dega = inc_ptr[la + 1] - inc_ptr[la], degb = inc_ptr[lb + 1] - inc_ptr[lb];
+  float4* f = reinterpret_cast<float4*>(feat + (R0 + k) * N_FEAT);
+  f[0] = make_float4(static_cast<float>(cc / (bb + sqrt(disc))), static_cast<float>(cc / (2.0 * d2)),
+                     static_cast<float>(bb / d2 - 1.0), static_cast<float>(sqrt(cx * cx + cy * cy + cz * cz) / d2));
+  f[1] = make_float4(static_cast<float>(fabs(ia - ib) / w), static_cast<float>((dega + degb - 2) * 0.25),
+                     static_cast<float>(abs(dega - degb) * 0.25), 0.0f);
+  wout[R0 + k] = static_cast<float>(w);
+  ex[k] = e0;
+  ex[n + k] = e1;
+  ex[2 * n + k] = e2;
+}
+
+template <typename Idx>
+__global__ void __launch_bounds__(kChunk) features_sum_kernel(const DevPlan P, const int2* __restrict__ chunks,
+                                                            const double* __restrict__ mass, int32_t S,
+                                                            const unsigned char* __restrict__ ws,
+                                                            float* __restrict__ feat,
+                                                            const float* __restrict__ wout) {
+  const RowCtx c = row_ctx<Idx>(P, chunks);
+  const MolDesc& md = c.md;
+  const int32_t k = c.k, n = md.n, s = md.s;
+  if (k >= n) return;
+  (void)S;
+  const Layout Lo = struct_layout(n, md.n_levels, md.n_up, md.n_l, md.n_pl, md.n_upd, static_cast<int>(sizeof(Idx)));
   const unsigned char* st = P.ix + md.ix_off;
   const Idx* up_start = reinterpret_cast<const Idx*>(st + Lo.up_start);
   const Idx* l_start = reinterpret_cast<const Idx*>(st + Lo.l_start);
   const Idx* ucol = reinterpret_cast<const Idx*>(st + Lo.ucol);
   // lower-slot records {column, transpose}, indexed by F index t
-  const Idx* lpair = reinterpret_cast<const Idx*>(st + Lo.lpair) - 2 * static_cast<int64_t>(n_up);
+  const Idx* lpair = reinterpret_cast<const Idx*>(st + Lo.lpair) - 2 * static_cast<int64_t>(md.n_up);
   const int32_t* coef = P.coef + md.coef_off;
   const int32_t* atom_gid = P.atom_gid + md.atom_off;
-  const int32_t* ra = P.ra + md.row_off;
-  const int32_t* rb = P.rb + md.row_off;
-  const double* d2 = P.d2 + md.row_off;
-  const int32_t* inc_ptr = P.inc_ptr + md.incp_off;
-  double* ex = reinterpret_cast<double*>(ws + md.ws_off);
-  double* ey = ex + n;
-  double* ez = ey + n;
   const int64_t R0 = md.row_off;
-
-  // own quantities
-  for (int32_t k = tid; k < n; k += 256) {
-    const int32_t la = ra[k], lb = rb[k];
-    const int32_t ga = atom_gid[la], gb = atom_gid[lb];
-    const double e0 = r[ga] - r[gb], e1 = r[S + ga] - r[S + gb], e2 = r[2 * S + ga] - r[2 * S + gb];
-    const double u0 = ru[ga] - ru[gb], u1 = ru[S + ga] - ru[S + gb], u2 = ru[2 * S + ga] - ru[2 * S + gb];
-    const double ia = 1.0 / mass[ga], ib = 1.0 / mass[gb];
-    const double w = ia + ib;
-    const double ee = e0 * e0 + e1 * e1 + e2 * e2;
-    const double bb = u0 * e0 + u1 * e1 + u2 * e2;
-    const double c = u0 * u0 + u1 * u1 + u2 * u2 - d2[k];
-    const double disc = fmax(bb * bb - ee * c, 0.0);
-    const double cx = u1 * e2 - u2 * e1, cy = u2 * e0 - u0 * e2, cz = u0 * e1 - u1 * e0;
-    const int32_t dega = inc_ptr[la + 1] - inc_ptr[la], degb = inc_ptr[lb + 1] - inc_ptr[lb];
-    float* f = feat + (R0 + k) * N_FEAT;
-    f[0] = static_cast<float>(c / (bb + sqrt(disc)));
-    f[1] = static_cast<float>(c / (2.0 * d2[k]));
-    f[2] = static_cast<float>(bb / d2[k] - 1.0);
-    f[3] = static_cast<float>(sqrt(cx * cx + cy * cy + cz * cz) / d2[k]);
-    f[4] = static_cast<float>(fabs(ia - ib) / w);
-    f[5] = static_cast<float>((dega + degb - 2) * 0.25);
-    f[6] = static_cast<float>(abs(dega - degb) * 0.25);
-    wout[R0 + k] = static_cast<float>(w);
-    ex[k] = e0;
-    ey[k] = e1;
-    ez[k] = e2;
-  }
-  __syncthreads();
-  // sums over the constraints sharing an atom (original entries only)
-  for (int32_t k = tid; k < n; k += 256) {
-    const double e0 = ex[k], e1 = ey[k], e2 = ez[k];
-    const double ee = e0 * e0 + e1 * e1 + e2 * e2;
-    const double wk = static_cast<double>(wout[R0 + k]);
-    double s7 = 0, s8 = 0, s9 = 0, s10 = 0, s11 = 0, s12 = 0, s14 = 0, s15 = 0, cnt = 0;
-    auto visit = [&](int32_t t, int32_t j) {
-      const int32_t cf = coef[t];
-      const int32_t x = cf >> 1;
-      if (x >= s) return;  // fill entry
-      const double sg = (cf & 1) ? -1.0 : 1.0;
-      const double dot = e0 * ex[j] + e1 * ey[j] + e2 * ez[j];
-      const double rho = sg * dot / (mass[atom_gid[x]] * wk * ee);
-      const double q = wk / static_cast<double>(wout[R0 + j]);
-      const float* fj = feat + (R0 + j) * N_FEAT;
-      s7 += rho * q * fj[0];
-      s8 += fabs(rho);
-      s9 = fmax(s9, fabs(rho));
-      s10 += rho * q * fj[1];
-      s11 += rho * rho;
-      s12 += sg * dot / sqrt(ee * (ex[j] * ex[j] + ey[j] * ey[j] + ez[j] * ez[j]));
-      s14 += rho * q * fj[2];
-      s15 += rho * q * fj[3];
-      cnt += 1.0;
-    };
-    for (int32_t q = up_start[k]; q < up_start[k + 1]; ++q) visit(q, ucol[q]);
-    for (int32_t t = l_start[k]; t < l_start[k + 1]; ++t) visit(t, lpair[2 * t]);
-    float* f = feat + (R0 + k) * N_FEAT;
-    f[7] = static_cast<float>(s7);
-    f[8] = static_cast<float>(s8);
-    f[9] = static_cast<float>(s9);
-    f[10] = static_cast<float>(s10);
-    f[11] = static_cast<float>(s11);
-    f[12] = static_cast<float>(s12 / fmax(cnt, 1.0));
-    f[13] = static_cast<float>(cnt / 6.0);
-    f[14] = static_cast<float>(s14);
-    f[15] = static_cast<float>(s15);
-  }
+  const double* ex = reinterpret_cast<const double*>(ws + md.ws_off);
+  const double* ey = ex + n;
+  const double* ez = ey + n;
+  const double e0 = ex[k], e1 = ey[k], e2 = ez[k];
+  const double ee = e0 * e0 + e1 * e1 + e2 * e2;
+  const double wk = static_cast<double>(wout[R0 + k]);
+  double s7 = 0, s8 = 0, s9 = 0, s10 = 0, s11 = 0, s12 = 0, s14 = 0, s15 = 0, cnt = 0;
+  auto visit = [&](int32_t t, int32_t j) {
+    const int32_t cf = coef[t];
+    const int32_t x = cf >> 1;
+    if (x >= s) return;  // fill entry
+    const double sg = (cf & 1) ? -1.0 : 1.0;
+    const double fx = ex[j], fy = ey[j], fz = ez[j];
+    const double dot = e0 * fx + e1 * fy + e2 * fz;
+    const double rho = sg * dot / (mass[atom_gid[x]] * wk * ee);
+    const double q = wk / static_cast<double>(wout[R0 + j]);
+    const float4 fj = *reinterpret_cast<const float4*>(feat + (R0 + j) * N_FEAT);
+    s7 += rho * q * fj.x;
+    s8 += fabs(rho);
+    s9 = fmax(s9, fabs(rho));
+    s10 += rho * q * fj.y;
+    s11 += rho * rho;
+    s12 += sg * dot / sqrt(ee * (fx * fx + fy * fy + fz * fz));
+    s14 += rho * q * fj.z;
+    s15 += rho * q * fj.w;
+    cnt += 1.0;
+  };
+  for (int32_t q = up_start[k]; q < up_start[k + 1]; ++q) visit(q, ucol[q]);
+  for (int32_t t = l_start[k]; t < l_start[k + 1]; ++t) visit(t, lpair[2 * t]);
+  float* f = feat + (R0 + k) * N_FEAT;
+  f[7] = static_cast<float>(s7);
+  reinterpret_cast<float4*>(f)[2] = make_float4(static_cast<float>(s8), static_cast<float>(s9),
+                                                static_cast<float>(s10), static_cast<float>(s11));
+  reinterpret_cast<float4*>(f)[3] = make_float4(static_cast<float>(s12 / fmax(cnt, 1.0)),
+                                                static_cast<float>(cnt / 6.0), static_cast<float>(s14),
+                                                static_cast<float>(s15));
 }
 
 // ---------------------------------------------------------------------------
@@ -205,7 +239,7 @@ __global__ void __launch_bounds__(256) mlp_infer_kernel(const float* __restrict_
       f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
       acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A1[hb], xb, acc, 0, 0, 0);
 #pragma unroll
-      for (int i = 0; i < 4; ++i) h1[hb][i] = to_bf16(gelu(acc[i] + bias1[hb][i]));
+      for (int i = 0; i < 4; ++i) h1[hb][i] = to_bf16(gelu_fast(acc[i] + bias1[hb][i]));
     }
     float part = 0.0f;
 #pragma unroll
@@ -214,7 +248,7 @@ __global__ void __launch_bounds__(256) mlp_infer_kernel(const float* __restrict_
 #pragma unroll
       for (int kb = 0; kb < 4; ++kb) acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A2[ob][kb], h1[kb], acc, 0, 0, 0);
 #pragma unroll
-      for (int i = 0; i < 4; ++i) part += w3[ob][i] * gelu(acc[i] + bias2[ob][i]);
+      for (int i = 0; i < 4; ++i) part += w3[ob][i] * gelu_fast(acc[i] + bias2[ob][i]);
     }
     // lanes l, l+16, l+32, l+48 hold partial sums of the same row
     part += __shfl_xor(part, 16, 64);
@@ -348,16 +382,21 @@ __global__ void adam_kernel(float* __restrict__ p, const float* __restrict__ g, 
 
 }  // namespace
 
-hipError_t launch_features(const DevPlan& P, const int32_t* mols, int32_t n_mols, bool wide, const double* r,
+hipError_t launch_features(const DevPlan& P, const int2* chunks, int32_t n_chunks, bool wide, const double* r,
                            const double* r_u, const double* mass, int32_t n_atoms, unsigned char* ws, float* feat,
                            float* w, hipStream_t stream) {
-  if (n_mols <= 0) return hipSuccess;
-  if (wide)
-    hipLaunchKernelGGL(features_kernel<int32_t>, dim3(n_mols), dim3(256), 0, stream, P, mols, r, r_u, mass,
+  if (n_chunks <= 0) return hipSuccess;
+  if (wide) {
+    hipLaunchKernelGGL(features_own_kernel<int32_t>, dim3(n_chunks), dim3(kChunk), 0, stream, P, chunks, r, r_u,
+                       mass, n_atoms, ws, feat, w);
+    hipLaunchKernelGGL(features_sum_kernel<int32_t>, dim3(n_chunks), dim3(kChunk), 0, stream, P, chunks, mass,
                        n_atoms, ws, feat, w);
-  else
-    hipLaunchKernelGGL(features_kernel<uint16_t>, dim3(n_mols), dim3(256), 0, stream, P, mols, r, r_u, mass,
+  } else {
+    hipLaunchKernelGGL(features_own_kernel<uint16_t>, dim3(n_chunks), dim3(kChunk), 0, stream, P, chunks, r, r_u,
+                       mass, n_atoms, ws, feat, w);
+    hipLaunchKernelGGL(features_sum_kernel<uint16_t>, dim3(n_chunks), dim3(kChunk), 0, stream, P, chunks, mass,
                        n_atoms, ws, feat, w);
+  }
   return hipGetLastError();
 }
 

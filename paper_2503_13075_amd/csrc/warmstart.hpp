@@ -17,10 +17,12 @@ constexpr int N_PARAMS = N_FEAT * N_HID + N_HID + N_HID * N_HID + N_HID + N_HID 
 // normalisation block: feature means [16], feature scales [16], output scale
 constexpr int N_NORM = 2 * N_FEAT + 1;
 constexpr int TRAIN_BS = 64;  // samples per training workgroup
+constexpr int kChunk = 256;   // rows per chunk of the feature passes
 
-// Features of every row of the listed molecules (plan row order), and
-// w_k = 1/m_a + 1/m_b.  Uses each molecule's workspace as scratch.
-hipError_t launch_features(const ilves_dev::DevPlan& P, const int32_t* mols, int32_t n_mols, bool wide,
+// Features of every row of the listed row chunks ({molecule, first row},
+// at most kChunk rows each; plan row order), and w_k = 1/m_a + 1/m_b.  Uses
+// each molecule's workspace as scratch.
+hipError_t launch_features(const ilves_dev::DevPlan& P, const int2* chunks, int32_t n_chunks, bool wide,
                            const double* r, const double* r_u, const double* mass, int32_t n_atoms,
                            unsigned char* ws, float* feat, float* w, hipStream_t stream);
 

@@ -1,0 +1,97 @@
+"""Summaries of rocprofv3 output for the batched solve.
+
+    python -m paper_2503_13075_amd.rocprof_summary trace <dir>
+    python -m paper_2503_13075_amd.rocprof_summary traffic <fetch dir> <write dir> <solves> <copy MiB> \
+        <algorithmic bytes per solve> [json out] [launch tuning as JSON]
+
+``trace`` prints the kernel statistics of a ``--kernel-trace --stats`` run as
+a markdown table.  ``traffic`` turns two ``--pmc FETCH_SIZE`` / ``--pmc
+WRITE_SIZE`` runs of ``bench.py --calibrate-copy MiB`` into HBM bytes per
+solve: the counters of every dispatch of the solve kernels are summed and
+divided by the number of solves, and each counter is scaled by what it reads
+for the plain device copy of known size that bench.py runs first (the
+largest ``__amd_rocclr_copyBuffer`` dispatch).
+"""
+from __future__ import annotations
+
+import csv
+import glob
+import json
+import os
+import sys
+
+SOLVE_KERNELS = ("solve_kernel", "reset_counters", "copy_free_atoms")
+
+
+def _csv(path_glob):
+    files = sorted(glob.glob(path_glob, recursive=True))
+    if not files:
+        raise FileNotFoundError(path_glob)
+    with open(files[0]) as f:
+        return list(csv.DictReader(f))
+
+
+def trace_table(d: str) -> str:
+    rows = _csv(os.path.join(d, "**", "*kernel_stats.csv"))
+    out = ["| kernel | calls | total us | average us | min us | max us |", "|---|---|---|---|---|---|"]
+    for r in rows:
+        name = r["Name"].replace("(anonymous namespace)::", "")
+        name = name.split("(")[0] if "solve_kernel" not in name else name.split(")(")[0] + ")"
+        out.append(f"| `{name[:90]}` | {r['Calls']} | {float(r['TotalDurationNs']) / 1e3:.1f} | "
+                   f"{float(r['AverageNs']) / 1e3:.1f} | {float(r['MinNs']) / 1e3:.1f} | "
+                   f"{float(r['MaxNs']) / 1e3:.1f} |")
+    return "\n".join(out)
+
+
+def _counter(d: str, name: str):
+    rows = _csv(os.path.join(d, "**", "*counter_collection.csv"))
+    solve, copies = 0.0, []
+    for r in rows:
+        if r["Counter_Name"] != name:
+            continue
+        v = float(r["Counter_Value"])
+        if any(k in r["Kernel_Name"] for k in SOLVE_KERNELS):
+            solve += v
+        elif "copyBuffer" in r["Kernel_Name"]:
+            copies.append(v)
+    return solve, (max(copies) if copies else None)
+
+
+def traffic(fetch_dir: str, write_dir: str, solves: int, copy_mib: int, algorithmic: float) -> dict:
+    copy_bytes = copy_mib * (1 << 20)
+    f_sum, f_copy = _counter(fetch_dir, "FETCH_SIZE")
+    w_sum, w_copy = _counter(write_dir, "WRITE_SIZE")
+    ff = copy_bytes / (f_copy * 1024.0)
+    fw = copy_bytes / (w_copy * 1024.0)
+    fetch = f_sum / solves * 1024.0 * ff
+    write = w_sum / solves * 1024.0 * fw
+    return {"fetch_bytes_per_solve": fetch, "write_bytes_per_solve": write,
+            "traffic_bytes_per_solve": fetch + write, "fetch_calibration_factor": ff,
+            "write_calibration_factor": fw, "raw_fetch_kib_per_solve": f_sum / solves,
+            "raw_write_kib_per_solve": w_sum / solves, "algorithmic_bytes_per_solve": algorithmic,
+            "traffic_over_algorithmic": (fetch + write) / algorithmic}
+
+
+def main(argv=None):
+    a = sys.argv[1:] if argv is None else argv
+    if a and a[0] == "trace":
+        print(trace_table(a[1]))
+    elif a and a[0] == "traffic":
+        res = traffic(a[1], a[2], int(a[3]), int(a[4]), float(a[5]))
+        from .build import kernel_source_hash
+        res["kernel_source_sha256_16"] = kernel_source_hash()
+        if len(a) > 7:
+            res["tuning"] = json.loads(a[7])
+        text = json.dumps(res, indent=1)
+        if len(a) > 6:
+            with open(a[6], "w") as f:
+                f.write(text + "\n")
+        print(text)
+    else:
+        print(__doc__)
+        return 2
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())
