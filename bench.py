@@ -129,6 +129,8 @@ def main():
                     help="launch tunings recorded per device and workload; a miss autotunes and records the result "
                          "in gpurun_out/tuning_new.json")
     ap.add_argument("--retune", action="store_true", help="autotune even when the tuning file has an entry")
+    ap.add_argument("--rng-steps", type=int, default=1000,
+                    help="also replay a graph of [device Philox inputs, solve, step += 1] this many times (0: skip)")
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="MiB of a plain device copy run once before timing (counter calibration)")
     args = ap.parse_args()
@@ -221,6 +223,70 @@ def main():
         rp = r_out.cpu().numpy().T
         viol = float(np.max(O.relative_violation(rp, sm.pairs, sm.d)))
         return viol
+
+    def rng_graph(steps, precision, learned):
+        """Many solves without the host: one captured graph draws the step's
+        r_u on the device (Philox4x32-10 + Box-Muller, step index in device
+        memory), solves, folds status and iterations into device
+        accumulators and advances the step; it is replayed `steps` times.
+        A graph of the generator alone gives its share of the step time."""
+        step = torch.tensor([0], dtype=torch.int64, device=dev)
+        ru = torch.empty_like(r)
+        it = torch.zeros(nm, dtype=torch.int32, device=dev)
+        stt = torch.zeros(nm, dtype=torch.int32, device=dev)
+        worst = torch.zeros(nm, dtype=torch.int32, device=dev)
+        it_sum = torch.zeros(nm, dtype=torch.int64, device=dev)
+
+        def gen():
+            L.perturb_normal(r, sigma, 1, step, ru)
+
+        def one():
+            gen()
+            if learned:
+                plan.solve_learned(r, ru, mass, 1e-12, r_out, lam, it, stt, precision=precision)
+            else:
+                plan.solve(r, ru, mass, 1e-12, r_out, lam, it, stt, precision=precision)
+            torch.maximum(worst, stt, out=worst)
+            it_sum.add_(it)
+            L.counter_add(step, 1)
+
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            one()
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        g_all, g_gen = torch.cuda.CUDAGraph(), torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g_all):
+            one()
+        with torch.cuda.graph(g_gen):
+            gen()
+        worst.zero_()
+        it_sum.zero_()
+        step.zero_()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            g_all.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        ok = bool((worst == 0).all().item())
+        iters = float(it_sum.sum().item()) / (steps * nm)
+        viol = check_last(None)
+        e0.record()
+        for _ in range(steps):
+            g_gen.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        gen_ms = e0.elapsed_time(e1) / steps
+        solve_ms = ms - gen_ms
+        return {"steps": steps, "ms_per_step_with_inputs": ms, "input_generation_ms": gen_ms,
+                "ms_per_step_solve": solve_ms,
+                "constraints_per_s_solve": (sm.n_constraints / (solve_ms / 1e3)) if ok else 0.0,
+                "all_ok": ok, "newton_iters_mean_per_molecule": iters, "max_rel_violation_last": viol,
+                "variant": "learned" if learned else "mixed", "seed": 1, "sigma_nm": sigma}
 
     if args.calibrate_copy > 0:
         nb = args.calibrate_copy * (1 << 20)
@@ -319,6 +385,9 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "algorithmic_bytes_per_step": abytes, "kernel": "solve_kernel (all launch groups of one solve)"},
     }
+    if args.rng_steps > 0:
+        out["rng_graph"] = rng_graph(args.rng_steps, L.PREC_MIXED, head_name == "learned")
+        log(f"rng graph: {out['rng_graph']}")
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(sm, pool_np[0], args.cpu_budget)

@@ -126,6 +126,28 @@ ilves_status_t ilves_plan_molecules(ilves_plan_t plan, int32_t* n_con, int32_t* 
                                     int32_t* n_levels, int32_t* first_constraint);
 
 /*
+ * Perturbed inputs for repeated solves (for example a captured HIP graph
+ * replayed over many steps): r_u = r + sigma * z, z standard normal, with
+ * z drawn from the counter-based generator Philox4x32-10 (Salmon et al.,
+ * SC 2011) and the Box-Muller transform.  For atom i and step s = *step:
+ * words w = Philox4x32-10(counter {i, 0, s mod 2^32, s / 2^32}, key {seed mod
+ * 2^32, seed / 2^32}); u1 = ((w1 2^32 + w0) >> 11 + 1/2) 2^-53, u2 likewise
+ * from (w3, w2); z_x = sqrt(-2 ln u1) cos(2 pi u2), z_y = sqrt(-2 ln u1)
+ * sin(2 pi u2); z_z is the first normal of the counter {i, 1, ...}.
+ * r, r_u: device SoA [3][n_atoms] FP64 (may not alias); step: device
+ * uint64, read when the kernel runs.  Asynchronous on hip_stream.
+ * Errors: ILVES_ERR_ARG (negative n_atoms or sigma, null pointers),
+ * ILVES_ERR_HIP.
+ */
+ilves_status_t ilves_perturb_normal(const double* r, int32_t n_atoms, double sigma, uint64_t seed,
+                                    const uint64_t* step, double* r_u, void* hip_stream);
+
+/* *counter += delta on the device (advances the step of
+ * ilves_perturb_normal inside a captured graph).  counter: device uint64.
+ * Errors: ILVES_ERR_ARG (null), ILVES_ERR_HIP. */
+ilves_status_t ilves_counter_add(uint64_t* counter, uint64_t delta, void* hip_stream);
+
+/*
  * Launch tuning of a plan (a performance knob; results agree to rounding).
  * band_block[b] is the threads per workgroup of launch band b.  Molecules
  * held wholly in LDS fall in bands 0..3 by their LDS size (<= 8 KB, <= 24 KB,

@@ -115,6 +115,10 @@ def lib() -> ctypes.CDLL:
     L.ilves_mlp_adam_f32.argtypes = [_P, _P, _P, _P, ctypes.c_int32, ctypes.c_float, ctypes.c_float,
                                      ctypes.c_float, ctypes.c_float, ctypes.c_int32, _P]
     L.ilves_mlp_adam_f32.restype = ctypes.c_int
+    L.ilves_perturb_normal.argtypes = [_P, ctypes.c_int32, ctypes.c_double, ctypes.c_uint64, _P, _P, _P]
+    L.ilves_perturb_normal.restype = ctypes.c_int
+    L.ilves_counter_add.argtypes = [_P, ctypes.c_uint64, _P]
+    L.ilves_counter_add.restype = ctypes.c_int
     L.ilves_plan_get_tuning.argtypes = [_P, ctypes.POINTER(Tuning)]
     L.ilves_plan_get_tuning.restype = ctypes.c_int
     L.ilves_plan_tune.argtypes = [_P, ctypes.POINTER(Tuning)]
@@ -348,6 +352,22 @@ def _plan_tune(self, band_block=None, lds_limit=None):
         t.band_block[i] = int(b)
     t.lds_limit = int(cur["lds_limit"] if lds_limit is None else lds_limit)
     check(self._L.ilves_plan_tune(self._h, ctypes.byref(t)))
+
+
+def perturb_normal(r, sigma, seed, step, r_u, stream=None):
+    """r_u = r + sigma * z on the device (Philox4x32-10 + Box-Muller); r and
+    r_u float64 [3, n_atoms] CUDA tensors, step a uint64-sized int64 CUDA
+    tensor of one element holding the step index."""
+    import torch
+    n = r.shape[1]
+    check(lib().ilves_perturb_normal(_dev(r, torch.float64, (3, n)), n, float(sigma), int(seed) & (2**64 - 1),
+                                     _dev(step, torch.int64, (1,)), _dev(r_u, torch.float64, (3, n)),
+                                     _stream(stream)))
+
+
+def counter_add(counter, delta=1, stream=None):
+    import torch
+    check(lib().ilves_counter_add(_dev(counter, torch.int64, (1,)), int(delta), _stream(stream)))
 
 
 Plan.get_tuning = _plan_get_tuning

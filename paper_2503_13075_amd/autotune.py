@@ -26,7 +26,8 @@ def plan_key(plan: L.Plan, precision: int, variant: int, warm: str = "zero") -> 
     import torch
     st = plan.stats()
     shape = [st[k] for k in ("molecules", "constraints", "atoms", "factor_entries", "updates", "sum_levels")]
-    dev = torch.cuda.get_device_name(torch.cuda.current_device())
+    props = torch.cuda.get_device_properties(torch.cuda.current_device())
+    dev = f"{getattr(props, 'gcnArchName', props.name).split(':')[0]}/{props.multi_processor_count}cu"
     text = json.dumps([dev, shape, int(precision), int(variant), warm])
     return hashlib.sha256(text.encode()).hexdigest()[:20]
 

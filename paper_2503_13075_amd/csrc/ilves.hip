@@ -48,6 +48,7 @@
 
 #include "../../include/ilves.h"
 #include "device_plan.hpp"
+#include "inputs.hpp"
 #include "plan.hpp"
 #include "warmstart.hpp"
 
@@ -1188,6 +1189,24 @@ ilves_status_t ilves_plan_destroy(ilves_plan_t P) {
   if (P->d_feat) (void)hipFree(P->d_feat);
   if (P->d_w) (void)hipFree(P->d_w);
   delete P;
+  return ILVES_OK;
+}
+
+ilves_status_t ilves_perturb_normal(const double* r, int32_t n_atoms, double sigma, uint64_t seed,
+                                    const uint64_t* step, double* r_u, void* hip_stream) {
+  if (n_atoms < 0) return fail(ILVES_ERR_ARG, "n_atoms must be >= 0");
+  if (!(sigma >= 0.0) || !std::isfinite(sigma)) return fail(ILVES_ERR_ARG, "sigma must be finite and >= 0");
+  if (n_atoms == 0) return ILVES_OK;
+  if (!r || !r_u || !step) return fail(ILVES_ERR_ARG, "null argument");
+  const hipError_t e = ilves_in::launch_perturb(r, n_atoms, sigma, seed, step, r_u, static_cast<hipStream_t>(hip_stream));
+  if (e != hipSuccess) return fail(ILVES_ERR_HIP, std::string("perturb kernel: ") + hipGetErrorString(e));
+  return ILVES_OK;
+}
+
+ilves_status_t ilves_counter_add(uint64_t* counter, uint64_t delta, void* hip_stream) {
+  if (!counter) return fail(ILVES_ERR_ARG, "null argument");
+  const hipError_t e = ilves_in::launch_counter_add(counter, delta, static_cast<hipStream_t>(hip_stream));
+  if (e != hipSuccess) return fail(ILVES_ERR_HIP, std::string("counter kernel: ") + hipGetErrorString(e));
   return ILVES_OK;
 }
 

@@ -607,3 +607,57 @@ def perturb(r: np.ndarray, sigma: float, seed: int) -> np.ndarray:
 def soa(x: np.ndarray) -> np.ndarray:
     """[s, 3] -> contiguous [3, s] (structure of arrays)."""
     return np.ascontiguousarray(np.asarray(x, dtype=np.float64).T)
+
+
+# ----------------------------------------------------------------------------
+# counter-based normal variates (the host side of the device generator)
+
+_PHILOX_M0, _PHILOX_M1 = 0xD2511F53, 0xCD9E8D57
+_PHILOX_W0, _PHILOX_W1 = 0x9E3779B9, 0xBB67AE85
+
+
+def philox4x32_10(ctr: np.ndarray, key) -> np.ndarray:
+    """Philox4x32-10 (Salmon et al., SC 2011) on an array of counters
+    ``ctr`` [m, 4] (uint32) with one key (k0, k1); returns [m, 4] uint32."""
+    c = [np.asarray(ctr[:, i], dtype=np.uint64) for i in range(4)]
+    k0, k1 = np.uint64(key[0] & 0xFFFFFFFF), np.uint64(key[1] & 0xFFFFFFFF)
+    mask = np.uint64(0xFFFFFFFF)
+    for _ in range(10):
+        p0 = np.uint64(_PHILOX_M0) * c[0]
+        p1 = np.uint64(_PHILOX_M1) * c[2]
+        hi0, lo0 = p0 >> np.uint64(32), p0 & mask
+        hi1, lo1 = p1 >> np.uint64(32), p1 & mask
+        c = [hi1 ^ c[1] ^ k0, lo1, hi0 ^ c[3] ^ k1, lo0]
+        k0 = (k0 + np.uint64(_PHILOX_W0)) & mask
+        k1 = (k1 + np.uint64(_PHILOX_W1)) & mask
+    return np.stack(c, axis=1).astype(np.uint32)
+
+
+def _uniform53(lo: np.ndarray, hi: np.ndarray) -> np.ndarray:
+    x = ((hi.astype(np.uint64) << np.uint64(32)) | lo.astype(np.uint64)) >> np.uint64(11)
+    return (x.astype(np.float64) + 0.5) * 2.0 ** -53
+
+
+def philox_normals(n_atoms: int, seed: int, step: int) -> np.ndarray:
+    """Standard normals z [n_atoms, 3] of atom i at a step: Box-Muller on the
+    words of the counters {i, 0, step} (x, y) and {i, 1, step} (z)."""
+    i = np.arange(n_atoms, dtype=np.uint64)
+    key = (seed & 0xFFFFFFFF, (seed >> 32) & 0xFFFFFFFF)
+    out = np.empty((n_atoms, 3))
+    for half in (0, 1):
+        ctr = np.stack([i, np.full_like(i, half), np.full_like(i, step & 0xFFFFFFFF),
+                        np.full_like(i, (step >> 32) & 0xFFFFFFFF)], axis=1)
+        w = philox4x32_10(ctr, key)
+        u1, u2 = _uniform53(w[:, 0], w[:, 1]), _uniform53(w[:, 2], w[:, 3])
+        rho = np.sqrt(-2.0 * np.log(u1))
+        th = 2.0 * np.pi * u2
+        if half == 0:
+            out[:, 0], out[:, 1] = rho * np.cos(th), rho * np.sin(th)
+        else:
+            out[:, 2] = rho * np.cos(th)
+    return out
+
+
+def perturb_philox(r: np.ndarray, sigma: float, seed: int, step: int) -> np.ndarray:
+    """r + sigma * philox_normals (AoS [n, 3])."""
+    return r + sigma * philox_normals(r.shape[0], seed, step)

@@ -86,3 +86,28 @@ def test_concat_keeps_molecules_apart():
     assert c.n_atoms == 100 and c.n_constraints == sum(x.n_constraints for x in m)
     assert _violation(c) < 1e-13
     assert list(c.mol_start) == [0, 20, 40, 60, 80]
+
+
+def test_philox_known_answers():
+    """Known-answer vectors of Philox4x32-10 published with the generator
+    (Random123 distribution): counter / key -> output words."""
+    cases = [([0, 0, 0, 0], (0, 0), [0x6627e8d5, 0xe169c58d, 0xbc57ac4c, 0x9b00dbd8]),
+             ([0xffffffff] * 4, (0xffffffff, 0xffffffff), [0x408f276d, 0x41c83b0e, 0xa20bc7c6, 0x6d5451fd]),
+             ([0x243f6a88, 0x85a308d3, 0x13198a2e, 0x03707344], (0xa4093822, 0x299f31d0),
+              [0xd16cfe09, 0x94fdcceb, 0x5001e420, 0x24126ea1])]
+    for ctr, key, want in cases:
+        got = S.philox4x32_10(np.array([ctr], np.uint32), key)[0]
+        assert [int(x) for x in got] == want
+
+
+def test_philox_normals_statistics_and_streams():
+    z = S.philox_normals(200_000, seed=11, step=5)
+    assert np.all(np.abs(z.mean(0)) < 0.01)
+    assert np.all(np.abs(z.std(0) - 1.0) < 0.01)
+    kurt = ((z - z.mean(0)) ** 4).mean(0) / z.var(0) ** 2
+    assert np.all(np.abs(kurt - 3.0) < 0.05)
+    # different steps, seeds and atoms give different draws
+    assert not np.allclose(S.philox_normals(10, 11, 5), S.philox_normals(10, 11, 6))
+    assert not np.allclose(S.philox_normals(10, 11, 5), S.philox_normals(10, 12, 5))
+    assert np.array_equal(S.philox_normals(10, 11, 5), S.philox_normals(20, 11, 5)[:10])
+    assert abs(np.corrcoef(z[:, 0], z[:, 2])[0, 1]) < 0.01
