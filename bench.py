@@ -43,6 +43,10 @@ def make_workload(name, seed):
         sm = S.angles_system(seed=seed)
         return sm, 0.006, {"workload": "20 proteins + 1000 lipid chains, bonds + H-X-H/H-X-Y angles",
                            "molecules": 1020}
+    if name == "water":
+        sm = S.water_box(500_000, seed=seed)
+        return sm, 0.002, {"workload": "500,000 rigid waters (O-H, O-H, H-H), small-molecule path",
+                           "molecules": 500_000}
     if name == "chain64":
         sm = S.chain64(seed)
         return sm, 0.002, {"workload": "64-atom chain, bonds + 1-3 angles", "molecules": 1}

@@ -69,6 +69,21 @@ struct DevPlan {
   const int32_t* inc;
 };
 
+// A molecule of at most kSmallCons constraints on at most kSmallAtoms atoms,
+// solved by one thread with the whole Newton loop in registers (water-,
+// diatomic- or triatomic-like molecules).  64 bytes.
+constexpr int kSmallCons = 3;
+constexpr int kSmallAtoms = 4;
+struct SmallMol {
+  int32_t atom[kSmallAtoms];  // input atom indices (unused entries repeat atom[0])
+  int32_t cid[kSmallCons];    // input constraint indices
+  int32_t mol;                // molecule index (iters / status / fallback slot)
+  uint8_t a[kSmallCons], b[kSmallCons];  // local atoms of each constraint
+  uint8_t nc, na;
+  double d2[kSmallCons];
+};
+static_assert(sizeof(SmallMol) == 64, "SmallMol is one 64-byte record");
+
 __host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~static_cast<size_t>(15); }
 
 }  // namespace ilves_dev

@@ -633,6 +633,159 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(const DevPlan P, const int
   }
 }
 
+// ---------------------------------------------------------------------------
+// small molecules (at most 3 constraints on at most 4 atoms): one thread per
+// molecule, the same constraint-space Newton iteration in FP64 registers,
+// the dense 3x3 system solved by elimination without pivoting.
+
+__global__ void __launch_bounds__(256) small_kernel(const SmallMol* __restrict__ sm, int32_t count,
+                                                   const SolveArgs A) {
+  const int32_t t = blockIdx.x * 256 + threadIdx.x;
+  if (t >= count) return;
+  const SmallMol M = sm[t];
+  const int32_t S = A.n_atoms;
+  const int nc = M.nc, na = M.na;
+  double invm[kSmallAtoms], ru[kSmallAtoms][3];
+  double rmax = 0.0;
+#pragma unroll
+  for (int i = 0; i < kSmallAtoms; ++i) {
+    const int32_t g = M.atom[i];
+    invm[i] = i < na ? 1.0 / A.mass[g] : 0.0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      ru[i][c] = A.r_u[c * S + g];
+      if (i < na) rmax = fmax(rmax, fabs(ru[i][c]));
+    }
+  }
+  double e[kSmallCons][3], u[kSmallCons][3], lam[kSmallCons], cdiag[kSmallCons], coup[kSmallCons][kSmallCons];
+  double v0 = 0.0;
+#pragma unroll
+  for (int k = 0; k < kSmallCons; ++k) {
+    const int a = M.a[k], b = M.b[k];
+    const int32_t ga = M.atom[a], gb = M.atom[b];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      e[k][c] = A.r[c * S + ga] - A.r[c * S + gb];
+      u[k][c] = ru[a][c] - ru[b][c];
+    }
+    lam[k] = (k < nc && A.warm) ? A.lambda[M.cid[k]] : 0.0;
+    cdiag[k] = invm[a] + invm[b];
+    if (k < nc)
+      v0 = fmax(v0, fabs(u[k][0] * u[k][0] + u[k][1] * u[k][1] + u[k][2] * u[k][2] - M.d2[k]) / (2.0 * M.d2[k]));
+  }
+  // C_kj for k != j: sign(k, x) sign(j, x) / m_x for the shared atom x
+#pragma unroll
+  for (int k = 0; k < kSmallCons; ++k)
+#pragma unroll
+    for (int j = 0; j < kSmallCons; ++j) {
+      double c = 0.0;
+      if (k != j && k < nc && j < nc) {
+        if (M.a[k] == M.a[j]) c = invm[M.a[k]];
+        else if (M.b[k] == M.b[j]) c = invm[M.b[k]];
+        else if (M.a[k] == M.b[j]) c = -invm[M.a[k]];
+        else if (M.b[k] == M.a[j]) c = -invm[M.b[k]];
+      }
+      coup[k][j] = c;
+    }
+  const double delta = 1.7320508075688772 * rmax * 0x1.0p-52;
+  const double delta2 = 0.5 * delta * delta;
+  int32_t it = 0, st_code = ILVES_ERR_NOT_CONVERGED, fell_back = 0, rises = 0;
+  double prev = INFINITY;
+  for (;;) {
+    double ep[kSmallCons][3], g[kSmallCons];
+    double gmax = 0.0;
+#pragma unroll
+    for (int k = 0; k < kSmallCons; ++k) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        double x = u[k][c] - cdiag[k] * lam[k] * e[k][c];
+#pragma unroll
+        for (int j = 0; j < kSmallCons; ++j) x -= coup[k][j] * lam[j] * e[j][c];
+        ep[k][c] = x;
+      }
+      const double pp = ep[k][0] * ep[k][0] + ep[k][1] * ep[k][1] + ep[k][2] * ep[k][2];
+      g[k] = 0.5 * (pp - M.d2[k]);
+      double rel = (fabs(g[k]) + sqrt(pp) * delta + delta2) / M.d2[k];
+      if (!(rel <= DBL_MAX)) rel = INFINITY;
+      if (k < nc) gmax = fmax(gmax, rel);
+    }
+    if (A.warm == 2 && !fell_back) {
+      rises = (it > 0 && gmax > prev) ? rises + 1 : 0;
+      if ((it == 0 && !(gmax < v0)) || rises >= 2) {
+        fell_back = 1;
+        prev = INFINITY;
+#pragma unroll
+        for (int k = 0; k < kSmallCons; ++k) lam[k] = 0.0;
+        continue;
+      }
+      prev = gmax;
+    }
+    if (gmax == INFINITY) { st_code = ILVES_ERR_NONFINITE; break; }
+    if (gmax <= A.tol) { st_code = ILVES_OK; break; }
+    if (it >= A.max_iter) { st_code = ILVES_ERR_NOT_CONVERGED; break; }
+    // A_kj = C_kj (e'_k . e_j); unused rows are the identity
+    double m[kSmallCons][kSmallCons + 1];
+#pragma unroll
+    for (int k = 0; k < kSmallCons; ++k) {
+#pragma unroll
+      for (int j = 0; j < kSmallCons; ++j) {
+        const double c = k == j ? cdiag[k] : coup[k][j];
+        const double* xk = A.chord ? e[k] : ep[k];  // chord: the constant A(r, r)
+        const double dot = xk[0] * e[j][0] + xk[1] * e[j][1] + xk[2] * e[j][2];
+        m[k][j] = k < nc ? c * dot : (k == j ? 1.0 : 0.0);
+      }
+      m[k][kSmallCons] = k < nc ? g[k] : 0.0;
+    }
+    bool sing = false;
+#pragma unroll
+    for (int p = 0; p < kSmallCons; ++p) {
+      if (!(fabs(m[p][p]) > 1e-13 * fabs(cdiag[p] * (e[p][0] * e[p][0] + e[p][1] * e[p][1] + e[p][2] * e[p][2]))))
+        sing = sing || p < nc;
+      const double inv = 1.0 / m[p][p];
+#pragma unroll
+      for (int q = p + 1; q < kSmallCons; ++q) {
+        const double f = m[q][p] * inv;
+#pragma unroll
+        for (int j = p; j <= kSmallCons; ++j) m[q][j] -= f * m[p][j];
+      }
+    }
+    if (sing) { st_code = ILVES_ERR_SINGULAR; break; }
+    double z[kSmallCons];
+#pragma unroll
+    for (int p = kSmallCons - 1; p >= 0; --p) {
+      double acc = m[p][kSmallCons];
+#pragma unroll
+      for (int j = p + 1; j < kSmallCons; ++j) acc -= m[p][j] * z[j];
+      z[p] = acc / m[p][p];
+    }
+#pragma unroll
+    for (int k = 0; k < kSmallCons; ++k)
+      if (k < nc) lam[k] += z[k];
+    ++it;
+  }
+#pragma unroll
+  for (int k = 0; k < kSmallCons; ++k)
+    if (k < nc) A.lambda[M.cid[k]] = lam[k];
+#pragma unroll
+  for (int i = 0; i < kSmallAtoms; ++i) {
+    if (i >= na) continue;
+    double d[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int k = 0; k < kSmallCons; ++k) {
+      if (k >= nc) continue;
+      const double l = M.a[k] == i ? lam[k] : (M.b[k] == i ? -lam[k] : 0.0);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) d[c] += l * e[k][c];
+    }
+    const int32_t gi = M.atom[i];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) A.r_out[c * S + gi] = ru[i][c] - invm[i] * d[c];
+  }
+  A.iters[M.mol] = it;
+  A.status[M.mol] = st_code;
+  if (A.fallback) A.fallback[M.mol] = fell_back;
+}
+
 __global__ void reset_counters(int32_t* __restrict__ c, int32_t n) {
   const int i = threadIdx.x;
   if (i < n) c[i] = 0;
@@ -728,6 +881,9 @@ struct ilves_plan {
   int32_t chunk_first[2] = {0, 0};     // row chunks of the feature passes, by index width
   int32_t chunk_count[2] = {0, 0};
   const int2* d_chunks = nullptr;      // {molecule, first row} pairs in d_buf
+  const SmallMol* d_small = nullptr;   // small-molecule records in d_buf
+  int32_t n_small = 0;
+  int small_stream = 0;                // stream of the small-molecule kernel
   float* d_mlp = nullptr;              // network parameters then normalisation block
   float* d_feat = nullptr;             // [n_constraints][16] features (plan row order)
   float* d_w = nullptr;                // [n_constraints] 1/m_a + 1/m_b
@@ -868,6 +1024,28 @@ ilves_status_t build_device_plan(ilves_plan* P) {
     return static_cast<int64_t>(desc[x].n_up) + desc[x].n_l + desc[x].n >
            static_cast<int64_t>(desc[y].n_up) + desc[y].n_l + desc[y].n;
   });
+  // small molecules go to the one-thread-per-molecule kernel
+  std::vector<char> small(nm, 0);
+  std::vector<SmallMol> smalls;
+  for (int32_t i = 0; i < nm; ++i) {
+    const ilves::MolPlan& M = P->mols[i];
+    if (M.n > kSmallCons || M.s > kSmallAtoms || M.n < 1) continue;
+    small[i] = 1;
+    SmallMol r{};
+    for (int a = 0; a < kSmallAtoms; ++a) r.atom[a] = M.atom_gid[a < M.s ? a : 0];
+    for (int k = 0; k < kSmallCons; ++k) {
+      const bool used = k < M.n;
+      r.cid[k] = used ? M.cid[k] : M.cid[0];
+      r.a[k] = static_cast<uint8_t>(used ? M.ra[k] : 0);
+      r.b[k] = static_cast<uint8_t>(used ? M.rb[k] : 0);
+      r.d2[k] = used ? M.d2[k] : 1.0;
+    }
+    r.mol = i;
+    r.nc = static_cast<uint8_t>(M.n);
+    r.na = static_cast<uint8_t>(M.s);
+    smalls.push_back(r);
+  }
+  ord.erase(std::remove_if(ord.begin(), ord.end(), [&](int32_t i) { return small[i] != 0; }), ord.end());
   std::vector<int32_t> lists;
   int64_t in_lds = 0, in_ws = 0;
   for (int prec = 0; prec < 2; ++prec) {
@@ -998,6 +1176,10 @@ ilves_status_t build_device_plan(ilves_plan* P) {
       g.stream = best;
       load[best] += g.work;
     }
+    int least = 0;
+    for (int i = 1; i < kStreams; ++i)
+      if (load[i] < load[least]) least = i;
+    P->small_stream = least;
   }
   // row chunks of the feature passes, narrow molecules then wide ones
   std::vector<int32_t> chunks;
@@ -1026,6 +1208,7 @@ ilves_status_t build_device_plan(ilves_plan* P) {
   const size_t o_inc = push_array(blob, inc);
   const size_t o_lists = push_array(blob, lists);
   const size_t o_chunks = push_array(blob, chunks);
+  const size_t o_small = push_array(blob, smalls);
   blob.resize(blob.size() + 256);
 
   HIP_TRY(hipMalloc(&P->d_buf, blob.size()));
@@ -1044,6 +1227,8 @@ ilves_status_t build_device_plan(ilves_plan* P) {
   P->dp.inc = reinterpret_cast<const int32_t*>(b + o_inc);
   P->d_lists = reinterpret_cast<int32_t*>(b + o_lists);
   P->d_chunks = reinterpret_cast<const int2*>(b + o_chunks);
+  P->d_small = reinterpret_cast<const SmallMol*>(b + o_small);
+  P->n_small = static_cast<int32_t>(smalls.size());
   if (ws > 0) {
     HIP_TRY(hipMalloc(&P->d_ws, ws));
     P->ws_bytes = ws;
@@ -1087,6 +1272,8 @@ void release_device_plan(ilves_plan* P) {
   P->dp = DevPlan{};
   P->d_lists = nullptr;
   P->d_chunks = nullptr;
+  P->d_small = nullptr;
+  P->n_small = 0;
 }
 
 }  // namespace
@@ -1313,14 +1500,14 @@ ilves_status_t solve_impl(ilves_plan_t P, const double* r, const double* r_u, co
     HIP_TRY(hipGetLastError());
   }
   const std::vector<Group>& groups = P->groups[precision == ILVES_PREC_MIXED ? 1 : 0];
-  if (groups.empty()) return ILVES_OK;
+  if (groups.empty() && P->n_small == 0) return ILVES_OK;
   // fork: the groups run concurrently on the plan's streams, joined back
   // into the caller's stream (also valid under graph capture)
   int32_t* counters = P->d_counters + (precision == ILVES_PREC_MIXED ? kMaxGroups : 0);
   hipLaunchKernelGGL(reset_counters, dim3(1), dim3(kMaxGroups), 0, stream, counters, kMaxGroups);
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipEventRecord(P->ev_fork, stream));
-  int ns = 1;
+  int ns = P->n_small > 0 ? P->small_stream + 1 : 1;
   for (const Group& g : groups) ns = std::max(ns, g.stream + 1);
   for (int i = 0; i < ns; ++i) HIP_TRY(hipStreamWaitEvent(P->streams[i], P->ev_fork, 0));
   for (size_t gi = 0; gi < groups.size(); ++gi) {
@@ -1335,6 +1522,11 @@ ilves_status_t solve_impl(ilves_plan_t P, const double* r, const double* r_u, co
     void* args[] = {&dp, &list, &count, &counter, &a};
     HIP_TRY(hipLaunchKernel(reinterpret_cast<const void*>(k), dim3(g.grid), dim3(g.block), args,
                             static_cast<size_t>(g.lds_bytes), s));
+  }
+  if (P->n_small > 0) {
+    hipLaunchKernelGGL(small_kernel, dim3((P->n_small + 255) / 256), dim3(256), 0, P->streams[P->small_stream],
+                       P->d_small, P->n_small, A);
+    HIP_TRY(hipGetLastError());
   }
   for (int i = 0; i < ns; ++i) {
     HIP_TRY(hipEventRecord(P->ev_join[i], P->streams[i]));

@@ -598,6 +598,76 @@ def angles_system(seed: int = 3, n_prot: int = 20, n_res: int = 315, n_lipid: in
     return concat(mols, spacing=1.2, name=f"angles_{n_prot}prot_{n_lipid}lipid")
 
 
+def _rotations(n: int, rng) -> np.ndarray:
+    """n uniformly random rotation matrices (QR of Gaussian matrices)."""
+    q, rr = np.linalg.qr(rng.normal(size=(n, 3, 3)))
+    q = q * np.sign(np.diagonal(rr, axis1=1, axis2=2))[:, None, :]
+    det = np.linalg.det(q)
+    q[:, :, 2] *= det[:, None]
+    return q
+
+
+def water_box(n_mol: int, seed: int = 0, spacing: float = 0.31) -> System:
+    """Rigid waters (three constraints each: O-H, O-H and H-H, the usual
+    rigid-water model: O-H 0.09572 nm, H-O-H 104.52 degrees) with random
+    orientations, oxygens on a cubic grid ``spacing`` nm apart."""
+    rng = np.random.default_rng(seed)
+    d_oh, th = 0.09572, math.radians(104.52)
+    local = np.array([[0.0, 0.0, 0.0], [d_oh, 0.0, 0.0], [d_oh * math.cos(th), d_oh * math.sin(th), 0.0]])
+    local = local - local.mean(axis=0)
+    side = max(1, int(math.ceil(n_mol ** (1.0 / 3.0))))
+    i = np.arange(n_mol)
+    centre = np.stack([i % side, (i // side) % side, i // (side * side)], axis=1) * spacing
+    rot = _rotations(n_mol, rng)
+    r = (centre[:, None, :] + np.einsum("mij,aj->mai", rot, local)).reshape(-1, 3)
+    base = 3 * i
+    pairs = np.stack([np.stack([base, base + 1], 1), np.stack([base, base + 2], 1),
+                      np.stack([base + 1, base + 2], 1)], axis=1).reshape(-1, 2).astype(np.int32)
+    d = np.linalg.norm(r[pairs[:, 0]] - r[pairs[:, 1]], axis=1)
+    mass = np.tile([15.999, 1.008, 1.008], n_mol)
+    kind = np.tile(np.array([0, 0, 1], np.int8), n_mol)
+    return System(pairs=pairs, d=d, mass=mass, r=r, kind=kind, elem=["O", "H", "H"] * n_mol,
+                  mol_start=base.astype(np.int64), name=f"water{n_mol}")
+
+
+def small_molecules(n_each: int, seed: int) -> System:
+    """Molecules of one to three constraints on two to four atoms: diatomics,
+    bent triatomics (two bonds), rigid waters, four-atom chains and
+    three-bond stars, ``n_each`` of each, randomly oriented."""
+    rng = np.random.default_rng(seed)
+    mols = []
+    for j in range(n_each):
+        rot = _rotations(4, rng)
+        # diatomic C-O
+        r = np.array([[0.0, 0.0, 0.0], [0.1128, 0.0, 0.0]]) @ rot[0].T
+        mols.append(System(pairs=np.array([[0, 1]], np.int32), d=np.array([0.1128]), mass=np.array([12.011, 15.999]),
+                           r=r, kind=np.zeros(1, np.int8), elem=["C", "O"]))
+        # bent H-S-H, two bonds only
+        th = math.radians(92.1)
+        r = np.array([[0.1336, 0.0, 0.0], [0.0, 0.0, 0.0], [0.1336 * math.cos(th), 0.1336 * math.sin(th), 0.0]])
+        mols.append(System(pairs=np.array([[0, 1], [1, 2]], np.int32), d=np.array([0.1336, 0.1336]),
+                           mass=np.array([1.008, 32.06, 1.008]), r=r @ rot[1].T, kind=np.zeros(2, np.int8),
+                           elem=["H", "S", "H"]))
+        # rigid water
+        w = water_box(1, seed=int(rng.integers(1 << 30)))
+        mols.append(w)
+        # C-C-C-C chain with random dihedral
+        ch = united_chain(4, int(rng.integers(1 << 30)), angles=False)
+        mols.append(ch)
+        # N with three H (bonds only)
+        hs = []
+        for k in range(3):
+            phi = 2.0 * math.pi * k / 3.0
+            hs.append([0.1012 * math.sin(math.radians(68.0)) * math.cos(phi),
+                       0.1012 * math.sin(math.radians(68.0)) * math.sin(phi), -0.1012 * math.cos(math.radians(68.0))])
+        r = np.concatenate([np.zeros((1, 3)), np.array(hs)]) @ rot[3].T
+        pairs = np.array([[0, 1], [0, 2], [0, 3]], np.int32)
+        mols.append(System(pairs=pairs, d=np.linalg.norm(r[pairs[:, 0]] - r[pairs[:, 1]], axis=1),
+                           mass=np.array([14.007, 1.008, 1.008, 1.008]), r=r, kind=np.zeros(3, np.int8),
+                           elem=["N", "H", "H", "H"]))
+    return concat(mols, spacing=0.6, name=f"small{n_each}")
+
+
 def perturb(r: np.ndarray, sigma: float, seed: int) -> np.ndarray:
     """Unconstrained positions: r + N(0, sigma^2) per coordinate."""
     rng = np.random.default_rng(seed)

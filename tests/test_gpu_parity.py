@@ -105,6 +105,36 @@ def test_angles(angles_case, name, prec, variant):
     _check(sm, ru, out, ref, f"angles/{name}")
 
 
+@pytest.fixture(scope="module")
+def small_case():
+    mols = [S.small_molecules(6, seed=41), S.water_box(300, seed=42), S.random_tree(60, seed=43)]
+    sm = S.concat(mols, spacing=3.0)
+    ru = S.perturb(sm.r, 0.003, 44)
+    return sm, ru, _oracle(sm, ru)
+
+
+@pytest.mark.parametrize("name,prec,variant", VARIANTS)
+def test_small_molecules(small_case, name, prec, variant):
+    """Molecules of one to three constraints on at most four atoms take the
+    one-thread-per-molecule path (register Newton, FP64 whatever the
+    precision); the tree in the same plan takes the general path."""
+    sm, ru, ref = small_case
+    out = solve_once(sm, ru, TOL, prec, variant)
+    _check(sm, ru, out, ref, f"small/{name}")
+
+
+def test_small_molecules_warm_start_and_failures(small_case):
+    sm, ru, ref = small_case
+    out = solve_once(sm, ru, TOL, L.PREC_FP64, lam0=ref["lam"])
+    assert np.all(out["status"] == L.OK) and np.all(out["iters"] <= 1)
+    out = solve_once(sm, ru, TOL, L.PREC_FP64, max_iter=1)
+    assert np.all(out["status"] == L.ERR_NOT_CONVERGED)
+    bad = ru.copy()
+    bad[0, 0] = np.inf
+    out = solve_once(sm, bad, TOL, L.PREC_FP64)
+    assert out["status"][0] == L.ERR_NONFINITE and np.all(out["status"][1:] == L.OK)
+
+
 def test_placements_and_lane_mappings_agree(batch_case):
     """Global-memory placement and a different lane mapping (other kernel
     instantiations) agree with the default schedule to rounding: the
