@@ -43,6 +43,36 @@ def trace_table(d: str) -> str:
     return "\n".join(out)
 
 
+def solve_spans(d: str) -> list:
+    """Per solve, the span from its queue-counter reset to the end of its
+    last solve-kernel dispatch (ns), from a ``--kernel-trace`` run.  The
+    launch groups of one solve run concurrently on several streams, so this
+    span -- not any single dispatch -- is the solve's duration."""
+    rows = _csv(os.path.join(d, "**", "*kernel_trace.csv"))
+    ev = sorted((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), r["Kernel_Name"]) for r in rows)
+    spans, start, end = [], None, None
+    for t0, t1, name in ev:
+        if "reset_counters" in name:
+            if start is not None and end is not None:
+                spans.append(end - start)
+            start, end = t0, None
+        elif start is not None and ("solve_kernel" in name or "small_kernel" in name):
+            end = t1 if end is None else max(end, t1)
+    if start is not None and end is not None:
+        spans.append(end - start)
+    return spans
+
+
+def span_table(d: str) -> str:
+    sp = solve_spans(d)
+    if not sp:
+        return "(no solves found)"
+    us = [x / 1e3 for x in sp]
+    return ("| solves | average span us | min us | max us |\n|---|---|---|---|\n"
+            f"| {len(us)} | {sum(us) / len(us):.1f} | {min(us):.1f} | {max(us):.1f} |\n\n"
+            "spans in order (us): " + ", ".join(f"{x:.1f}" for x in us))
+
+
 def _counter(d: str, name: str):
     rows = _csv(os.path.join(d, "**", "*counter_collection.csv"))
     solve, copies = 0.0, []
@@ -76,6 +106,8 @@ def main(argv=None):
     a = sys.argv[1:] if argv is None else argv
     if a and a[0] == "trace":
         print(trace_table(a[1]))
+        print()
+        print(span_table(a[1]))
     elif a and a[0] == "traffic":
         res = traffic(a[1], a[2], int(a[3]), int(a[4]), float(a[5]))
         from .build import kernel_source_hash
