@@ -148,6 +148,24 @@ ilves_status_t ilves_perturb_normal(const double* r, int32_t n_atoms, double sig
 ilves_status_t ilves_counter_add(uint64_t* counter, uint64_t delta, void* hip_stream);
 
 /*
+ * Leapfrog around the solve (constrained MD; main text, section on the
+ * constrained equations of motion, with the constraints solved for the new
+ * positions every step).  One step:
+ *   ilves_md_kick_drift:  v += h M^-1 f;  r_u = r + h v
+ *   ilves_solve(plan, r, r_u, mass, tol, r_new, ...)
+ *   ilves_md_finish:      v = (r_new - r) / h;  r = r_new
+ * All arrays are device SoA [3][n_atoms] FP64 (mass [n_atoms]); v holds the
+ * half-step velocities.  r_u and r_new must not alias r.  Units: nm, ps,
+ * amu, forces in amu nm ps^-2.  Asynchronous on hip_stream, graph-capturable.
+ * Errors: ILVES_ERR_ARG (n_atoms < 0, h not positive, null pointers),
+ * ILVES_ERR_HIP.
+ */
+ilves_status_t ilves_md_kick_drift(const double* r, double* v, const double* f, const double* mass, double h,
+                                   int32_t n_atoms, double* r_u, void* hip_stream);
+ilves_status_t ilves_md_finish(double* r, const double* r_new, double h, int32_t n_atoms, double* v,
+                               void* hip_stream);
+
+/*
  * Launch tuning of a plan (a performance knob; results agree to rounding).
  * band_block[b] is the threads per workgroup of launch band b.  Molecules
  * held wholly in LDS fall in bands 0..3 by their LDS size (<= 8 KB, <= 24 KB,

@@ -118,6 +118,10 @@ def lib() -> ctypes.CDLL:
     L.ilves_perturb_normal.argtypes = [_P, ctypes.c_int32, ctypes.c_double, ctypes.c_uint64, _P, _P, _P]
     L.ilves_perturb_normal.restype = ctypes.c_int
     L.ilves_counter_add.argtypes = [_P, ctypes.c_uint64, _P]
+    L.ilves_md_kick_drift.argtypes = [_P, _P, _P, _P, ctypes.c_double, ctypes.c_int32, _P, _P]
+    L.ilves_md_kick_drift.restype = ctypes.c_int
+    L.ilves_md_finish.argtypes = [_P, _P, ctypes.c_double, ctypes.c_int32, _P, _P]
+    L.ilves_md_finish.restype = ctypes.c_int
     L.ilves_counter_add.restype = ctypes.c_int
     L.ilves_plan_get_tuning.argtypes = [_P, ctypes.POINTER(Tuning)]
     L.ilves_plan_get_tuning.restype = ctypes.c_int
@@ -363,6 +367,23 @@ def perturb_normal(r, sigma, seed, step, r_u, stream=None):
     check(lib().ilves_perturb_normal(_dev(r, torch.float64, (3, n)), n, float(sigma), int(seed) & (2**64 - 1),
                                      _dev(step, torch.int64, (1,)), _dev(r_u, torch.float64, (3, n)),
                                      _stream(stream)))
+
+
+def md_kick_drift(r, v, f, mass, h, r_u, stream=None):
+    """v += h f / m; r_u = r + h v (float64 CUDA tensors, SoA [3, n])."""
+    import torch
+    n = r.shape[1]
+    check(lib().ilves_md_kick_drift(_dev(r, torch.float64, (3, n)), _dev(v, torch.float64, (3, n)),
+                                    _dev(f, torch.float64, (3, n)), _dev(mass, torch.float64, (n,)), float(h), n,
+                                    _dev(r_u, torch.float64, (3, n)), _stream(stream)))
+
+
+def md_finish(r, r_new, h, v, stream=None):
+    """v = (r_new - r) / h; r = r_new."""
+    import torch
+    n = r.shape[1]
+    check(lib().ilves_md_finish(_dev(r, torch.float64, (3, n)), _dev(r_new, torch.float64, (3, n)), float(h), n,
+                                _dev(v, torch.float64, (3, n)), _stream(stream)))
 
 
 def counter_add(counter, delta=1, stream=None):

@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libilves.so")
-SOURCES = ["plan.cpp", "replay.cpp", "ilves.hip", "warmstart.hip", "inputs.hip"]
+SOURCES = ["plan.cpp", "replay.cpp", "ilves.hip", "warmstart.hip", "inputs.hip", "md.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",

@@ -49,6 +49,7 @@
 #include "../../include/ilves.h"
 #include "device_plan.hpp"
 #include "inputs.hpp"
+#include "md.hpp"
 #include "plan.hpp"
 #include "warmstart.hpp"
 
@@ -1394,6 +1395,26 @@ ilves_status_t ilves_counter_add(uint64_t* counter, uint64_t delta, void* hip_st
   if (!counter) return fail(ILVES_ERR_ARG, "null argument");
   const hipError_t e = ilves_in::launch_counter_add(counter, delta, static_cast<hipStream_t>(hip_stream));
   if (e != hipSuccess) return fail(ILVES_ERR_HIP, std::string("counter kernel: ") + hipGetErrorString(e));
+  return ILVES_OK;
+}
+
+ilves_status_t ilves_md_kick_drift(const double* r, double* v, const double* f, const double* mass, double h,
+                                   int32_t n_atoms, double* r_u, void* hip_stream) {
+  if (n_atoms < 0 || !(h > 0.0) || !std::isfinite(h)) return fail(ILVES_ERR_ARG, "need n_atoms >= 0 and h > 0");
+  if (n_atoms == 0) return ILVES_OK;
+  if (!r || !v || !f || !mass || !r_u) return fail(ILVES_ERR_ARG, "null argument");
+  const hipError_t e = ilves_md::launch_kick_drift(r, v, f, mass, h, n_atoms, r_u, static_cast<hipStream_t>(hip_stream));
+  if (e != hipSuccess) return fail(ILVES_ERR_HIP, std::string("kick/drift kernel: ") + hipGetErrorString(e));
+  return ILVES_OK;
+}
+
+ilves_status_t ilves_md_finish(double* r, const double* r_new, double h, int32_t n_atoms, double* v,
+                               void* hip_stream) {
+  if (n_atoms < 0 || !(h > 0.0) || !std::isfinite(h)) return fail(ILVES_ERR_ARG, "need n_atoms >= 0 and h > 0");
+  if (n_atoms == 0) return ILVES_OK;
+  if (!r || !r_new || !v) return fail(ILVES_ERR_ARG, "null argument");
+  const hipError_t e = ilves_md::launch_finish(r, r_new, h, n_atoms, v, static_cast<hipStream_t>(hip_stream));
+  if (e != hipSuccess) return fail(ILVES_ERR_HIP, std::string("finish kernel: ") + hipGetErrorString(e));
   return ILVES_OK;
 }
 
