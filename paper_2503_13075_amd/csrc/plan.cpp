@@ -82,10 +82,13 @@ std::vector<std::vector<int32_t>> split_molecules(int32_t n_atoms, int32_t n_con
 // orderings
 
 std::vector<int32_t> order_min_degree(const std::vector<std::vector<int32_t>>& adj) {
-  // Minimum deficiency (fewest fill edges), ties broken by degree then
-  // index.  On chordal graphs -- the line graph of a tree is one -- the
-  // simplicial vertices have deficiency zero, so the order is a perfect
-  // elimination order and produces no fill at all.
+  // Minimum deficiency (fewest fill edges), ties broken by the elimination
+  // level the vertex would get now (the deepest already-eliminated vertex it
+  // depends on, plus one), then degree, then index.  On chordal graphs --
+  // the line graph of a tree is one -- the simplicial vertices have
+  // deficiency zero, so the order is a perfect elimination order and produces
+  // no fill at all; the level tie-break peels all branches in step, which
+  // keeps the elimination tree shallow (each level is a barrier on the GPU).
   const int32_t n = static_cast<int32_t>(adj.size());
   std::vector<std::vector<int32_t>> g = adj;
   auto has_edge = [&](int32_t a, int32_t b) { return std::binary_search(g[a].begin(), g[a].end(), b); };
@@ -97,11 +100,12 @@ std::vector<int32_t> order_min_degree(const std::vector<std::vector<int32_t>>& a
         if (!has_edge(nb[i], nb[j])) ++miss;
     return miss;
   };
-  using Key = std::tuple<int64_t, int32_t, int32_t>;
+  using Key = std::tuple<int64_t, int32_t, int32_t, int32_t>;
   std::set<Key> pq;
   std::vector<Key> key(n);
+  std::vector<int32_t> lev(n, 0);  // level v would get if eliminated now
   for (int32_t v = 0; v < n; ++v) {
-    key[v] = Key{deficiency(v), static_cast<int32_t>(g[v].size()), v};
+    key[v] = Key{deficiency(v), 0, static_cast<int32_t>(g[v].size()), v};
     pq.insert(key[v]);
   }
   std::vector<int32_t> order;
@@ -109,10 +113,11 @@ std::vector<int32_t> order_min_degree(const std::vector<std::vector<int32_t>>& a
   std::vector<int32_t> tmp, rest, touched;
   std::vector<char> mark(n, 0);
   while (!pq.empty()) {
-    const int32_t v = std::get<2>(*pq.begin());
+    const int32_t v = std::get<3>(*pq.begin());
     pq.erase(pq.begin());
     order.push_back(v);
     const std::vector<int32_t> nb = g[v];
+    for (int32_t u : nb) lev[u] = std::max(lev[u], lev[v] + 1);
     for (int32_t u : nb) {
       rest.clear();
       for (int32_t w : g[u])
@@ -139,7 +144,7 @@ std::vector<int32_t> order_min_degree(const std::vector<std::vector<int32_t>>& a
     for (int32_t w : touched) {
       mark[w] = 0;
       pq.erase(key[w]);
-      key[w] = Key{deficiency(w), static_cast<int32_t>(g[w].size()), w};
+      key[w] = Key{deficiency(w), lev[w], static_cast<int32_t>(g[w].size()), w};
       pq.insert(key[w]);
     }
   }
