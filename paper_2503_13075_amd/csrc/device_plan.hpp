@@ -67,6 +67,9 @@ struct DevPlan {
   const int32_t* atom_gid;
   const int32_t* inc_ptr;
   const int32_t* inc;
+  const int32_t* ga;     // per row: input index of atom a_k (same offsets as ra)
+  const int32_t* gb;     // per row: input index of atom b_k
+  const int32_t* gcoef;  // per slot: (input index of the shared atom << 1) | (sign < 0), -1 for fill
 };
 
 // A molecule of at most kSmallCons constraints on at most kSmallAtoms atoms,

@@ -241,7 +241,16 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(const DevPlan P, const int
     const int64_t nvec = Lo.total / 16;  // blocks are 16-byte aligned and padded
     const int4* gv = reinterpret_cast<const int4*>(gst);
     int4* lv = reinterpret_cast<int4*>(smem);
-    for (int64_t i = tid; i < nvec; i += BLOCK) lv[i] = gv[i];
+    // four 16-byte loads in flight per lane before their stores
+    int64_t i = tid;
+    for (; i + 3 * BLOCK < nvec; i += 4 * BLOCK) {
+      const int4 v0 = gv[i], v1 = gv[i + BLOCK], v2 = gv[i + 2 * BLOCK], v3 = gv[i + 3 * BLOCK];
+      lv[i] = v0;
+      lv[i + BLOCK] = v1;
+      lv[i + 2 * BLOCK] = v2;
+      lv[i + 3 * BLOCK] = v3;
+    }
+    for (; i < nvec; i += BLOCK) lv[i] = gv[i];
     st = smem;
   }
   const Idx* __restrict__ up_start = reinterpret_cast<const Idx*>(st + Lo.up_start);
@@ -253,7 +262,6 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(const DevPlan P, const int
   const Idx* __restrict__ prec = reinterpret_cast<const Idx*>(st + Lo.prec);
   const Idx* __restrict__ upd = reinterpret_cast<const Idx*>(st + Lo.upd);
   const Idx* __restrict__ updi = reinterpret_cast<const Idx*>(st + Lo.updi);
-  const int32_t* __restrict__ coef = P.coef + md.coef_off;
 
   // ---- workspace and values
   unsigned char* wsb = A.ws + md.ws_off;
@@ -272,8 +280,6 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(const DevPlan P, const int
   T* __restrict__ y = D + n;
 
   const int32_t* __restrict__ atom_gid = P.atom_gid + md.atom_off;
-  const int32_t* __restrict__ ra = P.ra + md.row_off;
-  const int32_t* __restrict__ rb = P.rb + md.row_off;
   const int32_t* __restrict__ cid = P.cid + md.row_off;
   const double* __restrict__ d2 = P.d2 + md.row_off;
   const double* __restrict__ rx = A.r;
@@ -281,6 +287,8 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(const DevPlan P, const int
 
   // ---- set-up: 1/m, old and unconstrained bond vectors, lambda_0,
   //      couplings, coordinate magnitude
+  // (the loops read input atom indices prepared with the plan, so each
+  // entry takes one round of gathers)
   double rmax = 0.0;
   for (int32_t a = tid; a < s; a += BLOCK) {
     const int32_t g = atom_gid[a];
@@ -291,16 +299,25 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(const DevPlan P, const int
     invm[s] = 0.0;  // fill entries point here: zero coupling
     singular = 0;
   }
+  const int32_t* __restrict__ rga = P.ga + md.row_off;
+  const int32_t* __restrict__ rgb = P.gb + md.row_off;
   double v0 = 0.0;  // max relative violation at lambda = 0 (learned start fallback test)
   for (int32_t k = tid; k < n; k += BLOCK) {
-    const int32_t ga = atom_gid[ra[k]], gb = atom_gid[rb[k]];
+    const int32_t ga = rga[k], gb = rgb[k];
     const double a0 = ux[ga] - ux[gb], a1 = ux[S + ga] - ux[S + gb], a2 = ux[2 * S + ga] - ux[2 * S + gb];
     st_rec(er + 4 * k, rx[ga] - rx[gb], rx[S + ga] - rx[S + gb], rx[2 * S + ga] - rx[2 * S + gb],
            A.warm ? A.lambda[cid[k]] : 0.0);
     u_x[k] = a0;
     u_y[k] = a1;
     u_z[k] = a2;
+    cd[k] = 1.0 / A.mass[ga] + 1.0 / A.mass[gb];
     v0 = fmax(v0, fabs(a0 * a0 + a1 * a1 + a2 * a2 - d2[k]) / (2.0 * d2[k]));
+  }
+  const int32_t* __restrict__ gcoef = P.gcoef + md.coef_off;
+  for (int32_t q = tid; q < n_up + n_l; q += BLOCK) {
+    const int32_t c = gcoef[q];
+    const double v = c < 0 ? 0.0 : 1.0 / A.mass[c >> 1];
+    cf[q] = (c & 1) ? -v : v;
   }
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {
@@ -312,12 +329,6 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(const DevPlan P, const int
     red0[tid >> 6] = v0;
   }
   __syncthreads();
-  for (int32_t k = tid; k < n; k += BLOCK) cd[k] = invm[ra[k]] + invm[rb[k]];
-  for (int32_t q = tid; q < n_up + n_l; q += BLOCK) {
-    const int32_t c = coef[q];
-    const double v = invm[c >> 1];
-    cf[q] = (c & 1) ? -v : v;
-  }
   // Rounding r' to doubles moves each output coordinate by at most
   // |r'| 2^-53, so a bond vector formed from the returned positions differs
   // from the one iterated here by at most delta = sqrt(3) rmax 2^-52.  The
@@ -974,7 +985,7 @@ ilves_status_t build_device_plan(ilves_plan* P) {
   const int32_t nm = static_cast<int32_t>(P->mols.size());
   std::vector<MolDesc> desc(nm);
   std::vector<unsigned char> pool;
-  std::vector<int32_t> coef, ra, rb, cid, atom_gid, inc_ptr, inc;
+  std::vector<int32_t> coef, ra, rb, cid, atom_gid, inc_ptr, inc, gcoef, gra, grb;
   std::vector<double> d2;
   std::vector<char> wide(nm, 0);
   int64_t fill = 0, work = 0, maxlev = 0, sumlev = 0, nslots = 0, natoms = 0, ncon = 0;
@@ -996,6 +1007,12 @@ ilves_status_t build_device_plan(ilves_plan* P) {
     D.coef_off = static_cast<int32_t>(coef.size());
     coef.insert(coef.end(), M.ucoef.begin(), M.ucoef.end());
     coef.insert(coef.end(), M.lcoef.begin(), M.lcoef.end());
+    for (const std::vector<int32_t>* cv : {&M.ucoef, &M.lcoef})
+      for (int32_t c : *cv) gcoef.push_back((c >> 1) >= M.s ? -1 : ((M.atom_gid[c >> 1] << 1) | (c & 1)));
+    for (int32_t k = 0; k < M.n; ++k) {
+      gra.push_back(M.atom_gid[M.ra[k]]);
+      grb.push_back(M.atom_gid[M.rb[k]]);
+    }
     D.row_off = static_cast<int32_t>(ra.size());
     ra.insert(ra.end(), M.ra.begin(), M.ra.end());
     rb.insert(rb.end(), M.rb.begin(), M.rb.end());
@@ -1200,6 +1217,9 @@ ilves_status_t build_device_plan(ilves_plan* P) {
   const size_t o_desc = push_array(blob, desc);
   const size_t o_pool = push_array(blob, pool);
   const size_t o_coef = push_array(blob, coef);
+  const size_t o_gcoef = push_array(blob, gcoef);
+  const size_t o_gra = push_array(blob, gra);
+  const size_t o_grb = push_array(blob, grb);
   const size_t o_ra = push_array(blob, ra);
   const size_t o_rb = push_array(blob, rb);
   const size_t o_cid = push_array(blob, cid);
@@ -1219,6 +1239,9 @@ ilves_status_t build_device_plan(ilves_plan* P) {
   P->dp.mol = reinterpret_cast<const MolDesc*>(b + o_desc);
   P->dp.ix = b + o_pool;
   P->dp.coef = reinterpret_cast<const int32_t*>(b + o_coef);
+  P->dp.gcoef = reinterpret_cast<const int32_t*>(b + o_gcoef);
+  P->dp.ga = reinterpret_cast<const int32_t*>(b + o_gra);
+  P->dp.gb = reinterpret_cast<const int32_t*>(b + o_grb);
   P->dp.ra = reinterpret_cast<const int32_t*>(b + o_ra);
   P->dp.rb = reinterpret_cast<const int32_t*>(b + o_rb);
   P->dp.cid = reinterpret_cast<const int32_t*>(b + o_cid);
