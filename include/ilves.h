@@ -53,7 +53,10 @@ typedef enum {
   ILVES_ERR_SINGULAR = 5,       /* per molecule: a pivot vanished (redundant constraints)   */
   ILVES_ERR_NOT_CONVERGED = 6,  /* per molecule: iteration cap reached before tol           */
   ILVES_ERR_NONFINITE = 7,      /* per molecule: NaN or Inf met in the residual             */
-  ILVES_ERR_UNSUPPORTED = 8     /* option combination not built into this library           */
+  ILVES_ERR_UNSUPPORTED = 8,    /* option combination not built into this library           */
+  ILVES_ERR_TIMEOUT = 9         /* per molecule: the workgroups of a split molecule did not
+                                   meet at a barrier within its wait limit; the plan must be
+                                   recreated                                                */
 } ilves_status_t;
 
 enum { ILVES_PREC_FP64 = 0, ILVES_PREC_MIXED = 1 };
@@ -77,7 +80,12 @@ typedef struct {
                             fit in LDS always use 512 or 1024                   */
   int32_t lds_limit;     /* bytes of LDS a molecule may use; 0 = auto            */
   int32_t ordering;      /* 0 auto, 1 minimum degree, 2 nested dissection        */
-  int32_t reserved;
+  int32_t split_rows;    /* molecules with more constraints than this are split
+                            across several workgroups (block-bordered LU with a
+                            Schur complement on the constraints that join the
+                            parts); 0 = automatic (4096), < 0 = never          */
+  int32_t split_part_rows; /* constraints per part of a split molecule;
+                            0 = automatic (split_rows / 4, at least 64)         */
 } ilves_options_t;
 
 /* Fills *opt with defaults (FP64 Newton, lambda_0 = 0, automatic schedule). */
@@ -112,9 +120,11 @@ int32_t ilves_plan_num_molecules(ilves_plan_t plan);
  *   [3] stored factor entries, [4] fill entries, [5] factor updates,
  *   [6] largest level count, [7] sum of level counts, [8] molecules whose factor fits in
  *   LDS (mixed precision), [9] the others, [10] workspace bytes,
- *   [11] plan bytes on the device.
+ *   [11] plan bytes on the device, [12] molecules split across workgroups,
+ *   [13] workgroups (parts) of the split molecules, [14] largest separator
+ *   (constraints joining the parts of one molecule).
  */
-#define ILVES_STAT_COUNT 12
+#define ILVES_STAT_COUNT 15
 ilves_status_t ilves_plan_stats(ilves_plan_t plan, int64_t* stats);
 
 /*
@@ -289,14 +299,15 @@ ilves_status_t ilves_mlp_adam_f32(float* params, const float* grad, float* m, fl
  * Planner diagnostics (host only, no GPU needed; not a solve path -- the
  * solve entry points never call it).  Plans the topology like
  * ilves_plan_create and replays, on the host and in the same order of
- * operations, the level schedule that the device kernel executes.  Used to
- * test the ordering, symbolic factorisation and task lists on machines
- * without a GPU.
+ * operations, the level schedule that the device kernel executes, including
+ * the block-bordered scheme of molecules split across workgroups (options
+ * split_rows / split_part_rows).  Used to test the ordering, symbolic
+ * factorisation, task lists and splits on machines without a GPU.
  *   mass [n_atoms], r, r_u, r_out [3][n_atoms], lambda [n_constraints]: host
  *   iters, status: host int32 arrays with room for n_constraints entries
  *   (at least the number of molecules); *n_molecules receives that number
- *   schedule_stats: host int64 [5] (molecules, factor entries, factor updates,
- *   largest level count, fill entries) or NULL
+ *   schedule_stats: host int64 [6] (molecules, factor entries, factor updates,
+ *   largest level count, fill entries, split molecules) or NULL
  */
 ilves_status_t ilves_plan_replay_host(int32_t n_atoms, int32_t n_constraints, const int32_t* pairs,
                                       const double* d, const ilves_options_t* opt, const double* mass,

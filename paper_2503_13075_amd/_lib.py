@@ -17,12 +17,13 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libilves.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "ilves.h")
 
-OK, ERR_ARG, ERR_TOPOLOGY, ERR_HIP, ERR_NOMEM, ERR_SINGULAR, ERR_NOT_CONVERGED, ERR_NONFINITE, ERR_UNSUPPORTED = range(9)
+OK, ERR_ARG, ERR_TOPOLOGY, ERR_HIP, ERR_NOMEM, ERR_SINGULAR, ERR_NOT_CONVERGED, ERR_NONFINITE, ERR_UNSUPPORTED, ERR_TIMEOUT = range(10)
 PREC_FP64, PREC_MIXED = 0, 1
 VARIANT_NEWTON, VARIANT_CHORD = 0, 1
 WARM_ZERO, WARM_MLP, WARM_CALLER = 0, 1, 2
 STAT_NAMES = ["molecules", "constraints", "atoms", "factor_entries", "fill", "updates", "max_levels",
-              "sum_levels", "mol_lds", "mol_workspace", "workspace_bytes", "plan_bytes"]
+              "sum_levels", "mol_lds", "mol_workspace", "workspace_bytes", "plan_bytes", "split_molecules",
+              "split_parts", "max_separator"]
 
 
 class IlvesError(RuntimeError):
@@ -34,7 +35,7 @@ class IlvesError(RuntimeError):
 class Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("variant", ctypes.c_int32), ("max_iter", ctypes.c_int32),
                 ("warm_start", ctypes.c_int32), ("block_threads", ctypes.c_int32), ("lds_limit", ctypes.c_int32),
-                ("ordering", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("ordering", ctypes.c_int32), ("split_rows", ctypes.c_int32), ("split_part_rows", ctypes.c_int32)]
 
 
 class Tuning(ctypes.Structure):
@@ -141,11 +142,12 @@ def _ptr(a: np.ndarray, ctype):
 
 
 def make_options(precision=PREC_FP64, variant=VARIANT_NEWTON, max_iter=0, warm_start=WARM_ZERO,
-                 block_threads=0, lds_limit=0, ordering=0) -> Options:
+                 block_threads=0, lds_limit=0, ordering=0, split_rows=0, split_part_rows=0) -> Options:
     o = Options()
     lib().ilves_default_options(ctypes.byref(o))
     o.precision, o.variant, o.max_iter, o.warm_start = precision, variant, max_iter, warm_start
     o.block_threads, o.lds_limit, o.ordering = block_threads, lds_limit, ordering
+    o.split_rows, o.split_part_rows = split_rows, split_part_rows
     return o
 
 
@@ -158,7 +160,7 @@ def _topology(pairs, d):
 
 
 def replay_host(n_atoms, pairs, d, mass, r_soa, ru_soa, tol, precision=PREC_FP64, variant=VARIANT_NEWTON,
-                max_iter=0, ordering=0):
+                max_iter=0, ordering=0, split_rows=0, split_part_rows=0):
     """Runs the planner and replays the device schedule on the host
     (planner diagnostics; see ilves_plan_replay_host)."""
     L = lib()
@@ -172,8 +174,8 @@ def replay_host(n_atoms, pairs, d, mass, r_soa, ru_soa, tol, precision=PREC_FP64
     iters = np.zeros(max(n, 1), np.int32)
     status = np.zeros(max(n, 1), np.int32)
     nm = ctypes.c_int32(0)
-    st = np.zeros(5, np.int64)
-    o = make_options(ordering=ordering)
+    st = np.zeros(6, np.int64)
+    o = make_options(ordering=ordering, split_rows=split_rows, split_part_rows=split_part_rows)
     check(L.ilves_plan_replay_host(n_atoms, n, _ptr(pairs, ctypes.c_int32), _ptr(d, ctypes.c_double), ctypes.byref(o),
                                    _ptr(mass, ctypes.c_double), _ptr(r_soa, ctypes.c_double),
                                    _ptr(ru_soa, ctypes.c_double), tol, precision, variant, max_iter,
@@ -182,20 +184,21 @@ def replay_host(n_atoms, pairs, d, mass, r_soa, ru_soa, tol, precision=PREC_FP64
                                    _ptr(st, ctypes.c_int64)))
     k = nm.value
     return {"r_out": r_out, "lam": lam, "iters": iters[:k].copy(), "status": status[:k].copy(),
-            "stats": dict(zip(["molecules", "factor_entries", "updates", "max_levels", "fill"], st.tolist()))}
+            "stats": dict(zip(["molecules", "factor_entries", "updates", "max_levels", "fill", "split"], st.tolist()))}
 
 
 class Plan:
     """A planned topology on the current GPU (wraps ilves_plan_create)."""
 
     def __init__(self, n_atoms, pairs, d, precision=PREC_FP64, variant=VARIANT_NEWTON, max_iter=0,
-                 warm_start=WARM_ZERO, block_threads=0, lds_limit=0, ordering=0):
+                 warm_start=WARM_ZERO, block_threads=0, lds_limit=0, ordering=0, split_rows=0, split_part_rows=0):
         L = lib()
         self._L = L
         pairs, d = _topology(pairs, d)
         self.n_atoms = int(n_atoms)
         self.n_constraints = int(pairs.shape[0])
-        o = make_options(precision, variant, max_iter, warm_start, block_threads, lds_limit, ordering)
+        o = make_options(precision, variant, max_iter, warm_start, block_threads, lds_limit, ordering, split_rows,
+                         split_part_rows)
         h = _P()
         check(L.ilves_plan_create(self.n_atoms, self.n_constraints, _ptr(pairs, ctypes.c_int32),
                                   _ptr(d, ctypes.c_double), ctypes.byref(o), ctypes.byref(h)))

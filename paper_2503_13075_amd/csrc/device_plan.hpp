@@ -70,7 +70,70 @@ struct DevPlan {
   const int32_t* ga;     // per row: input index of atom a_k (same offsets as ra)
   const int32_t* gb;     // per row: input index of atom b_k
   const int32_t* gcoef;  // per slot: (input index of the shared atom << 1) | (sign < 0), -1 for fill
+  // molecules split across workgroups (one workgroup per part)
+  const struct SplitPart* split;  // per part, in launch order
+  const struct SepRow* sep;       // separator rows of every split molecule
+  const int32_t* sadj;            // separator couplings: {other separator row, coupling} pairs
+  const int32_t* bsep;            // per border row: separator row | (1 << 30 when the part owns it)
+  const int32_t* ext_ptr;         // per border row: first external coupling (CSR, one extra entry per part)
+  const int64_t* ext_rec;         // external coupling: offset (doubles) of the holder's record in the workspace
+  const int32_t* ext_coef;        // external coupling: (input atom << 1) | (sign < 0)
 };
+
+// One part of a split molecule (block-bordered LU, see the solve kernel).
+struct SplitPart {
+  int32_t desc;     // descriptor of the part's rows (MolDesc index)
+  int32_t report;   // molecule index for iters / status / fallback
+  int32_t part, n_parts;
+  int32_t n_int;    // interior rows [0, n_int), border rows [n_int, n)
+  int32_t h_int;    // levels [0, h_int) hold the interior rows
+  int32_t s_own;    // local atoms [0, s_own) are the part's own
+  int32_t m;        // separator rows of the molecule
+  int32_t bsep_off;  // into bsep (n - n_int entries)
+  int32_t ext_off;   // into ext_ptr (n - n_int + 1 entries)
+  int32_t sep_off;   // first SepRow of the molecule
+  int32_t ew_off;    // doubles from the exchange area to this part's E block (nb*nb, then w: nb)
+  int64_t xch;       // byte offset of the molecule's exchange area in the workspace
+  int32_t lds_extra[2];  // byte offset of the split scratch in dynamic LDS (FP64, FP32 values)
+};
+static_assert(sizeof(SplitPart) == 64, "SplitPart is one 64-byte record");
+
+// A separator row: the two parts holding it as a border row (part0 owns
+// it), its border index in each, its atoms and its separator couplings.
+struct SepRow {
+  int32_t part0, part1;  // part indices within the molecule
+  int32_t loc0, loc1;
+  int32_t ga, gb;
+  int32_t adj_off, adj_cnt;  // into sadj (pairs)
+  int32_t ew0, ew1;          // E/w blocks of the two parts (doubles from the exchange area)
+  int32_t nb0, nb1;          // border rows of the two parts
+};
+
+// Exchange area of a split molecule in the workspace (byte offsets):
+//   [0, 64)          barrier: arrival count, generation, poisoned flag
+//   PartX[n_parts]   per part: max relative violation, violation at
+//                    lambda = 0, singular flag
+//   SepX[m]          per separator row (owner writes): bond vector e', g, e
+//   E/w blocks       per part: Schur contribution E (nb x nb), reduced
+//                    right-hand side contribution w (nb)
+struct PartX {
+  double viol, rel0;
+  int32_t singular, pad[3];
+};
+struct SepX {
+  double ep[3], g, e[3], pad;
+};
+__host__ __device__ inline int64_t xch_partx(int32_t) { return 64; }
+__host__ __device__ inline int64_t xch_sepx(int32_t n_parts) { return 64 + 32 * static_cast<int64_t>(n_parts); }
+__host__ __device__ inline int64_t xch_ew(int32_t n_parts, int32_t m) { return xch_sepx(n_parts) + 64 * static_cast<int64_t>(m); }
+
+// Split scratch in LDS after the factor values (doubles): the separator
+// system [m][m + 1], its solution z[m], and per border row the saved
+// residual gB[nb]; the border block of the matrix, the unit-lower and the
+// upper factors ([nb][nb] each).
+__host__ __device__ inline int64_t split_lds_bytes(int32_t m, int32_t nb) {
+  return 8 * (static_cast<int64_t>(m) * (m + 1) + m + nb + 3 * static_cast<int64_t>(nb) * nb);
+}
 
 // A molecule of at most kSmallCons constraints on at most kSmallAtoms atoms,
 // solved by one thread with the whole Newton loop in registers (water-,

@@ -162,6 +162,68 @@ __device__ __forceinline__ MolDesc uni(const MolDesc& m) {
   return r;
 }
 
+__device__ __forceinline__ SplitPart uni(const SplitPart& p) {
+  SplitPart r;
+  r.desc = uni(p.desc);
+  r.report = uni(p.report);
+  r.part = uni(p.part);
+  r.n_parts = uni(p.n_parts);
+  r.n_int = uni(p.n_int);
+  r.h_int = uni(p.h_int);
+  r.s_own = uni(p.s_own);
+  r.m = uni(p.m);
+  r.bsep_off = uni(p.bsep_off);
+  r.ext_off = uni(p.ext_off);
+  r.sep_off = uni(p.sep_off);
+  r.ew_off = uni(p.ew_off);
+  r.xch = uni(p.xch);
+  r.lds_extra[0] = uni(p.lds_extra[0]);
+  r.lds_extra[1] = uni(p.lds_extra[1]);
+  return r;
+}
+
+// Barrier of the workgroups of one split molecule (all resident: the
+// launch never holds more of them than fit on the device at once).  Every
+// wave first makes its global writes visible device-wide; one lane per
+// workgroup arrives on the counter, the last arrival resets it and advances
+// the generation, the others wait for the generation to change; the
+// acquire fence then drops stale cached lines.  The wait is bounded: after
+// kSpinCap polls (seconds) the workgroup marks the molecule poisoned, which
+// also releases every other waiter, and reports false.
+constexpr int32_t kSpinCap = 1 << 22;
+__device__ bool grid_barrier(uint32_t* bar, int32_t n_parts, int32_t* flag) {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int32_t good = __hip_atomic_load(bar + 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u;
+    if (good) {
+      const uint32_t g = __hip_atomic_load(bar + 1, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+      const uint32_t a = __hip_atomic_fetch_add(bar, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+      if (a == static_cast<uint32_t>(n_parts - 1)) {
+        __hip_atomic_store(bar, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(bar + 1, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      } else {
+        for (int32_t i = 0; __hip_atomic_load(bar + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g; ++i) {
+          if (__hip_atomic_load(bar + 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
+            good = 0;
+            break;
+          }
+          if (i >= kSpinCap) {
+            __hip_atomic_store(bar + 2, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            good = 0;
+            break;
+          }
+          __builtin_amdgcn_s_sleep(2);
+        }
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    *flag = good;
+  }
+  __syncthreads();
+  return __builtin_amdgcn_readfirstlane(*flag) != 0;
+}
+
 // per-row record of the workspace: old bond vector and lambda, read with
 // two 16-byte loads
 struct Rec {
@@ -207,7 +269,23 @@ template <> __device__ inline float pivot_eps<float>() { return 1e-6f; }
 // ---------------------------------------------------------------------------
 // the solve kernel: one workgroup per molecule
 
-template <typename T, typename Idx, int MODE, int BLOCK>
+//
+// SPLIT: one workgroup per part of a molecule split across workgroups
+// (block-bordered LU).  A part holds its interior rows and its border rows
+// (the separator rows touching its atoms), ordered so that the border rows
+// come last in levels of their own.  Per Newton iteration every part forms
+// its residuals (a border row also gathers the coupled rows that other parts
+// hold), factors its rows with the forward substitution fused, and takes
+// from the border block of its factors the Schur contribution
+//   E_i = L_BB U_BB - A_BB = -A_BI A_II^-1 A_IB
+// and the reduced right-hand side contribution w_i = g_B - L_BB y_B =
+// A_BI A_II^-1 g_I.  After a barrier every workgroup reads all parts'
+// violations (the same convergence decision everywhere), assembles the
+// dense separator system (A_SS + sum E_i) z_S = g_S - sum w_i from the
+// published border data in the same order, and solves it; each part then
+// sets its border unknowns to z_S, substitutes backward through its interior
+// levels and updates lambda; a second barrier publishes the new lambdas.
+template <typename T, typename Idx, int MODE, int BLOCK, bool SPLIT = false>
 __global__ void __launch_bounds__(BLOCK) solve_kernel(const DevPlan P, const int32_t* __restrict__ mols,
                                                       const int32_t count, int32_t* __restrict__ counter,
                                                       const SolveArgs A) {
@@ -221,11 +299,19 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(const DevPlan P, const int
   // persistent workgroup: take molecules (largest first) from the queue
   // until it is empty; every wave of the workgroup leaves together
   for (;;) {
-  if (tid == 0) next_slot = atomicAdd(counter, 1);
-  __syncthreads();
-  const int32_t slot = uni(next_slot);
-  if (slot >= count) break;
-  const int32_t m_idx = uni(mols[slot]);
+  int32_t slot;
+  if constexpr (SPLIT) {
+    slot = blockIdx.x;
+  } else {
+    if (tid == 0) next_slot = atomicAdd(counter, 1);
+    __syncthreads();
+    slot = uni(next_slot);
+    if (slot >= count) break;
+  }
+  SplitPart sp{};
+  if constexpr (SPLIT) sp = uni(P.split[slot]);
+  const int32_t m_idx = SPLIT ? sp.desc : uni(mols[slot]);
+  const int32_t report = SPLIT ? sp.report : m_idx;
   const MolDesc md = uni(P.mol[m_idx]);
   const int32_t n = md.n, s = md.s, n_up = md.n_up, n_l = md.n_l, n_upd = md.n_upd, H = md.n_levels;
   const int32_t n_pl = md.n_pl;
@@ -279,6 +365,23 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(const DevPlan P, const int
   T* __restrict__ D = F + n_up + n_l;
   T* __restrict__ y = D + n;
 
+  // split parts: exchange area of the molecule and the LDS scratch
+  const int32_t ni = SPLIT ? sp.n_int : n;  // interior rows
+  const int32_t nb = n - ni;                // border rows
+  const int32_t ms = SPLIT ? sp.m : 0;      // separator rows
+  unsigned char* xb = A.ws + (SPLIT ? sp.xch : 0);
+  uint32_t* bar = reinterpret_cast<uint32_t*>(xb);
+  PartX* pxa = reinterpret_cast<PartX*>(xb + 64);
+  SepX* sxa = reinterpret_cast<SepX*>(xb + xch_sepx(SPLIT ? sp.n_parts : 0));
+  double* xd = reinterpret_cast<double*>(xb);
+  double* ew = xd + (SPLIT ? sp.ew_off : 0);  // this part's E (nb x nb), then w (nb)
+  double* Sm = reinterpret_cast<double*>(smem + (SPLIT ? sp.lds_extra[sizeof(T) == 4 ? 1 : 0] : 0));  // [ms][ms + 1]
+  double* zs = Sm + ms * (ms + 1);
+  double* gB = zs + ms;
+  double* Ab = gB + nb;
+  double* Lb = Ab + nb * nb;
+  double* Ub = Lb + nb * nb;
+
   const int32_t* __restrict__ atom_gid = P.atom_gid + md.atom_off;
   const int32_t* __restrict__ cid = P.cid + md.row_off;
   const double* __restrict__ d2 = P.d2 + md.row_off;
@@ -305,8 +408,19 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(const DevPlan P, const int
   for (int32_t k = tid; k < n; k += BLOCK) {
     const int32_t ga = rga[k], gb = rgb[k];
     const double a0 = ux[ga] - ux[gb], a1 = ux[S + ga] - ux[S + gb], a2 = ux[2 * S + ga] - ux[2 * S + gb];
-    st_rec(er + 4 * k, rx[ga] - rx[gb], rx[S + ga] - rx[S + gb], rx[2 * S + ga] - rx[2 * S + gb],
-           A.warm ? A.lambda[cid[k]] : 0.0);
+    const double e0 = rx[ga] - rx[gb], e1 = rx[S + ga] - rx[S + gb], e2 = rx[2 * S + ga] - rx[2 * S + gb];
+    st_rec(er + 4 * k, e0, e1, e2, A.warm ? A.lambda[cid[k]] : 0.0);
+    if constexpr (SPLIT) {
+      if (k >= ni) {
+        const int32_t v = P.bsep[sp.bsep_off + (k - ni)];
+        if (v >> 30) {
+          SepX& X = sxa[v & 0x3fffffff];
+          X.e[0] = e0;
+          X.e[1] = e1;
+          X.e[2] = e2;
+        }
+      }
+    }
     u_x[k] = a0;
     u_y[k] = a1;
     u_z[k] = a2;
@@ -481,9 +595,9 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(const DevPlan P, const int
       __syncthreads();
     }
   };
-  // backward substitution, levels H-1 .. 0
-  auto back_sweep = [&]() {
-    for (int32_t h = H - 1; h >= 0; --h) {
+  // backward substitution, levels h_top-1 .. 0
+  auto back_sweep = [&](int32_t h_top) {
+    for (int32_t h = h_top - 1; h >= 0; --h) {
       const int32_t k0 = uni(static_cast<int32_t>(lvh[4 * h])), k1 = uni(static_cast<int32_t>(lvh[4 * h + 1]));
       for (int32_t k = k0 + tid; k < k1; k += BLOCK) {
         T acc = y[k];
@@ -509,6 +623,146 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(const DevPlan P, const int
     }
   };
 
+
+  // ---- split parts: border block, Schur contribution, separator system
+  // border block of the matrix (rows built, not yet factored), one thread
+  // per border row
+  auto save_border = [&]() {
+    for (int32_t i = tid; i < nb * nb; i += BLOCK) Ab[i] = 0.0;
+    __syncthreads();
+    for (int32_t j = tid; j < nb; j += BLOCK) {
+      const int32_t k = ni + j;
+      Ab[j * nb + j] = static_cast<double>(D[k]);
+      for (int32_t q = up_start[k]; q < up_start[k + 1]; ++q) Ab[j * nb + (ucol[q] - ni)] = static_cast<double>(F[q]);
+      for (int32_t t = l_start[k]; t < l_start[k + 1]; ++t) {
+        const int32_t i = lpair[2 * t];
+        if (i >= ni) Ab[j * nb + (i - ni)] = static_cast<double>(F[t]);
+      }
+    }
+    __syncthreads();
+  };
+  // factors of the border block (after the factorisation) and, with schur,
+  // the contribution E = L_BB U_BB - A_BB to the exchange area
+  auto border_factors = [&](bool schur) {
+    for (int32_t i = tid; i < nb * nb; i += BLOCK) {
+      Lb[i] = 0.0;
+      Ub[i] = 0.0;
+    }
+    __syncthreads();
+    for (int32_t j = tid; j < nb; j += BLOCK) {
+      const int32_t k = ni + j;
+      Lb[j * nb + j] = 1.0;
+      Ub[j * nb + j] = 1.0 / static_cast<double>(D[k]);
+      for (int32_t q = up_start[k]; q < up_start[k + 1]; ++q) Ub[j * nb + (ucol[q] - ni)] = static_cast<double>(F[q]);
+      for (int32_t t = l_start[k]; t < l_start[k + 1]; ++t) {
+        const int32_t i = lpair[2 * t];
+        if (i >= ni) Lb[j * nb + (i - ni)] = static_cast<double>(F[t]) * static_cast<double>(D[i]);
+      }
+    }
+    __syncthreads();
+    if (schur)
+      for (int32_t i = tid; i < nb * nb; i += BLOCK) {
+        const int32_t p = i / nb, q = i - p * nb;
+        double acc = 0.0;
+        for (int32_t t = 0; t <= (p < q ? p : q); ++t) acc += Lb[p * nb + t] * Ub[t * nb + q];
+        ew[i] = acc - Ab[i];
+      }
+  };
+  // reduced right-hand side contribution w = g_B - L_BB y_B (after the
+  // forward substitution)
+  auto border_rhs = [&]() {
+    for (int32_t p = tid; p < nb; p += BLOCK) {
+      double acc = static_cast<double>(y[ni + p]);
+      for (int32_t t = 0; t < p; ++t) acc += Lb[p * nb + t] * static_cast<double>(y[ni + t]);
+      ew[nb * nb + p] = gB[p] - acc;
+    }
+  };
+  // separator matrix A_SS (at the owners' bond vectors e', or e for the
+  // chord) plus the parts' contributions, into Sm[:, :ms]
+  auto assemble = [&](bool at_e) {
+    for (int32_t i = tid; i < ms * (ms + 1); i += BLOCK) Sm[i] = 0.0;
+    __syncthreads();
+    for (int32_t b = tid; b < ms; b += BLOCK) {
+      const SepRow R = P.sep[sp.sep_off + b];
+      const SepX& X = sxa[b];
+      const double p0 = at_e ? X.e[0] : X.ep[0], p1 = at_e ? X.e[1] : X.ep[1], p2 = at_e ? X.e[2] : X.ep[2];
+      Sm[b * (ms + 1) + b] = (1.0 / A.mass[R.ga] + 1.0 / A.mass[R.gb]) * (p0 * X.e[0] + p1 * X.e[1] + p2 * X.e[2]);
+      for (int32_t a = 0; a < R.adj_cnt; ++a) {
+        const int32_t c = P.sadj[2 * (R.adj_off + a)], cc = P.sadj[2 * (R.adj_off + a) + 1];
+        const SepX& Y = sxa[c];
+        Sm[b * (ms + 1) + c] = ((cc & 1) ? -1.0 : 1.0) / A.mass[cc >> 1] * (p0 * Y.e[0] + p1 * Y.e[1] + p2 * Y.e[2]);
+      }
+    }
+    __syncthreads();
+    for (int32_t i = tid; i < ms * ms; i += BLOCK) {
+      const int32_t b = i / (ms > 0 ? ms : 1), c = i - b * ms;  // (ms > 0 whenever this runs)
+      const SepRow Rb = P.sep[sp.sep_off + b], Rc = P.sep[sp.sep_off + c];
+      double acc = Sm[b * (ms + 1) + c];
+      for (int u = 0; u < 2; ++u) {
+        const int32_t g = u ? Rb.part1 : Rb.part0, lb = u ? Rb.loc1 : Rb.loc0;
+        const int32_t eo = u ? Rb.ew1 : Rb.ew0, nbg = u ? Rb.nb1 : Rb.nb0;
+        for (int v = 0; v < 2; ++v)
+          if ((v ? Rc.part1 : Rc.part0) == g) acc += xd[eo + lb * nbg + (v ? Rc.loc1 : Rc.loc0)];
+      }
+      Sm[b * (ms + 1) + c] = acc;
+    }
+    __syncthreads();
+  };
+  // elimination without pivoting of the first cols columns (ms + 1: with
+  // the right-hand side); false when a pivot vanishes (every thread tests
+  // the same row, so the answer is uniform)
+  auto eliminate = [&](int32_t cols) -> bool {
+    for (int32_t p = 0; p < ms; ++p) {
+      const double piv = Sm[p * (ms + 1) + p];
+      double a0 = 0.0;
+      for (int32_t c = 0; c < ms; ++c) a0 = fmax(a0, fabs(Sm[p * (ms + 1) + c]));
+      if (!(fabs(piv) > 1e-13 * a0)) return false;
+      const int32_t w = cols - p - 1;
+      for (int32_t i = tid; i < (ms - p - 1) * w; i += BLOCK) {
+        const int32_t q = p + 1 + i / w, c = p + 1 + i % w;
+        const double f = Sm[q * (ms + 1) + p] / piv;
+        Sm[q * (ms + 1) + c] -= f * Sm[p * (ms + 1) + c];
+      }
+      __syncthreads();
+    }
+    return true;
+  };
+  // separator right-hand side g_S - sum_i w_i into zs (and the last column
+  // of Sm for the Newton elimination)
+  auto sep_rhs = [&]() {
+    for (int32_t b = tid; b < ms; b += BLOCK) {
+      const SepRow R = P.sep[sp.sep_off + b];
+      const double r = sxa[b].g - xd[R.ew0 + R.nb0 * R.nb0 + R.loc0] - xd[R.ew1 + R.nb1 * R.nb1 + R.loc1];
+      zs[b] = r;
+      Sm[b * (ms + 1) + ms] = r;
+    }
+    __syncthreads();
+  };
+  // triangular solves of the eliminated system by wave 0 (one lane per
+  // separator row, ms <= 64): forward (chord: the right-hand side was not
+  // eliminated with the matrix) then backward; z in zs
+  auto sep_solve = [&](bool forward) {
+    if (tid < 64) {
+      double r = tid < ms ? (forward ? zs[tid] : Sm[tid * (ms + 1) + ms]) : 0.0;
+      if (forward)
+        for (int32_t p = 0; p < ms; ++p) {
+          const double rp = __shfl(r, p, 64);
+          if (tid > p && tid < ms) r -= Sm[tid * (ms + 1) + p] / Sm[p * (ms + 1) + p] * rp;
+        }
+      if (tid < ms) zs[tid] = r;
+      for (int32_t q = ms - 1; q >= 0; --q) {
+        double part = 0.0;
+        for (int32_t c = q + 1 + tid; c < ms; c += 64) part -= Sm[q * (ms + 1) + c] * zs[c];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off, 64);
+        if (tid == 0) zs[q] = (zs[q] + part) / Sm[q * (ms + 1) + q];
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      }
+    }
+    __syncthreads();
+  };
+
   // ---- chord: factor A(r, r) once
   if (A.chord) {
     for (int32_t k = tid; k < n; k += BLOCK) {
@@ -516,15 +770,44 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(const DevPlan P, const int
       build_row(k, ek.x, ek.y, ek.z);
     }
     __syncthreads();
+    if constexpr (SPLIT) save_border();
     factor_sweep(std::true_type{}, std::false_type{});
+    if constexpr (SPLIT) border_factors(true);
   }
 
   int32_t it = 0;
   int32_t st_code = ILVES_ERR_NOT_CONVERGED;
   int32_t fell_back = 0, rises = 0;
   double prev_gmax = INFINITY;
-  const bool chord_singular = A.chord && uni(singular);
-  if (chord_singular) st_code = ILVES_ERR_SINGULAR;
+  bool chord_singular = A.chord && uni(singular);
+  if constexpr (SPLIT) {
+    // every part's set-up (records, owners' bond vectors, chord factors) is
+    // published before anything is read across parts
+    if (tid == 0) {
+      pxa[sp.part].rel0 = rel_zero;
+      pxa[sp.part].singular = singular;
+    }
+    bool stop = !grid_barrier(bar, sp.n_parts, &next_slot);
+    if (stop) {
+      st_code = ILVES_ERR_TIMEOUT;
+    } else {
+      int32_t sing = 0;
+      for (int32_t q = 0; q < sp.n_parts; ++q) {
+        rel_zero = fmax(rel_zero, pxa[q].rel0);
+        sing |= pxa[q].singular;
+      }
+      rel_zero = uni(rel_zero);
+      chord_singular = A.chord && uni(sing) != 0;
+      if (A.chord && !chord_singular) {
+        assemble(true);
+        chord_singular = !eliminate(ms);
+      }
+      if (chord_singular) st_code = ILVES_ERR_SINGULAR;
+    }
+    stop = stop || chord_singular;
+    chord_singular = stop;
+  }
+  if (!SPLIT && chord_singular) st_code = ILVES_ERR_SINGULAR;
   while (!chord_singular) {
     // ---- residual at the current lambda; Newton: rebuild the matrix rows.
     //      The neighbour entries are gathered kBatchN at a time; when a row
@@ -559,12 +842,38 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(const DevPlan P, const int
           }
         }
       }
+      if constexpr (SPLIT) {
+        if (k >= ni) {  // couplings to rows held by other parts
+          const int32_t e0 = P.ext_ptr[sp.ext_off + (k - ni)], e1 = P.ext_ptr[sp.ext_off + (k - ni) + 1];
+          for (int32_t e = e0; e < e1; ++e) {
+            const Rec h = ld_rec(reinterpret_cast<const double*>(A.ws) + P.ext_rec[e]);
+            const int32_t cc = P.ext_coef[e];
+            const double c = ((cc & 1) ? -1.0 : 1.0) / A.mass[cc >> 1] * h.l;
+            px -= c * h.x;
+            py -= c * h.y;
+            pz -= c * h.z;
+          }
+        }
+      }
       const double pp = px * px + py * py + pz * pz;
       const double g = 0.5 * (pp - d2[k]);
       double rel = (fabs(g) + sqrt(pp) * delta + delta2) / d2[k];
       if (!(rel <= DBL_MAX)) rel = INFINITY;  // NaN or Inf
       vmax = fmax(vmax, rel);
       y[k] = static_cast<T>(g);
+      if constexpr (SPLIT) {
+        if (k >= ni) {
+          gB[k - ni] = static_cast<double>(static_cast<T>(g));
+          const int32_t v = P.bsep[sp.bsep_off + (k - ni)];
+          if (v >> 30) {
+            SepX& X = sxa[v & 0x3fffffff];
+            X.ep[0] = px;
+            X.ep[1] = py;
+            X.ep[2] = pz;
+            X.g = g;
+          }
+        }
+      }
       if (!A.chord) {
         if (tot <= kBatchN) {
           set_diag(k, static_cast<T>(cd[k] * (px * ek.x + py * ek.y + pz * ek.z)));
@@ -585,6 +894,28 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(const DevPlan P, const int
 #pragma unroll
     for (int w = 1; w < BLOCK / 64; ++w) gmax = fmax(gmax, red[w]);
     gmax = uni(gmax);
+    [[maybe_unused]] int32_t sing_all = 0;
+    if constexpr (SPLIT) {
+      // factor (speculatively: the decision needs every part's violation),
+      // publish the border data, then decide from all parts alike
+      if (!A.chord) save_border();
+      if (A.chord) factor_sweep(std::false_type{}, std::true_type{});
+      else factor_sweep(std::true_type{}, std::true_type{});
+      if (!A.chord) border_factors(true);
+      border_rhs();
+      if (tid == 0) {
+        pxa[sp.part].viol = gmax;
+        pxa[sp.part].singular = singular;
+      }
+      if (!grid_barrier(bar, sp.n_parts, &next_slot)) { st_code = ILVES_ERR_TIMEOUT; break; }
+      double gm = 0.0;
+      for (int32_t q = 0; q < sp.n_parts; ++q) {
+        gm = fmax(gm, pxa[q].viol);
+        sing_all |= pxa[q].singular;
+      }
+      gmax = uni(gm);
+      sing_all = uni(sing_all);
+    }
     if (A.warm == 2 && !fell_back) {
       // learned start: keep it only while it beats lambda = 0 and the
       // residual does not rise twice in a row; otherwise restart from 0
@@ -594,6 +925,9 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(const DevPlan P, const int
         prev_gmax = INFINITY;
         for (int32_t k = tid; k < n; k += BLOCK) er[4 * k + 3] = 0.0;
         __syncthreads();
+        if constexpr (SPLIT) {
+          if (!grid_barrier(bar, sp.n_parts, &next_slot)) { st_code = ILVES_ERR_TIMEOUT; break; }
+        }
         continue;
       }
       prev_gmax = gmax;
@@ -602,25 +936,44 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(const DevPlan P, const int
     if (gmax <= A.tol) { st_code = ILVES_OK; break; }
     if (it >= A.max_iter) { st_code = ILVES_ERR_NOT_CONVERGED; break; }
 
-    // ---- factorisation fused with the forward substitution (Newton), or
-    //      the forward substitution alone (chord)
-    if (A.chord) factor_sweep(std::false_type{}, std::true_type{});
-    else factor_sweep(std::true_type{}, std::true_type{});
-    if (uni(singular)) { st_code = ILVES_ERR_SINGULAR; break; }
+    if constexpr (SPLIT) {
+      // ---- separator system, then the backward substitution of the
+      //      interior levels from the border unknowns z_S
+      if (sing_all) { st_code = ILVES_ERR_SINGULAR; break; }
+      if (!A.chord) assemble(false);
+      sep_rhs();
+      if (!A.chord && !eliminate(ms + 1)) { st_code = ILVES_ERR_SINGULAR; break; }
+      sep_solve(A.chord != 0);
+      for (int32_t j = tid; j < nb; j += BLOCK) y[ni + j] = static_cast<T>(zs[P.bsep[sp.bsep_off + j] & 0x3fffffff]);
+      __syncthreads();
+      back_sweep(sp.h_int);
+    } else {
+      // ---- factorisation fused with the forward substitution (Newton), or
+      //      the forward substitution alone (chord)
+      if (A.chord) factor_sweep(std::false_type{}, std::true_type{});
+      else factor_sweep(std::true_type{}, std::true_type{});
+      if (uni(singular)) { st_code = ILVES_ERR_SINGULAR; break; }
 
-    // ---- backward substitution, then the lambda update
-    back_sweep();
+      // ---- backward substitution, then the lambda update
+      back_sweep(H);
+    }
     // lambda update after the sweep: keeps global traffic out of the levels
     for (int32_t k = tid; k < n; k += BLOCK) er[4 * k + 3] += static_cast<double>(y[k]);
     __syncthreads();
+    if constexpr (SPLIT) {
+      if (!grid_barrier(bar, sp.n_parts, &next_slot)) { st_code = ILVES_ERR_TIMEOUT; break; }
+    }
     ++it;
   }
 
   // ---- outputs: lambda in input order and r' = r_u - M^{-1} G(r)^T lambda
-  for (int32_t k = tid; k < n; k += BLOCK) A.lambda[cid[k]] = er[4 * k + 3];
+  //      (a part: its interior rows, the separator rows it owns, its atoms)
+  for (int32_t k = tid; k < n; k += BLOCK)
+    if (!SPLIT || k < ni || (P.bsep[sp.bsep_off + (k - ni)] >> 30)) A.lambda[cid[k]] = er[4 * k + 3];
   const int32_t* __restrict__ inc_ptr = P.inc_ptr + md.incp_off;
   const int32_t* __restrict__ inc = P.inc + md.inc_off;
-  for (int32_t a = tid; a < s; a += BLOCK) {
+  const int32_t s_out = SPLIT ? sp.s_own : s;
+  for (int32_t a = tid; a < s_out; a += BLOCK) {
     double dx = 0.0, dy = 0.0, dz = 0.0;
     for (int32_t q = inc_ptr[a]; q < inc_ptr[a + 1]; ++q) {
       const int32_t e = inc[q];
@@ -636,12 +989,13 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(const DevPlan P, const int
     A.r_out[S + g] = ux[S + g] - im * dy;
     A.r_out[2 * S + g] = ux[2 * S + g] - im * dz;
   }
-  if (tid == 0) {
-    A.iters[m_idx] = it;
-    A.status[m_idx] = st_code;
-    if (A.fallback) A.fallback[m_idx] = fell_back;
+  if (tid == 0 && (!SPLIT || sp.part == 0)) {
+    A.iters[report] = it;
+    A.status[report] = st_code;
+    if (A.fallback) A.fallback[report] = fell_back;
   }
   __syncthreads();  // LDS and next_slot are reused by the next molecule
+  if constexpr (SPLIT) break;
   }
 }
 
@@ -851,6 +1205,13 @@ KernelFn pick_kernel(bool fp32, int mode, bool wide, int block) {
   return fp32 ? pick_mode<float>(mode, wide, block) : pick_mode<double>(mode, wide, block);
 }
 
+// parts of split molecules: structure and values in LDS, 16-bit indices
+constexpr int kSplitBlock = 256;
+KernelFn pick_split(bool fp32) {
+  return fp32 ? solve_kernel<float, uint16_t, ALL_LDS, kSplitBlock, true>
+              : solve_kernel<double, uint16_t, ALL_LDS, kSplitBlock, true>;
+}
+
 constexpr int kLdsMax = 160 * 1024 - 1024;  // dynamic LDS a molecule may use
 constexpr int kStreams = 4;                 // concurrent launch groups
 
@@ -867,6 +1228,14 @@ struct Group {
   int64_t work = 0;     // sum over its molecules of rows + off-diagonal slots
 };
 constexpr int kMaxGroups = 64;
+
+// One launch of split-molecule parts: whole molecules, at most as many
+// parts as can be resident on the device at once (their barriers need it).
+struct SplitLaunch {
+  int32_t first = 0, count = 0;  // parts, in the device part array
+  int lds_bytes = 0;
+  int stream = 0;
+};
 
 }  // namespace
 
@@ -890,12 +1259,18 @@ struct ilves_plan {
   int n_cu = 0;
   int32_t band_block[5] = {64, 128, 256, 512, 1024};  // block size per LDS band (tunable)
   std::vector<Group> groups[2];        // [0] FP64, [1] mixed
+  std::vector<ilves::SplitPlan> splits;  // molecules split across workgroups
+  std::vector<int32_t> split_mol;        // their molecule indices
+  std::vector<int32_t> split_first;      // first part (device part index) of each
+  std::vector<int> split_lds[2];         // per part: dynamic LDS bytes
+  std::vector<SplitLaunch> split_launch[2];
   int32_t chunk_first[2] = {0, 0};     // row chunks of the feature passes, by index width
   int32_t chunk_count[2] = {0, 0};
   const int2* d_chunks = nullptr;      // {molecule, first row} pairs in d_buf
   const SmallMol* d_small = nullptr;   // small-molecule records in d_buf
   int32_t n_small = 0;
   int small_stream = 0;                // stream of the small-molecule kernel
+  int split_stream[2] = {0, 0};        // stream of the split-molecule launches
   float* d_mlp = nullptr;              // network parameters then normalisation block
   float* d_feat = nullptr;             // [n_constraints][16] features (plan row order)
   float* d_w = nullptr;                // [n_constraints] 1/m_a + 1/m_b
@@ -983,15 +1358,22 @@ std::pair<int, int> placement(const ilves::MolPlan& M, bool wide, int64_t lds_li
 
 ilves_status_t build_device_plan(ilves_plan* P) {
   const int32_t nm = static_cast<int32_t>(P->mols.size());
-  std::vector<MolDesc> desc(nm);
+  int32_t n_parts = 0;
+  for (const auto& sp : P->splits) n_parts += static_cast<int32_t>(sp.parts.size());
+  std::vector<MolDesc> desc(nm + n_parts);
   std::vector<unsigned char> pool;
   std::vector<int32_t> coef, ra, rb, cid, atom_gid, inc_ptr, inc, gcoef, gra, grb;
   std::vector<double> d2;
-  std::vector<char> wide(nm, 0);
+  std::vector<char> wide(nm + n_parts, 0);
   int64_t fill = 0, work = 0, maxlev = 0, sumlev = 0, nslots = 0, natoms = 0, ncon = 0;
   size_t ws = 0;
-  for (int32_t i = 0; i < nm; ++i) {
-    const ilves::MolPlan& M = P->mols[i];
+  // descriptors: the molecules, then the parts of the split molecules
+  std::vector<const ilves::MolPlan*> plans;
+  for (const auto& M : P->mols) plans.push_back(&M);
+  for (const auto& sp : P->splits)
+    for (const auto& M : sp.parts) plans.push_back(&M);
+  for (int32_t i = 0; i < nm + n_parts; ++i) {
+    const ilves::MolPlan& M = *plans[i];
     MolDesc& D = desc[i];
     D.n = M.n;
     D.s = M.s;
@@ -1027,6 +1409,7 @@ ilves_status_t build_device_plan(ilves_plan* P) {
     D.ws_off = static_cast<int64_t>(ws);
     ws += (ws_vec_bytes(M.n, M.s, M.n_up, M.n_l) + value_bytes<double>(M.n, M.n_up, M.n_l) + 255) &
           ~static_cast<size_t>(255);
+    if (i >= nm) continue;  // statistics count whole molecules
     fill += M.fill;
     work += M.n_upd;
     maxlev = std::max<int64_t>(maxlev, M.n_levels);
@@ -1064,6 +1447,101 @@ ilves_status_t build_device_plan(ilves_plan* P) {
     smalls.push_back(r);
   }
   ord.erase(std::remove_if(ord.begin(), ord.end(), [&](int32_t i) { return small[i] != 0; }), ord.end());
+  std::vector<char> is_split(nm, 0);
+  for (int32_t i : P->split_mol) is_split[i] = 1;
+  std::vector<int32_t> ord_solve;  // molecules solved by the per-molecule kernels
+  for (int32_t i : ord)
+    if (!is_split[i]) ord_solve.push_back(i);
+
+  // split molecules: part records, separator tables, exchange areas
+  std::vector<SplitPart> sparts;
+  std::vector<SepRow> seprows;
+  std::vector<int32_t> sadj, bsep, ext_ptr, ext_coef;
+  std::vector<int64_t> ext_rec;
+  P->split_first.clear();
+  for (int prec = 0; prec < 2; ++prec) P->split_lds[prec].clear();
+  int64_t max_sep = 0;
+  {
+    int32_t d0 = nm;  // descriptor of the first part of the current molecule
+    for (size_t si = 0; si < P->splits.size(); ++si) {
+      const ilves::SplitPlan& SPL = P->splits[si];
+      const int32_t G = static_cast<int32_t>(SPL.parts.size()), m = SPL.m;
+      max_sep = std::max<int64_t>(max_sep, m);
+      ws = (ws + 255) & ~static_cast<size_t>(255);
+      const int64_t xch = static_cast<int64_t>(ws);
+      std::vector<int32_t> ew_off(G);
+      int64_t xsz = xch_ew(G, m);
+      for (int32_t g = 0; g < G; ++g) {
+        ew_off[g] = static_cast<int32_t>(xsz / 8);
+        const int64_t nbg = SPL.parts[g].n - SPL.parts[g].n_int;
+        xsz += 8 * (nbg * nbg + nbg);
+      }
+      ws += static_cast<size_t>((xsz + 255) & ~static_cast<int64_t>(255));
+      const int32_t sep_off = static_cast<int32_t>(seprows.size());
+      for (int32_t b = 0; b < m; ++b) {
+        SepRow R{};
+        R.part0 = SPL.sep_part[2 * b];
+        R.part1 = SPL.sep_part[2 * b + 1];
+        R.loc0 = SPL.sep_loc[2 * b];
+        R.loc1 = SPL.sep_loc[2 * b + 1];
+        R.ga = SPL.sep_ga[b];
+        R.gb = SPL.sep_gb[b];
+        R.adj_off = static_cast<int32_t>(sadj.size() / 2);
+        R.adj_cnt = SPL.sadj_ptr[b + 1] - SPL.sadj_ptr[b];
+        for (int32_t a = SPL.sadj_ptr[b]; a < SPL.sadj_ptr[b + 1]; ++a) {
+          sadj.push_back(SPL.sadj_col[a]);
+          sadj.push_back(SPL.sadj_coef[a]);
+        }
+        R.ew0 = ew_off[R.part0];
+        R.ew1 = ew_off[R.part1];
+        R.nb0 = SPL.parts[R.part0].n - SPL.parts[R.part0].n_int;
+        R.nb1 = SPL.parts[R.part1].n - SPL.parts[R.part1].n_int;
+        seprows.push_back(R);
+      }
+      P->split_first.push_back(static_cast<int32_t>(sparts.size()));
+      for (int32_t g = 0; g < G; ++g) {
+        const ilves::MolPlan& M = SPL.parts[g];
+        const int32_t nbg = M.n - M.n_int;
+        SplitPart X{};
+        X.desc = d0 + g;
+        X.report = P->split_mol[si];
+        X.part = g;
+        X.n_parts = G;
+        X.n_int = M.n_int;
+        X.h_int = M.h_int;
+        X.s_own = M.s_own;
+        X.m = m;
+        X.bsep_off = static_cast<int32_t>(bsep.size());
+        for (int32_t j = 0; j < nbg; ++j) {
+          int32_t v = -1;
+          for (int32_t b = 0; b < m && v < 0; ++b)
+            for (int u = 0; u < 2; ++u)
+              if (SPL.sep_part[2 * b + u] == g && SPL.sep_loc[2 * b + u] == j) v = b | (u == 0 ? (1 << 30) : 0);
+          if (v < 0) return fail(ILVES_ERR_ARG, "internal: border row without separator row");
+          bsep.push_back(v);
+        }
+        X.ext_off = static_cast<int32_t>(ext_ptr.size());
+        for (int32_t j = 0; j <= nbg; ++j) ext_ptr.push_back(static_cast<int32_t>(ext_rec.size()) + SPL.ext_ptr[g][j]);
+        for (size_t e = 0; e < SPL.ext_part[g].size(); ++e)
+          ext_coef.push_back(SPL.ext_coef[g][e]);
+        for (size_t e = 0; e < SPL.ext_part[g].size(); ++e)
+          ext_rec.push_back(desc[d0 + SPL.ext_part[g][e]].ws_off / 8 + 4 * static_cast<int64_t>(SPL.ext_row[g][e]));
+        X.sep_off = sep_off;
+        X.ew_off = ew_off[g];
+        X.xch = xch;
+        // LDS: structure and values (ALL_LDS) then the split scratch
+        const int64_t sb = struct_layout(M.n, M.n_levels, M.n_up, M.n_l, static_cast<int32_t>(M.plist.size()),
+                                         M.n_upd, 2).total;
+        for (int prec = 0; prec < 2; ++prec) {
+          const int64_t vb = prec == 0 ? value_bytes<double>(M.n, M.n_up, M.n_l) : value_bytes<float>(M.n, M.n_up, M.n_l);
+          X.lds_extra[prec] = static_cast<int32_t>(align16(sb + vb));
+          P->split_lds[prec].push_back(static_cast<int>(align16(sb + vb) + split_lds_bytes(m, nbg)));
+        }
+        sparts.push_back(X);
+      }
+      d0 += G;
+    }
+  }
   std::vector<int32_t> lists;
   int64_t in_lds = 0, in_ws = 0;
   for (int prec = 0; prec < 2; ++prec) {
@@ -1082,7 +1560,7 @@ ilves_status_t build_device_plan(ilves_plan* P) {
     std::vector<std::pair<Key, std::vector<int32_t>>> buckets;
     std::vector<int> lds_of(nm, 0);
     std::vector<int32_t> in_lds_list;
-    for (int32_t i : ord) {
+    for (int32_t i : ord_solve) {
       const ilves::MolPlan& M = P->mols[i];
       auto pl = prec == 0 ? placement<double>(M, wide[i], P->opt.lds_limit)
                           : placement<float>(M, wide[i], P->opt.lds_limit);
@@ -1194,10 +1672,18 @@ ilves_status_t build_device_plan(ilves_plan* P) {
       g.stream = best;
       load[best] += g.work;
     }
-    int least = 0;
-    for (int i = 1; i < kStreams; ++i)
-      if (load[i] < load[least]) least = i;
-    P->small_stream = least;
+    auto least_loaded = [&]() {
+      int least = 0;
+      for (int i = 1; i < kStreams; ++i)
+        if (load[i] < load[least]) least = i;
+      return least;
+    };
+    // split molecules (every launch of them on one stream), then the small ones
+    int64_t split_work = 0;
+    for (size_t i = nm; i < plans.size(); ++i) split_work += static_cast<int64_t>(plans[i]->n) + plans[i]->n_up + plans[i]->n_l;
+    P->split_stream[prec] = least_loaded();
+    load[P->split_stream[prec]] += split_work;
+    P->small_stream = least_loaded();
   }
   // row chunks of the feature passes, narrow molecules then wide ones
   std::vector<int32_t> chunks;
@@ -1230,6 +1716,20 @@ ilves_status_t build_device_plan(ilves_plan* P) {
   const size_t o_lists = push_array(blob, lists);
   const size_t o_chunks = push_array(blob, chunks);
   const size_t o_small = push_array(blob, smalls);
+  if (sparts.empty()) sparts.resize(1);
+  if (seprows.empty()) seprows.resize(1);
+  if (sadj.empty()) sadj.resize(2, 0);
+  if (bsep.empty()) bsep.resize(1, 0);
+  if (ext_ptr.empty()) ext_ptr.resize(1, 0);
+  if (ext_rec.empty()) ext_rec.resize(1, 0);
+  if (ext_coef.empty()) ext_coef.resize(1, 0);
+  const size_t o_sparts = push_array(blob, sparts);
+  const size_t o_seprows = push_array(blob, seprows);
+  const size_t o_sadj = push_array(blob, sadj);
+  const size_t o_bsep = push_array(blob, bsep);
+  const size_t o_extp = push_array(blob, ext_ptr);
+  const size_t o_extr = push_array(blob, ext_rec);
+  const size_t o_extc = push_array(blob, ext_coef);
   blob.resize(blob.size() + 256);
 
   HIP_TRY(hipMalloc(&P->d_buf, blob.size()));
@@ -1252,9 +1752,17 @@ ilves_status_t build_device_plan(ilves_plan* P) {
   P->d_lists = reinterpret_cast<int32_t*>(b + o_lists);
   P->d_chunks = reinterpret_cast<const int2*>(b + o_chunks);
   P->d_small = reinterpret_cast<const SmallMol*>(b + o_small);
+  P->dp.split = reinterpret_cast<const SplitPart*>(b + o_sparts);
+  P->dp.sep = reinterpret_cast<const SepRow*>(b + o_seprows);
+  P->dp.sadj = reinterpret_cast<const int32_t*>(b + o_sadj);
+  P->dp.bsep = reinterpret_cast<const int32_t*>(b + o_bsep);
+  P->dp.ext_ptr = reinterpret_cast<const int32_t*>(b + o_extp);
+  P->dp.ext_rec = reinterpret_cast<const int64_t*>(b + o_extr);
+  P->dp.ext_coef = reinterpret_cast<const int32_t*>(b + o_extc);
   P->n_small = static_cast<int32_t>(smalls.size());
   if (ws > 0) {
     HIP_TRY(hipMalloc(&P->d_ws, ws));
+    HIP_TRY(hipMemset(P->d_ws, 0, ws));  // barrier counters of split molecules start at zero
     P->ws_bytes = ws;
   }
   P->stats[0] = nm;
@@ -1269,6 +1777,9 @@ ilves_status_t build_device_plan(ilves_plan* P) {
   P->stats[9] = in_ws;
   P->stats[10] = static_cast<int64_t>(ws);
   P->stats[11] = static_cast<int64_t>(blob.size());
+  P->stats[12] = static_cast<int64_t>(P->splits.size());
+  P->stats[13] = n_parts;
+  P->stats[14] = max_sep;
   return ILVES_OK;
 }
 
@@ -1285,6 +1796,44 @@ ilves_status_t finalize_groups(ilves_plan* P) {
       if (per_cu < 1) return fail(ILVES_ERR_HIP, "a solve kernel cannot be resident on a compute unit");
       g.grid = static_cast<int32_t>(std::min<int64_t>(g.count, static_cast<int64_t>(per_cu) * P->n_cu));
     }
+  // split molecules: launches of whole molecules whose parts can all be
+  // resident at once (the barriers of a molecule wait for all its parts)
+  for (int prec = 0; prec < 2; ++prec) {
+    P->split_launch[prec].clear();
+    if (P->splits.empty()) continue;
+    const void* k = reinterpret_cast<const void*>(pick_split(prec == 1));
+    HIP_TRY(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsMax));
+    auto capacity = [&](int lds, int64_t& cap) -> ilves_status_t {
+      int per_cu = 0;
+      HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, kSplitBlock, static_cast<size_t>(lds)));
+      cap = static_cast<int64_t>(per_cu) * P->n_cu;
+      return ILVES_OK;
+    };
+    SplitLaunch cur;
+    cur.stream = P->split_stream[prec];
+    for (size_t si = 0; si < P->splits.size(); ++si) {
+      const int32_t first = P->split_first[si];
+      const int32_t G = static_cast<int32_t>(P->splits[si].parts.size());
+      int lds = 0;
+      for (int32_t g = 0; g < G; ++g) lds = std::max(lds, P->split_lds[prec][first + g]);
+      int64_t cap_alone = 0, cap_joined = 0;
+      ilves_status_t st = capacity(lds, cap_alone);
+      if (st != ILVES_OK) return st;
+      if (cap_alone < G) return fail(ILVES_ERR_UNSUPPORTED, "a split molecule has more parts than can be resident");
+      st = capacity(std::max(lds, cur.lds_bytes), cap_joined);
+      if (st != ILVES_OK) return st;
+      if (cur.count > 0 && cur.count + G > cap_joined) {
+        P->split_launch[prec].push_back(cur);
+        cur.first = first;
+        cur.count = 0;
+        cur.lds_bytes = 0;
+      }
+      if (cur.count == 0) cur.first = first;
+      cur.count += G;
+      cur.lds_bytes = std::max(cur.lds_bytes, lds);
+    }
+    P->split_launch[prec].push_back(cur);
+  }
   return ILVES_OK;
 }
 
@@ -1334,6 +1883,7 @@ const char* ilves_status_string(ilves_status_t s) {
     case ILVES_ERR_NOT_CONVERGED: return "not converged";
     case ILVES_ERR_NONFINITE: return "non-finite values";
     case ILVES_ERR_UNSUPPORTED: return "unsupported option";
+    case ILVES_ERR_TIMEOUT: return "workgroups of a split molecule did not meet";
   }
   return "unknown status";
 }
@@ -1360,8 +1910,30 @@ ilves_status_t ilves_plan_create(int32_t n_atoms, int32_t n_constraints, const i
   ilves::PlanOptions po;
   po.ordering = P->opt.ordering;
   P->mols.reserve(mols.size());
+  // molecules above split_rows constraints are split across workgroups
+  // when every part then fits in LDS with 16-bit indices
+  const int32_t split_rows = P->opt.split_rows == 0 ? 4096 : P->opt.split_rows;
+  const int32_t part_rows = P->opt.split_part_rows > 0 ? P->opt.split_part_rows : std::max(64, split_rows / 4);
   try {
     for (const auto& c : mols) P->mols.push_back(ilves::plan_molecule(c, pairs, d, po));
+    for (size_t i = 0; i < mols.size(); ++i) {
+      if (split_rows < 0 || static_cast<int32_t>(mols[i].size()) <= split_rows) continue;
+      ilves::SplitPlan sp;
+      if (!ilves::plan_split(mols[i], pairs, d, po, part_rows, sp)) continue;
+      bool fits = true;
+      for (const auto& M : sp.parts) {
+        const int32_t nb = M.n - M.n_int;
+        const bool wide = static_cast<int64_t>(M.n_up) + M.n_l >= 65535 || M.n >= 65535 || M.n_upd >= 65535;
+        const int64_t sb = struct_layout(M.n, M.n_levels, M.n_up, M.n_l, static_cast<int32_t>(M.plist.size()),
+                                         M.n_upd, 2).total;
+        if (wide || static_cast<int64_t>(align16(sb + value_bytes<double>(M.n, M.n_up, M.n_l))) +
+                            split_lds_bytes(sp.m, nb) > kLdsMax)
+          fits = false;
+      }
+      if (!fits) continue;
+      P->splits.push_back(std::move(sp));
+      P->split_mol.push_back(static_cast<int32_t>(i));
+    }
   } catch (const std::bad_alloc&) {
     return fail(ILVES_ERR_NOMEM, "host allocation failed while planning");
   }
@@ -1544,16 +2116,32 @@ ilves_status_t solve_impl(ilves_plan_t P, const double* r, const double* r_u, co
     HIP_TRY(hipGetLastError());
   }
   const std::vector<Group>& groups = P->groups[precision == ILVES_PREC_MIXED ? 1 : 0];
-  if (groups.empty() && P->n_small == 0) return ILVES_OK;
+  if (groups.empty() && P->n_small == 0 && P->splits.empty()) return ILVES_OK;
   // fork: the groups run concurrently on the plan's streams, joined back
   // into the caller's stream (also valid under graph capture)
   int32_t* counters = P->d_counters + (precision == ILVES_PREC_MIXED ? kMaxGroups : 0);
   hipLaunchKernelGGL(reset_counters, dim3(1), dim3(kMaxGroups), 0, stream, counters, kMaxGroups);
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipEventRecord(P->ev_fork, stream));
+  const int pr = precision == ILVES_PREC_MIXED ? 1 : 0;
   int ns = P->n_small > 0 ? P->small_stream + 1 : 1;
   for (const Group& g : groups) ns = std::max(ns, g.stream + 1);
+  for (const SplitLaunch& l : P->split_launch[pr]) ns = std::max(ns, l.stream + 1);
   for (int i = 0; i < ns; ++i) HIP_TRY(hipStreamWaitEvent(P->streams[i], P->ev_fork, 0));
+  // split molecules first: their parts wait for each other, so they should
+  // be dispatched before the persistent groups fill the device
+  for (const SplitLaunch& l : P->split_launch[pr]) {
+    KernelFn k = pick_split(pr == 1);
+    DevPlan dp = P->dp;
+    dp.split = P->dp.split + l.first;
+    const int32_t* list = nullptr;
+    int32_t count = l.count;
+    int32_t* counter = nullptr;
+    SolveArgs a = A;
+    void* args[] = {&dp, &list, &count, &counter, &a};
+    HIP_TRY(hipLaunchKernel(reinterpret_cast<const void*>(k), dim3(l.count), dim3(kSplitBlock), args,
+                            static_cast<size_t>(l.lds_bytes), P->streams[l.stream]));
+  }
   for (size_t gi = 0; gi < groups.size(); ++gi) {
     const Group& g = groups[gi];
     KernelFn k = pick_kernel(precision == ILVES_PREC_MIXED, g.mode, g.wide, g.block);

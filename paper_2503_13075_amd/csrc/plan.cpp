@@ -363,12 +363,14 @@ struct Symbolic {
   std::vector<std::vector<int32_t>> up, low;  // strict upper / lower structure per row
   std::vector<int32_t> level;
   int32_t n_levels = 0;
+  int32_t h_int = 0;  // levels holding the rows before the tail
   int64_t nnz_off = 0;
   double cost = 0.0;
 };
 
-// adj: adjacency in the permuted numbering.
-Symbolic symbolic(const std::vector<std::vector<int32_t>>& adj) {
+// adj: adjacency in the permuted numbering.  The last n_tail rows (border
+// rows of a part) are held back to levels after every other row.
+Symbolic symbolic(const std::vector<std::vector<int32_t>>& adj, int32_t n_tail = 0) {
   const int32_t n = static_cast<int32_t>(adj.size());
   Symbolic S;
   S.up.resize(n);
@@ -386,11 +388,16 @@ Symbolic symbolic(const std::vector<std::vector<int32_t>>& adj) {
       par.insert(par.end(), u.begin() + 1, u.end());
     }
   }
-  for (int32_t p = 0; p < n; ++p)
+  const int32_t n_int = n - n_tail;
+  S.h_int = 0;
+  for (int32_t p = 0; p < n; ++p) {
+    if (p < n_int) S.h_int = std::max(S.h_int, S.level[p] + 1);
+    else S.level[p] = std::max(S.level[p], S.h_int);  // every interior level is final here
     for (int32_t q : S.up[p]) {
       S.low[q].push_back(p);
       S.level[q] = std::max(S.level[q], S.level[p] + 1);
     }
+  }
   for (int32_t p = 0; p < n; ++p) {
     S.n_levels = std::max(S.n_levels, S.level[p] + 1);
     S.nnz_off += static_cast<int64_t>(S.up[p].size());
@@ -454,11 +461,13 @@ int32_t find_sorted(const std::vector<int32_t>& v, int32_t x) {
 }  // namespace
 
 MolPlan plan_molecule(const std::vector<int32_t>& cons, const int32_t* pairs, const double* d,
-                      const PlanOptions& opt) {
+                      const PlanOptions& opt, const PartSpec* part) {
   MolPlan P;
   const int32_t n = static_cast<int32_t>(cons.size());
+  const int32_t n_tail = part ? part->n_tail : 0;
+  const int32_t n_int = n - n_tail;
   P.n = n;
-  // local atoms
+  // local atoms (a part's own atoms first, each run sorted)
   std::vector<int32_t> atoms;
   atoms.reserve(2 * n);
   for (int32_t c : cons) {
@@ -467,12 +476,28 @@ MolPlan plan_molecule(const std::vector<int32_t>& cons, const int32_t* pairs, co
   }
   std::sort(atoms.begin(), atoms.end());
   atoms.erase(std::unique(atoms.begin(), atoms.end()), atoms.end());
+  int32_t s_own = static_cast<int32_t>(atoms.size());
+  if (part && part->owned) {
+    const std::vector<int32_t>& own = *part->owned;
+    std::vector<int32_t> rest;
+    for (int32_t a : atoms)
+      if (!std::binary_search(own.begin(), own.end(), a)) rest.push_back(a);
+    s_own = static_cast<int32_t>(own.size());
+    atoms = own;
+    atoms.insert(atoms.end(), rest.begin(), rest.end());
+  }
   P.s = static_cast<int32_t>(atoms.size());
+  P.s_own = s_own;
   P.atom_gid = atoms;
+  auto local_atom = [&](int32_t g) {
+    auto it = std::lower_bound(atoms.begin(), atoms.begin() + s_own, g);
+    if (it != atoms.begin() + s_own && *it == g) return static_cast<int32_t>(it - atoms.begin());
+    return static_cast<int32_t>(std::lower_bound(atoms.begin() + s_own, atoms.end(), g) - atoms.begin());
+  };
   std::vector<int32_t> la(n), lb(n);
   for (int32_t c = 0; c < n; ++c) {
-    la[c] = find_sorted(atoms, pairs[2 * cons[c]]);
-    lb[c] = find_sorted(atoms, pairs[2 * cons[c] + 1]);
+    la[c] = local_atom(pairs[2 * cons[c]]);
+    lb[c] = local_atom(pairs[2 * cons[c] + 1]);
   }
   // incidence (local constraint order) and line graph
   std::vector<std::vector<int32_t>> inc(P.s);
@@ -493,13 +518,25 @@ MolPlan plan_molecule(const std::vector<int32_t>& cons, const int32_t* pairs, co
   }
   n_edges /= 2;
 
-  // ordering
-  std::vector<int32_t> perm = order_min_degree(adj);
-  Symbolic S = symbolic(permute_graph(adj, perm));
+  // ordering (of a part: its interior rows, the border rows after them)
+  std::vector<std::vector<int32_t>> adj_int;
+  if (n_tail > 0) {
+    adj_int.resize(n_int);
+    for (int32_t c = 0; c < n_int; ++c)
+      for (int32_t x : adj[c])
+        if (x < n_int) adj_int[c].push_back(x);
+  }
+  const std::vector<std::vector<int32_t>>& adj_o = n_tail > 0 ? adj_int : adj;
+  auto with_tail = [&](std::vector<int32_t> pm) {
+    for (int32_t c = n_int; c < n; ++c) pm.push_back(c);
+    return pm;
+  };
+  std::vector<int32_t> perm = with_tail(order_min_degree(adj_o));
+  Symbolic S = symbolic(permute_graph(adj, perm), n_tail);
   P.ordering = 1;
-  if (opt.ordering == 2 || (opt.ordering == 0 && n > 2 * opt.nd_leaf)) {
-    std::vector<int32_t> perm_nd = order_nested_dissection(adj, opt.nd_leaf);
-    Symbolic Snd = symbolic(permute_graph(adj, perm_nd));
+  if (opt.ordering == 2 || (opt.ordering == 0 && n_int > 2 * opt.nd_leaf)) {
+    std::vector<int32_t> perm_nd = with_tail(order_nested_dissection(adj_o, opt.nd_leaf));
+    Symbolic Snd = symbolic(permute_graph(adj, perm_nd), n_tail);
     if (opt.ordering == 2 || Snd.cost < S.cost) {
       perm = perm_nd;
       S = std::move(Snd);
@@ -518,15 +555,19 @@ MolPlan plan_molecule(const std::vector<int32_t>& cons, const int32_t* pairs, co
     const int64_t nnz_before = S.nnz_off;
     const int32_t lev_before = S.n_levels;
     perm = perm2;
-    S = symbolic(permute_graph(adj, perm));
+    S = symbolic(permute_graph(adj, perm), n_tail);
     if (S.nnz_off != nnz_before || S.n_levels != lev_before)
       throw std::logic_error("level renumbering changed the filled pattern");
     for (int32_t p = 1; p < n; ++p)
       if (S.level[p] < S.level[p - 1]) throw std::logic_error("rows are not sorted by level");
+    for (int32_t p = n_int; p < n; ++p)
+      if (perm[p] < n_int) throw std::logic_error("a border row moved before an interior row");
   }
   std::vector<int32_t> inv(n);
   for (int32_t p = 0; p < n; ++p) inv[perm[p]] = p;
   P.n_levels = S.n_levels;
+  P.n_int = n_int;
+  P.h_int = n_tail > 0 ? S.h_int : S.n_levels;
   P.fill = S.nnz_off - n_edges;
   P.cost = S.cost;
 
@@ -609,8 +650,11 @@ MolPlan plan_molecule(const std::vector<int32_t>& cons, const int32_t* pairs, co
       if (P.ustart[q + 1] > P.ustart[q]) P.plist.push_back(q);
     P.pl_start[h + 1] = static_cast<int32_t>(P.plist.size());
   }
-  for (int32_t p = 0; p < n; ++p)
-    if ((S.level[p] == 0) != S.low[p].empty()) throw std::logic_error("level 0 must be the rows without lower entries");
+  for (int32_t p = 0; p < n; ++p) {
+    if (S.level[p] == 0 && !S.low[p].empty()) throw std::logic_error("level-0 rows must have no lower entries");
+    if (p < n_int && S.level[p] > 0 && S.low[p].empty()) throw std::logic_error("rows without lower entries must be at level 0");
+    if ((p < n_int) != (S.level[p] < P.h_int)) throw std::logic_error("border rows must sit alone in the last levels");
+  }
   // incidence in elimination order
   P.inc_ptr.assign(P.s + 1, 0);
   for (int32_t x = 0; x < P.s; ++x) P.inc_ptr[x + 1] = P.inc_ptr[x] + static_cast<int32_t>(inc[x].size());
@@ -625,6 +669,219 @@ MolPlan plan_molecule(const std::vector<int32_t>& cons, const int32_t* pairs, co
     }
   }
   return P;
+}
+
+// ---------------------------------------------------------------------------
+// split of one molecule across several workgroups
+
+namespace {
+
+// Groups of atoms of about `target` constraints each, from a breadth-first
+// spanning tree of the bond graph rooted at a peripheral atom: walking the
+// tree bottom-up, a subtree is cut off as a group once it holds `target`
+// constraints (each constraint counts at its endpoint found later by the
+// search), and a vertex whose uncut children together exceed 1.5 target
+// first cuts its heaviest children.  Groups are numbered in search order of
+// their roots, so neighbouring groups of a chain get consecutive numbers.
+std::vector<int32_t> group_atoms(int32_t s, const std::vector<int32_t>& la, const std::vector<int32_t>& lb,
+                                 int32_t target, int32_t& n_groups) {
+  const int32_t n = static_cast<int32_t>(la.size());
+  std::vector<std::vector<int32_t>> nb(s);
+  for (int32_t c = 0; c < n; ++c) {
+    nb[la[c]].push_back(lb[c]);
+    nb[lb[c]].push_back(la[c]);
+  }
+  auto bfs = [&](int32_t root, std::vector<int32_t>& order, std::vector<int32_t>& parent) {
+    order.assign(1, root);
+    parent.assign(s, -2);
+    parent[root] = -1;
+    for (size_t h = 0; h < order.size(); ++h)
+      for (int32_t y : nb[order[h]])
+        if (parent[y] == -2) {
+          parent[y] = order[h];
+          order.push_back(y);
+        }
+  };
+  std::vector<int32_t> order, parent;
+  bfs(0, order, parent);
+  bfs(order.back(), order, parent);  // from an atom at the far end
+  std::vector<int32_t> pos(s);
+  for (int32_t h = 0; h < s; ++h) pos[order[h]] = h;
+  std::vector<double> resid(s, 0.0), added(s, 0.0);
+  for (int32_t c = 0; c < n; ++c) resid[pos[la[c]] > pos[lb[c]] ? la[c] : lb[c]] += 1.0;
+  std::vector<std::vector<int32_t>> kids(s);
+  for (int32_t v : order)
+    if (parent[v] >= 0) kids[parent[v]].push_back(v);
+  std::vector<char> cut(s, 0);
+  const double T = static_cast<double>(target);
+  for (int32_t h = s - 1; h >= 0; --h) {
+    const int32_t v = order[h];
+    while (resid[v] > 1.5 * T) {
+      int32_t best = -1;
+      for (int32_t k : kids[v])
+        if (!cut[k] && added[k] > 0.0 && (best < 0 || added[k] > added[best])) best = k;
+      if (best < 0) break;
+      cut[best] = 1;
+      resid[v] -= added[best];
+    }
+    if (parent[v] >= 0 && resid[v] >= T) {
+      cut[v] = 1;
+    } else if (parent[v] >= 0) {
+      added[v] = resid[v];
+      resid[parent[v]] += resid[v];
+    }
+  }
+  std::vector<int32_t> group(s, -1);
+  n_groups = 0;
+  for (int32_t v : order) group[v] = (parent[v] < 0 || cut[v]) ? n_groups++ : group[parent[v]];
+  return group;
+}
+
+}  // namespace
+
+bool plan_split(const std::vector<int32_t>& cons, const int32_t* pairs, const double* d, const PlanOptions& opt,
+                int32_t part_rows, SplitPlan& out) {
+  const int32_t n = static_cast<int32_t>(cons.size());
+  std::vector<int32_t> atoms;
+  for (int32_t c : cons) {
+    atoms.push_back(pairs[2 * c]);
+    atoms.push_back(pairs[2 * c + 1]);
+  }
+  std::sort(atoms.begin(), atoms.end());
+  atoms.erase(std::unique(atoms.begin(), atoms.end()), atoms.end());
+  const int32_t s = static_cast<int32_t>(atoms.size());
+  std::vector<int32_t> la(n), lb(n);
+  for (int32_t c = 0; c < n; ++c) {
+    la[c] = find_sorted(atoms, pairs[2 * cons[c]]);
+    lb[c] = find_sorted(atoms, pairs[2 * cons[c] + 1]);
+  }
+  int32_t G = 0;
+  std::vector<int32_t> group = group_atoms(s, la, lb, std::max<int32_t>(part_rows, 8), G);
+  // a group without interior constraints joins the group across its first
+  // separator constraint (repeated until every group has some)
+  for (int round = 0; round < G; ++round) {
+    std::vector<int32_t> inner(G, 0);
+    for (int32_t c = 0; c < n; ++c)
+      if (group[la[c]] == group[lb[c]]) ++inner[group[la[c]]];
+    int32_t bad = -1;
+    for (int32_t g = 0; g < G && bad < 0; ++g)
+      if (inner[g] == 0) bad = g;
+    if (bad < 0) break;
+    int32_t into = -1;
+    for (int32_t c = 0; c < n && into < 0; ++c) {
+      if (group[la[c]] == bad && group[lb[c]] != bad) into = group[lb[c]];
+      else if (group[lb[c]] == bad && group[la[c]] != bad) into = group[la[c]];
+    }
+    if (into < 0) break;
+    std::vector<int32_t> relabel(G);
+    int32_t k = 0;
+    for (int32_t g = 0; g < G; ++g) relabel[g] = g == bad ? -1 : k++;
+    for (int32_t& g : group) g = g == bad ? relabel[into] : relabel[g];
+    G = k;
+  }
+  if (G < 2 || G > kSplitMaxParts) return false;
+  std::vector<std::vector<int32_t>> interior(G), border(G), owned(G);
+  std::vector<int32_t> sep;  // local constraint indices of the separator rows
+  for (int32_t c = 0; c < n; ++c) {
+    const int32_t ga = group[la[c]], gb = group[lb[c]];
+    if (ga == gb) {
+      interior[ga].push_back(c);
+    } else {
+      sep.push_back(c);
+      border[ga].push_back(c);
+      border[gb].push_back(c);
+    }
+  }
+  const int32_t m = static_cast<int32_t>(sep.size());
+  if (m > kSplitMaxSep) return false;
+  for (int32_t g = 0; g < G; ++g)
+    if (interior[g].empty() || static_cast<int32_t>(border[g].size()) > kSplitMaxBorder) return false;
+  for (int32_t x = 0; x < s; ++x) owned[group[x]].push_back(atoms[x]);  // sorted, as atoms is
+
+  SplitPlan S;
+  S.m = m;
+  S.parts.resize(G);
+  std::vector<std::vector<int32_t>> row_of(G);  // per part: local constraint -> local row (or -1)
+  for (int32_t g = 0; g < G; ++g) {
+    std::vector<int32_t> pc;
+    for (int32_t c : interior[g]) pc.push_back(cons[c]);
+    for (int32_t c : border[g]) pc.push_back(cons[c]);
+    PartSpec spec;
+    spec.n_tail = static_cast<int32_t>(border[g].size());
+    spec.owned = &owned[g];
+    S.parts[g] = plan_molecule(pc, pairs, d, opt, &spec);
+    const MolPlan& M = S.parts[g];
+    if (M.n_int != static_cast<int32_t>(interior[g].size())) throw std::logic_error("part row count");
+    row_of[g].assign(n, -1);
+    for (int32_t p = 0; p < M.n; ++p) {
+      const int32_t c = static_cast<int32_t>(std::lower_bound(cons.begin(), cons.end(), M.cid[p]) - cons.begin());
+      row_of[g][c] = p;
+    }
+  }
+  std::vector<int32_t> sep_index(n, -1);
+  for (int32_t b = 0; b < m; ++b) sep_index[sep[b]] = b;
+  S.sep_cid.resize(m);
+  S.sep_ga.resize(m);
+  S.sep_gb.resize(m);
+  S.sep_part.resize(2 * m);
+  S.sep_loc.resize(2 * m);
+  for (int32_t b = 0; b < m; ++b) {
+    const int32_t c = sep[b];
+    S.sep_cid[b] = cons[c];
+    S.sep_ga[b] = atoms[la[c]];
+    S.sep_gb[b] = atoms[lb[c]];
+    const int32_t g0 = std::min(group[la[c]], group[lb[c]]), g1 = std::max(group[la[c]], group[lb[c]]);
+    S.sep_part[2 * b] = g0;
+    S.sep_part[2 * b + 1] = g1;
+    S.sep_loc[2 * b] = row_of[g0][c] - S.parts[g0].n_int;
+    S.sep_loc[2 * b + 1] = row_of[g1][c] - S.parts[g1].n_int;
+  }
+  // constraint incidence of the atoms, for couplings
+  std::vector<std::vector<int32_t>> inc(s);
+  for (int32_t c = 0; c < n; ++c) {
+    inc[la[c]].push_back(c);
+    inc[lb[c]].push_back(c);
+  }
+  auto coupling = [&](int32_t x, int32_t c1, int32_t c2) {
+    const int s1 = la[c1] == x ? 1 : -1, s2 = la[c2] == x ? 1 : -1;
+    return (atoms[x] << 1) | (s1 * s2 < 0 ? 1 : 0);
+  };
+  S.sadj_ptr.assign(1, 0);
+  for (int32_t b = 0; b < m; ++b) {
+    const int32_t c = sep[b];
+    for (int32_t x : {la[c], lb[c]})
+      for (int32_t c2 : inc[x])
+        if (c2 != c && sep_index[c2] >= 0) {
+          S.sadj_col.push_back(sep_index[c2]);
+          S.sadj_coef.push_back(coupling(x, c, c2));
+        }
+    S.sadj_ptr.push_back(static_cast<int32_t>(S.sadj_col.size()));
+  }
+  // rows coupled to a border row that its part does not hold
+  S.ext_ptr.resize(G);
+  S.ext_part.resize(G);
+  S.ext_row.resize(G);
+  S.ext_coef.resize(G);
+  for (int32_t g = 0; g < G; ++g) {
+    const MolPlan& M = S.parts[g];
+    S.ext_ptr[g].assign(1, 0);
+    for (int32_t p = M.n_int; p < M.n; ++p) {
+      const int32_t c = static_cast<int32_t>(std::lower_bound(cons.begin(), cons.end(), M.cid[p]) - cons.begin());
+      for (int32_t x : {la[c], lb[c]})
+        for (int32_t c2 : inc[x]) {
+          if (c2 == c || row_of[g][c2] >= 0) continue;
+          // held by the part of its interior group, or (separator row) by its owner
+          const int32_t h = sep_index[c2] >= 0 ? S.sep_part[2 * sep_index[c2]] : group[la[c2]];
+          if (row_of[h][c2] < 0) throw std::logic_error("coupled row not held by its part");
+          S.ext_part[g].push_back(h);
+          S.ext_row[g].push_back(row_of[h][c2]);
+          S.ext_coef[g].push_back(coupling(x, c, c2));
+        }
+      S.ext_ptr[g].push_back(static_cast<int32_t>(S.ext_part[g].size()));
+    }
+  }
+  out = std::move(S);
+  return true;
 }
 
 }  // namespace ilves

@@ -46,7 +46,50 @@ struct MolPlan {
   int64_t fill = 0;
   int ordering = 0;                // 1 minimum fill, 2 nested dissection
   double cost = 0.0;               // critical-path estimate of one Newton iteration (planner units)
+  // Parts of a split molecule (plan_split): rows [0, n_int) are the part's
+  // interior constraints, rows [n_int, n) its border constraints, which
+  // occupy levels [h_int, n_levels) alone; local atoms [0, s_own) belong to
+  // the part (their positions are its output).  A whole molecule has
+  // n_int = n, h_int = n_levels, s_own = s.
+  int32_t n_int = 0, h_int = 0, s_own = 0;
 };
+
+// A part of a split molecule: the constraints, interior ones first, with
+// n_tail border constraints at the end, and the input atoms the part owns
+// (sorted).
+struct PartSpec {
+  int32_t n_tail = 0;
+  const std::vector<int32_t>* owned = nullptr;
+};
+
+// A molecule split across several workgroups (block-bordered form).  The
+// atoms are partitioned into groups; a constraint inside a group is an
+// interior row of that group's part, a constraint joining two groups is a
+// separator row and a border row of both parts.  After ordering every
+// part's interior rows before its border rows, the Newton matrix is
+//   [A_11         A_1S]
+//   [      ...    ... ]     A_SS - sum_i A_Si A_ii^-1 A_iS = Schur complement
+//   [A_S1  ...    A_SS]
+// and each part's LU of its own rows yields its contribution to the Schur
+// complement and to the reduced right-hand side.
+struct SplitPlan {
+  std::vector<MolPlan> parts;
+  int32_t m = 0;                        // separator rows
+  std::vector<int32_t> sep_cid;         // [m] input constraint
+  std::vector<int32_t> sep_ga, sep_gb;  // [m] input atoms a_b, b_b
+  std::vector<int32_t> sep_part;        // [2m] the two parts holding row b (owner first)
+  std::vector<int32_t> sep_loc;         // [2m] its border index (local row - n_int) in each
+  std::vector<int32_t> sadj_ptr;        // [m + 1] CSR: separator rows coupled to b
+  std::vector<int32_t> sadj_col;        //   other separator row
+  std::vector<int32_t> sadj_coef;       //   coupling (input atom << 1) | (sign < 0)
+  // per part, per border row (CSR): coupled rows not held by the part, as
+  // (holding part, local row there, coupling)
+  std::vector<std::vector<int32_t>> ext_ptr, ext_part, ext_row, ext_coef;
+};
+
+constexpr int32_t kSplitMaxParts = 64;    // workgroups of one split molecule
+constexpr int32_t kSplitMaxSep = 64;      // separator rows of one split molecule
+constexpr int32_t kSplitMaxBorder = 24;   // border rows of one part
 
 struct PlanOptions {
   int ordering = 0;      // 0 auto, 1 MD, 2 ND
@@ -62,9 +105,16 @@ std::string validate_topology(int32_t n_atoms, int32_t n_con, const int32_t* pai
 std::vector<std::vector<int32_t>> split_molecules(int32_t n_atoms, int32_t n_con, const int32_t* pairs,
                                                   std::vector<int32_t>& free_atoms);
 
-// Builds the plan of one molecule from its input constraint indices.
+// Builds the plan of one molecule (or, with part, of one part of a split
+// molecule) from its input constraint indices.
 MolPlan plan_molecule(const std::vector<int32_t>& cons, const int32_t* pairs, const double* d,
-                      const PlanOptions& opt);
+                      const PlanOptions& opt, const PartSpec* part = nullptr);
+
+// Splits a molecule into parts of about part_rows constraints.  Returns false
+// (out untouched) when the split would exceed the limits above or leave a
+// part without interior constraints.
+bool plan_split(const std::vector<int32_t>& cons, const int32_t* pairs, const double* d, const PlanOptions& opt,
+                int32_t part_rows, SplitPlan& out);
 
 // Orderings of a graph given as sorted adjacency lists (exposed for tests).
 std::vector<int32_t> order_min_degree(const std::vector<std::vector<int32_t>>& adj);

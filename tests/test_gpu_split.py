@@ -1,0 +1,165 @@
+"""Molecules split across workgroups on the GPU (block-bordered LU with a
+Schur complement on the separator rows, one workgroup per part, device-wide
+barriers between the phases of a Newton iteration): parity with the oracle
+and with the host replay of the same schedule, for FP64 / mixed precision,
+Newton / chord, caller's warm start; repeated solves on one plan (the
+barrier state carries over), graph replay, status reporting, and a system
+that mixes split, whole and small molecules with free atoms."""
+import numpy as np
+import pytest
+
+from oracle import newton_dense as O
+from paper_2503_13075_amd import _lib as L
+from paper_2503_13075_amd import synth as S
+from paper_2503_13075_amd.device import DeviceSystem, solve_once
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+POS_TOL = 1e-10
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    L.lib()
+    return torch
+
+
+def _oracle(sm, ru):
+    return O.solve(sm.pairs, sm.d, sm.mass, sm.r, ru, tol=1e-15, until_stagnation=True, max_iter=40)
+
+
+def _check(sm, out, ref, label):
+    assert np.all(out["status"] == L.OK), (label, out["status"])
+    viol = np.max(O.relative_violation(out["r_out"], sm.pairs, sm.d))
+    dpos = np.max(np.abs(out["r_out"] - ref["r_new"]))
+    dlam = np.max(np.abs(out["lam"] - ref["lam"])) / np.max(np.abs(ref["lam"]))
+    print(f"{label}: violation {viol:.2e}, |dr'| {dpos:.2e} nm, |dlambda| rel {dlam:.2e}, iters {out['iters']}",
+          flush=True)
+    assert viol <= TOL and dpos <= POS_TOL and dlam <= 1e-6, label
+
+
+CASES = {
+    "protein": lambda: (S.protein(60, seed=3), 0.002, 100, 50),
+    "tree_rings": lambda: (S.random_tree(1500, seed=11, ring_frac=0.08), 0.002, 200, 64),
+    "h_angles": lambda: (S.add_h_angles(S.protein(50, seed=9)), 0.004, 300, 100),
+}
+VARIANTS = [("fp64", L.PREC_FP64, L.VARIANT_NEWTON), ("mixed", L.PREC_MIXED, L.VARIANT_NEWTON),
+            ("chord64", L.PREC_FP64, L.VARIANT_CHORD), ("chord_mixed", L.PREC_MIXED, L.VARIANT_CHORD)]
+
+
+@pytest.fixture(scope="module")
+def cases():
+    out = {}
+    for name, make in CASES.items():
+        sm, sigma, rows, part = make()
+        ru = S.perturb(sm.r, sigma, 5)
+        out[name] = (sm, ru, rows, part, _oracle(sm, ru))
+    return out
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+@pytest.mark.parametrize("name,prec,variant", VARIANTS)
+def test_split_matches_oracle_and_replay(cases, case, name, prec, variant):
+    sm, ru, rows, part, ref = cases[case]
+    print(f"== split {case}/{name}", flush=True)
+    out = solve_once(sm, ru, TOL, prec, variant, split_rows=rows, split_part_rows=part)
+    st = out["plan"].stats()
+    assert st["split_molecules"] == 1 and st["split_parts"] >= 2, st
+    print(f"   parts {st['split_parts']}, separator rows {st['max_separator']}", flush=True)
+    _check(sm, out, ref, f"{case}/{name}")
+    rep = L.replay_host(sm.n_atoms, sm.pairs, sm.d, sm.mass, S.soa(sm.r), S.soa(ru), TOL, precision=prec,
+                        variant=variant, split_rows=rows, split_part_rows=part)
+    assert np.max(np.abs(out["r_out"] - rep["r_out"].T)) <= POS_TOL
+    if variant == L.VARIANT_NEWTON:
+        assert abs(int(out["iters"][0]) - int(rep["iters"][0])) <= 1
+
+
+def test_split_warm_start_and_repeated_solves(cases):
+    """Caller's lambda_0 near the answer converges in at most one step; ten
+    solves in a row on one plan (the barrier counters carry over between
+    launches) give bitwise the same result."""
+    import torch
+    sm, ru, rows, part, ref = cases["protein"]
+    print("== split warm start / repeats", flush=True)
+    lam0 = ref["lam"] * (1.0 + 1e-9)
+    out = solve_once(sm, ru, TOL, L.PREC_FP64, L.VARIANT_NEWTON, lam0=lam0, split_rows=rows, split_part_rows=part)
+    _check(sm, out, ref, "protein/warm")
+    assert out["iters"][0] <= 1
+    plan = out["plan"]
+    ds = DeviceSystem(sm).alloc_status(plan.n_molecules)
+    rud = ds.upload_ru(ru)
+    first = None
+    for rep in range(10):
+        plan.solve(ds.r, rud, ds.mass, TOL, ds.r_out, ds.lam, ds.iters, ds.status, precision=L.PREC_MIXED)
+        torch.cuda.synchronize()
+        r = ds.r_out.cpu().numpy().copy()
+        assert np.all(ds.status.cpu().numpy()[:plan.n_molecules] == L.OK)
+        if first is None:
+            first = r
+        else:
+            assert np.array_equal(r, first), rep
+
+
+def test_split_in_graph_replay(cases):
+    """A captured solve of a split molecule replayed five times, with eager
+    work and synchronisation between replays: every replay matches the
+    eager solve bitwise."""
+    import torch
+    sm, ru, rows, part, ref = cases["tree_rings"]
+    print("== split graph replay", flush=True)
+    plan = L.Plan(sm.n_atoms, sm.pairs, sm.d, split_rows=rows, split_part_rows=part)
+    ds = DeviceSystem(sm).alloc_status(plan.n_molecules)
+    rud = ds.upload_ru(ru)
+    plan.solve(ds.r, rud, ds.mass, TOL, ds.r_out, ds.lam, ds.iters, ds.status, precision=L.PREC_MIXED)
+    torch.cuda.synchronize()
+    eager = ds.r_out.cpu().numpy().copy()
+    s = torch.cuda.Stream()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        plan.solve(ds.r, rud, ds.mass, TOL, ds.r_out, ds.lam, ds.iters, ds.status, precision=L.PREC_MIXED, stream=s)
+        s.synchronize()
+        with torch.cuda.graph(g, stream=s):
+            plan.solve(ds.r, rud, ds.mass, TOL, ds.r_out, ds.lam, ds.iters, ds.status, precision=L.PREC_MIXED,
+                       stream=s)
+    for rep in range(5):
+        ds.r_out.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(ds.r_out.cpu().numpy(), eager), rep
+        assert np.all(ds.status.cpu().numpy()[:plan.n_molecules] == L.OK)
+
+
+def test_split_status_paths(cases):
+    """Iteration cap and a non-finite input reach every part's decision
+    alike (the solve returns with the status of the molecule)."""
+    sm, ru, rows, part, ref = cases["protein"]
+    print("== split status paths", flush=True)
+    out = solve_once(sm, ru, TOL, L.PREC_FP64, L.VARIANT_NEWTON, max_iter=1, split_rows=rows, split_part_rows=part)
+    assert out["status"][0] == L.ERR_NOT_CONVERGED and out["iters"][0] == 1
+    bad = ru.copy()
+    bad[sm.pairs[len(sm.pairs) // 2, 0], 1] = np.nan
+    out = solve_once(sm, bad, TOL, L.PREC_FP64, L.VARIANT_NEWTON, split_rows=rows, split_part_rows=part)
+    assert out["status"][0] == L.ERR_NONFINITE
+
+
+def test_mixed_system_with_split_molecules():
+    """Two split proteins next to whole trees, small molecules and free
+    atoms, FP64 and mixed, against the oracle."""
+    print("== split mixed system", flush=True)
+    sm = S.concat([S.random_tree(30, seed=1), S.protein(50, seed=2), S.water_box(2, seed=3), S.random_tree(200, seed=4),
+                   S.protein(40, seed=5)], spacing=2.0)
+    free = np.array([[9.0, 9.0, 9.0]])
+    sm = S.System(pairs=sm.pairs, d=sm.d, mass=np.concatenate([sm.mass, [12.0]]), r=np.concatenate([sm.r, free]),
+                  kind=sm.kind)
+    ru = S.perturb(sm.r, 0.002, 7)
+    ref = _oracle(sm, ru)
+    for prec in (L.PREC_FP64, L.PREC_MIXED):
+        out = solve_once(sm, ru, TOL, prec, L.VARIANT_NEWTON, split_rows=300, split_part_rows=80)
+        assert out["plan"].stats()["split_molecules"] == 2
+        _check(sm, out, ref, f"mixed system/{prec}")
+        assert np.array_equal(out["r_out"][-1], ru[-1])

@@ -22,7 +22,7 @@ def test_exports_every_header_symbol():
 
 def test_status_strings():
     lib = L.lib()
-    for code in range(9):
+    for code in range(10):
         assert lib.ilves_status_string(code)
 
 
