@@ -39,6 +39,10 @@ def make_workload(name, seed):
     if name == "protein300":
         sm = S.protein_system(seed=seed, n_res=300)
         return sm, 0.002, {"workload": "one protein-like molecule, 300 residues, all bonds", "molecules": 1}
+    if name == "giant":
+        sm = S.protein_system(seed=seed, n_res=1650)
+        return sm, 0.002, {"workload": "one protein-like molecule of 1650 residues (~26,600 bond constraints, "
+                                       "the size of the paper's largest single molecule), all bonds", "molecules": 1}
     if name == "angles":
         sm = S.angles_system(seed=seed)
         return sm, 0.006, {"workload": "20 proteins + 1000 lipid chains, bonds + H-X-H/H-X-Y angles",
@@ -379,7 +383,8 @@ def main():
         "config": dict(cfg, atoms=sm.n_atoms, constraints=sm.n_constraints,
                        variant=("mixed precision Newton, learned lambda_0" if head_name == "learned"
                                 else "mixed precision Newton, lambda_0 = 0"),
-                       sigma_nm=sigma, tol=1e-12),
+                       sigma_nm=sigma, tol=1e-12, split_molecules=st["split_molecules"],
+                       split_parts=st["split_parts"]),
         "newton_iters": {k: v["iters_mean"] for k, v in results.items()},
         "variants": variants,
         "speedup_vs_fp64": head["constraints_per_s"] / results["fp64"]["constraints_per_s"],

@@ -85,7 +85,7 @@ typedef struct {
                             Schur complement on the constraints that join the
                             parts); 0 = automatic (4096), < 0 = never          */
   int32_t split_part_rows; /* constraints per part of a split molecule;
-                            0 = automatic (split_rows / 4, at least 64)         */
+                            0 = automatic (split_rows / 8, at least 64)         */
 } ilves_options_t;
 
 /* Fills *opt with defaults (FP64 Newton, lambda_0 = 0, automatic schedule). */

@@ -95,8 +95,12 @@ struct SplitPart {
   int32_t ew_off;    // doubles from the exchange area to this part's E block (nb*nb, then w: nb)
   int64_t xch;       // byte offset of the molecule's exchange area in the workspace
   int32_t lds_extra[2];  // byte offset of the split scratch in dynamic LDS (FP64, FP32 values)
+  int32_t ew_total;  // doubles of the molecule's E/w blocks (all parts)
+  int32_t n_sadj;    // separator couplings of the molecule
+  int32_t bw;        // half-bandwidth of the separator matrix with its fill
+  int32_t pad;
 };
-static_assert(sizeof(SplitPart) == 64, "SplitPart is one 64-byte record");
+static_assert(sizeof(SplitPart) == 80, "SplitPart is one 80-byte record");
 
 // A separator row: the two parts holding it as a border row (part0 owns
 // it), its border index in each, its atoms and its separator couplings.
@@ -128,11 +132,14 @@ __host__ __device__ inline int64_t xch_sepx(int32_t n_parts) { return 64 + 32 * 
 __host__ __device__ inline int64_t xch_ew(int32_t n_parts, int32_t m) { return xch_sepx(n_parts) + 64 * static_cast<int64_t>(m); }
 
 // Split scratch in LDS after the factor values (doubles): the separator
-// system [m][m + 1], its solution z[m], and per border row the saved
-// residual gB[nb]; the border block of the matrix, the unit-lower and the
-// upper factors ([nb][nb] each).
-__host__ __device__ inline int64_t split_lds_bytes(int32_t m, int32_t nb) {
-  return 8 * (static_cast<int64_t>(m) * (m + 1) + m + nb + 3 * static_cast<int64_t>(nb) * nb);
+// system [m][m + 1], its solution z[m], per border row the saved residual
+// gB[nb]; the border block of the matrix, the unit-lower and the upper
+// factors ([nb][nb] each); the row maxima of the separator matrix [m]; a
+// copy of the exchange area's SepX records and E/w blocks [8m + ew_total];
+// the molecule's SepRow records [m] and separator couplings [n_sadj pairs].
+__host__ __device__ inline int64_t split_lds_bytes(int32_t m, int32_t nb, int32_t ew_total, int32_t n_sadj) {
+  return 8 * (static_cast<int64_t>(m) * (m + 1) + m + nb + 3 * static_cast<int64_t>(nb) * nb + m + 8 * m + ew_total) +
+         static_cast<int64_t>(sizeof(SepRow)) * m + 8 * static_cast<int64_t>(n_sadj);
 }
 
 // A molecule of at most kSmallCons constraints on at most kSmallAtoms atoms,

@@ -179,17 +179,34 @@ __device__ __forceinline__ SplitPart uni(const SplitPart& p) {
   r.xch = uni(p.xch);
   r.lds_extra[0] = uni(p.lds_extra[0]);
   r.lds_extra[1] = uni(p.lds_extra[1]);
+  r.ew_total = uni(p.ew_total);
+  r.n_sadj = uni(p.n_sadj);
+  r.bw = uni(p.bw);
+  r.pad = 0;
   return r;
+}
+
+// Data one workgroup of a split molecule writes and another reads (the
+// exchange area, lambdas of rows coupled across parts) is read with
+// device-coherent loads, which fetch past the caches of the reading
+// compute unit and XCD; everything a part reads only of its own stays
+// cacheable (no cache invalidation at the barriers).
+__device__ __forceinline__ double ld_coh(const double* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int32_t ld_coh(const int32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Barrier of the workgroups of one split molecule (all resident: the
 // launch never holds more of them than fit on the device at once).  Every
-// wave first makes its global writes visible device-wide; one lane per
-// workgroup arrives on the counter, the last arrival resets it and advances
-// the generation, the others wait for the generation to change; the
-// acquire fence then drops stale cached lines.  The wait is bounded: after
-// kSpinCap polls (seconds) the workgroup marks the molecule poisoned, which
-// also releases every other waiter, and reports false.
+// wave first writes its global data back device-wide (release); one lane
+// per workgroup arrives on the counter, the last arrival resets it and
+// advances the generation, the others wait for the generation to change.
+// Readers use ld_coh for data written by other workgroups, so no acquire
+// invalidation is needed.  The wait is bounded: after kSpinCap polls
+// (seconds) the workgroup marks the molecule poisoned, which also releases
+// every other waiter, and reports false.
 constexpr int32_t kSpinCap = 1 << 22;
 __device__ bool grid_barrier(uint32_t* bar, int32_t n_parts, int32_t* flag) {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
@@ -197,8 +214,9 @@ __device__ bool grid_barrier(uint32_t* bar, int32_t n_parts, int32_t* flag) {
   if (threadIdx.x == 0) {
     int32_t good = __hip_atomic_load(bar + 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u;
     if (good) {
-      const uint32_t g = __hip_atomic_load(bar + 1, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-      const uint32_t a = __hip_atomic_fetch_add(bar, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+      const uint32_t g = __hip_atomic_load(bar + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __builtin_amdgcn_s_waitcnt(0);  // the generation is read before arriving
+      const uint32_t a = __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
       if (a == static_cast<uint32_t>(n_parts - 1)) {
         __hip_atomic_store(bar, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __hip_atomic_fetch_add(bar + 1, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
@@ -217,7 +235,6 @@ __device__ bool grid_barrier(uint32_t* bar, int32_t n_parts, int32_t* flag) {
         }
       }
     }
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     *flag = good;
   }
   __syncthreads();
@@ -381,6 +398,12 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(const DevPlan P, const int
   double* Ab = gB + nb;
   double* Lb = Ab + nb * nb;
   double* Ub = Lb + nb * nb;
+  double* amax = Ub + nb * nb;  // row maxima of the separator matrix
+  double* xs = amax + ms;       // copy of SepX[ms] (8 doubles each) then the E/w blocks
+  const int32_t ew_total = SPLIT ? sp.ew_total : 0;
+  SepRow* srow = reinterpret_cast<SepRow*>(xs + 8 * ms + ew_total);
+  int32_t* sadj_l = reinterpret_cast<int32_t*>(srow + ms);
+  const int32_t ew_base = static_cast<int32_t>(xch_ew(SPLIT ? sp.n_parts : 0, ms) / 8);
 
   const int32_t* __restrict__ atom_gid = P.atom_gid + md.atom_off;
   const int32_t* __restrict__ cid = P.cid + md.row_off;
@@ -432,6 +455,16 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(const DevPlan P, const int
     const int32_t c = gcoef[q];
     const double v = c < 0 ? 0.0 : 1.0 / A.mass[c >> 1];
     cf[q] = (c & 1) ? -v : v;
+  }
+  int32_t adj0 = 0;  // first separator coupling of the molecule
+  if constexpr (SPLIT) {
+    // separator rows and couplings of the molecule into LDS (plan data)
+    const int32_t* src = reinterpret_cast<const int32_t*>(P.sep + sp.sep_off);
+    int32_t* dst = reinterpret_cast<int32_t*>(srow);
+    constexpr int kw = static_cast<int>(sizeof(SepRow) / 4);
+    for (int32_t i = tid; i < ms * kw; i += BLOCK) dst[i] = src[i];
+    adj0 = uni(P.sep[sp.sep_off].adj_off);
+    for (int32_t i = tid; i < 2 * sp.n_sadj; i += BLOCK) sadj_l[i] = P.sadj[2 * adj0 + i];
   }
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {
@@ -677,88 +710,117 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(const DevPlan P, const int
       ew[nb * nb + p] = gB[p] - acc;
     }
   };
+  // the exchange area's SepX records and E/w blocks into LDS, one round of
+  // device-coherent loads
+  auto stage = [&]() {
+    const double* src = reinterpret_cast<const double*>(xb + xch_sepx(sp.n_parts));
+    for (int32_t i = tid; i < 8 * ms + ew_total; i += BLOCK) xs[i] = ld_coh(src + i);
+    __syncthreads();
+  };
   // separator matrix A_SS (at the owners' bond vectors e', or e for the
-  // chord) plus the parts' contributions, into Sm[:, :ms]
+  // chord) plus the parts' contributions, into Sm[:, :ms] (from the staged
+  // copies)
   auto assemble = [&](bool at_e) {
     for (int32_t i = tid; i < ms * (ms + 1); i += BLOCK) Sm[i] = 0.0;
     __syncthreads();
     for (int32_t b = tid; b < ms; b += BLOCK) {
-      const SepRow R = P.sep[sp.sep_off + b];
-      const SepX& X = sxa[b];
-      const double p0 = at_e ? X.e[0] : X.ep[0], p1 = at_e ? X.e[1] : X.ep[1], p2 = at_e ? X.e[2] : X.ep[2];
-      Sm[b * (ms + 1) + b] = (1.0 / A.mass[R.ga] + 1.0 / A.mass[R.gb]) * (p0 * X.e[0] + p1 * X.e[1] + p2 * X.e[2]);
+      const SepRow& R = srow[b];
+      const double* X = xs + 8 * b;  // e'[3], g, e[3]
+      const double p0 = at_e ? X[4] : X[0], p1 = at_e ? X[5] : X[1], p2 = at_e ? X[6] : X[2];
+      Sm[b * (ms + 1) + b] = (1.0 / A.mass[R.ga] + 1.0 / A.mass[R.gb]) * (p0 * X[4] + p1 * X[5] + p2 * X[6]);
       for (int32_t a = 0; a < R.adj_cnt; ++a) {
-        const int32_t c = P.sadj[2 * (R.adj_off + a)], cc = P.sadj[2 * (R.adj_off + a) + 1];
-        const SepX& Y = sxa[c];
-        Sm[b * (ms + 1) + c] = ((cc & 1) ? -1.0 : 1.0) / A.mass[cc >> 1] * (p0 * Y.e[0] + p1 * Y.e[1] + p2 * Y.e[2]);
+        const int32_t c = sadj_l[2 * (R.adj_off - adj0 + a)], cc = sadj_l[2 * (R.adj_off - adj0 + a) + 1];
+        const double* Y = xs + 8 * c;
+        Sm[b * (ms + 1) + c] = ((cc & 1) ? -1.0 : 1.0) / A.mass[cc >> 1] * (p0 * Y[4] + p1 * Y[5] + p2 * Y[6]);
       }
     }
     __syncthreads();
+    const double* E = xs + 8 * ms - ew_base;  // indexed by doubles from the exchange area
     for (int32_t i = tid; i < ms * ms; i += BLOCK) {
       const int32_t b = i / (ms > 0 ? ms : 1), c = i - b * ms;  // (ms > 0 whenever this runs)
-      const SepRow Rb = P.sep[sp.sep_off + b], Rc = P.sep[sp.sep_off + c];
+      const SepRow& Rb = srow[b];
+      const SepRow& Rc = srow[c];
       double acc = Sm[b * (ms + 1) + c];
       for (int u = 0; u < 2; ++u) {
         const int32_t g = u ? Rb.part1 : Rb.part0, lb = u ? Rb.loc1 : Rb.loc0;
         const int32_t eo = u ? Rb.ew1 : Rb.ew0, nbg = u ? Rb.nb1 : Rb.nb0;
         for (int v = 0; v < 2; ++v)
-          if ((v ? Rc.part1 : Rc.part0) == g) acc += xd[eo + lb * nbg + (v ? Rc.loc1 : Rc.loc0)];
+          if ((v ? Rc.part1 : Rc.part0) == g) acc += E[eo + lb * nbg + (v ? Rc.loc1 : Rc.loc0)];
       }
       Sm[b * (ms + 1) + c] = acc;
     }
     __syncthreads();
   };
   // elimination without pivoting of the first cols columns (ms + 1: with
-  // the right-hand side); false when a pivot vanishes (every thread tests
-  // the same row, so the answer is uniform)
+  // the right-hand side), inside the band of half-width bw that holds every
+  // entry and its fill: wave 0 alone, lane i updating row p + 1 + i at step
+  // p (LDS accesses of one wave stay in order, so no workgroup barrier per
+  // step).  False when a pivot falls below 1e-13 of its row's largest entry
+  // before the elimination.
   auto eliminate = [&](int32_t cols) -> bool {
-    for (int32_t p = 0; p < ms; ++p) {
-      const double piv = Sm[p * (ms + 1) + p];
+    const int32_t bw = sp.bw;
+    for (int32_t p = tid; p < ms; p += BLOCK) {
       double a0 = 0.0;
       for (int32_t c = 0; c < ms; ++c) a0 = fmax(a0, fabs(Sm[p * (ms + 1) + c]));
-      if (!(fabs(piv) > 1e-13 * a0)) return false;
-      const int32_t w = cols - p - 1;
-      for (int32_t i = tid; i < (ms - p - 1) * w; i += BLOCK) {
-        const int32_t q = p + 1 + i / w, c = p + 1 + i % w;
-        const double f = Sm[q * (ms + 1) + p] / piv;
-        Sm[q * (ms + 1) + c] -= f * Sm[p * (ms + 1) + c];
-      }
-      __syncthreads();
+      amax[p] = a0;
     }
-    return true;
+    __syncthreads();
+    if (tid < 64) {
+      int32_t bad = 0;
+      for (int32_t p = 0; p < ms; ++p) {
+        const double piv = Sm[p * (ms + 1) + p];
+        if (!(fabs(piv) > 1e-13 * amax[p])) {
+          bad = 1;
+          break;
+        }
+        const double inv = 1.0 / piv;
+        const int32_t q = p + 1 + tid, c1 = p + bw < ms - 1 ? p + bw : ms - 1;
+        if (tid < bw && q < ms) {
+          const double f = Sm[q * (ms + 1) + p] * inv;
+          for (int32_t c = p + 1; c <= c1; ++c) Sm[q * (ms + 1) + c] -= f * Sm[p * (ms + 1) + c];
+          if (cols > ms) Sm[q * (ms + 1) + ms] -= f * Sm[p * (ms + 1) + ms];
+        }
+        __builtin_amdgcn_wave_barrier();
+      }
+      if (tid == 0) next_slot = bad;
+    }
+    __syncthreads();
+    return __builtin_amdgcn_readfirstlane(next_slot) == 0;
   };
   // separator right-hand side g_S - sum_i w_i into zs (and the last column
   // of Sm for the Newton elimination)
   auto sep_rhs = [&]() {
+    const double* E = xs + 8 * ms - ew_base;
     for (int32_t b = tid; b < ms; b += BLOCK) {
-      const SepRow R = P.sep[sp.sep_off + b];
-      const double r = sxa[b].g - xd[R.ew0 + R.nb0 * R.nb0 + R.loc0] - xd[R.ew1 + R.nb1 * R.nb1 + R.loc1];
+      const SepRow& R = srow[b];
+      const double r = xs[8 * b + 3] - E[R.ew0 + R.nb0 * R.nb0 + R.loc0] - E[R.ew1 + R.nb1 * R.nb1 + R.loc1];
       zs[b] = r;
       Sm[b * (ms + 1) + ms] = r;
     }
     __syncthreads();
   };
-  // triangular solves of the eliminated system by wave 0 (one lane per
-  // separator row, ms <= 64): forward (chord: the right-hand side was not
-  // eliminated with the matrix) then backward; z in zs
+  // triangular solves of the eliminated system inside the band: forward
+  // (chord: the right-hand side was not eliminated with the matrix) by
+  // wave 0, lane i updating row p + 1 + i; backward by lane 0; z in zs
   auto sep_solve = [&](bool forward) {
+    const int32_t bw = sp.bw;
     if (tid < 64) {
-      double r = tid < ms ? (forward ? zs[tid] : Sm[tid * (ms + 1) + ms]) : 0.0;
+      if (!forward)
+        for (int32_t q = tid; q < ms; q += 64) zs[q] = Sm[q * (ms + 1) + ms];
+      __builtin_amdgcn_wave_barrier();
       if (forward)
         for (int32_t p = 0; p < ms; ++p) {
-          const double rp = __shfl(r, p, 64);
-          if (tid > p && tid < ms) r -= Sm[tid * (ms + 1) + p] / Sm[p * (ms + 1) + p] * rp;
+          const int32_t q = p + 1 + tid;
+          if (tid < bw && q < ms) zs[q] -= Sm[q * (ms + 1) + p] / Sm[p * (ms + 1) + p] * zs[p];
+          __builtin_amdgcn_wave_barrier();
         }
-      if (tid < ms) zs[tid] = r;
-      for (int32_t q = ms - 1; q >= 0; --q) {
-        double part = 0.0;
-        for (int32_t c = q + 1 + tid; c < ms; c += 64) part -= Sm[q * (ms + 1) + c] * zs[c];
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off, 64);
-        if (tid == 0) zs[q] = (zs[q] + part) / Sm[q * (ms + 1) + q];
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      }
+      if (tid == 0)
+        for (int32_t q = ms - 1; q >= 0; --q) {
+          double acc = zs[q];
+          const int32_t c1 = q + bw < ms - 1 ? q + bw : ms - 1;
+          for (int32_t c = q + 1; c <= c1; ++c) acc -= Sm[q * (ms + 1) + c] * zs[c];
+          zs[q] = acc / Sm[q * (ms + 1) + q];
+        }
     }
     __syncthreads();
   };
@@ -793,12 +855,13 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(const DevPlan P, const int
     } else {
       int32_t sing = 0;
       for (int32_t q = 0; q < sp.n_parts; ++q) {
-        rel_zero = fmax(rel_zero, pxa[q].rel0);
-        sing |= pxa[q].singular;
+        rel_zero = fmax(rel_zero, ld_coh(&pxa[q].rel0));
+        sing |= ld_coh(&pxa[q].singular);
       }
       rel_zero = uni(rel_zero);
       chord_singular = A.chord && uni(sing) != 0;
       if (A.chord && !chord_singular) {
+        stage();
         assemble(true);
         chord_singular = !eliminate(ms);
       }
@@ -846,7 +909,8 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(const DevPlan P, const int
         if (k >= ni) {  // couplings to rows held by other parts
           const int32_t e0 = P.ext_ptr[sp.ext_off + (k - ni)], e1 = P.ext_ptr[sp.ext_off + (k - ni) + 1];
           for (int32_t e = e0; e < e1; ++e) {
-            const Rec h = ld_rec(reinterpret_cast<const double*>(A.ws) + P.ext_rec[e]);
+            const double* hp = reinterpret_cast<const double*>(A.ws) + P.ext_rec[e];
+            const Rec h{ld_coh(hp), ld_coh(hp + 1), ld_coh(hp + 2), ld_coh(hp + 3)};
             const int32_t cc = P.ext_coef[e];
             const double c = ((cc & 1) ? -1.0 : 1.0) / A.mass[cc >> 1] * h.l;
             px -= c * h.x;
@@ -910,8 +974,8 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(const DevPlan P, const int
       if (!grid_barrier(bar, sp.n_parts, &next_slot)) { st_code = ILVES_ERR_TIMEOUT; break; }
       double gm = 0.0;
       for (int32_t q = 0; q < sp.n_parts; ++q) {
-        gm = fmax(gm, pxa[q].viol);
-        sing_all |= pxa[q].singular;
+        gm = fmax(gm, ld_coh(&pxa[q].viol));
+        sing_all |= ld_coh(&pxa[q].singular);
       }
       gmax = uni(gm);
       sing_all = uni(sing_all);
@@ -940,6 +1004,7 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(const DevPlan P, const int
       // ---- separator system, then the backward substitution of the
       //      interior levels from the border unknowns z_S
       if (sing_all) { st_code = ILVES_ERR_SINGULAR; break; }
+      stage();
       if (!A.chord) assemble(false);
       sep_rhs();
       if (!A.chord && !eliminate(ms + 1)) { st_code = ILVES_ERR_SINGULAR; break; }
@@ -1477,6 +1542,8 @@ ilves_status_t build_device_plan(ilves_plan* P) {
         xsz += 8 * (nbg * nbg + nbg);
       }
       ws += static_cast<size_t>((xsz + 255) & ~static_cast<int64_t>(255));
+      const int32_t ew_total = static_cast<int32_t>((xsz - xch_ew(G, m)) / 8);
+      const int32_t n_sadj = static_cast<int32_t>(SPL.sadj_col.size());
       const int32_t sep_off = static_cast<int32_t>(seprows.size());
       for (int32_t b = 0; b < m; ++b) {
         SepRow R{};
@@ -1529,13 +1596,16 @@ ilves_status_t build_device_plan(ilves_plan* P) {
         X.sep_off = sep_off;
         X.ew_off = ew_off[g];
         X.xch = xch;
+        X.ew_total = ew_total;
+        X.n_sadj = n_sadj;
+        X.bw = SPL.bw;
         // LDS: structure and values (ALL_LDS) then the split scratch
         const int64_t sb = struct_layout(M.n, M.n_levels, M.n_up, M.n_l, static_cast<int32_t>(M.plist.size()),
                                          M.n_upd, 2).total;
         for (int prec = 0; prec < 2; ++prec) {
           const int64_t vb = prec == 0 ? value_bytes<double>(M.n, M.n_up, M.n_l) : value_bytes<float>(M.n, M.n_up, M.n_l);
           X.lds_extra[prec] = static_cast<int32_t>(align16(sb + vb));
-          P->split_lds[prec].push_back(static_cast<int>(align16(sb + vb) + split_lds_bytes(m, nbg)));
+          P->split_lds[prec].push_back(static_cast<int>(align16(sb + vb) + split_lds_bytes(m, nbg, ew_total, n_sadj)));
         }
         sparts.push_back(X);
       }
@@ -1913,7 +1983,7 @@ ilves_status_t ilves_plan_create(int32_t n_atoms, int32_t n_constraints, const i
   // molecules above split_rows constraints are split across workgroups
   // when every part then fits in LDS with 16-bit indices
   const int32_t split_rows = P->opt.split_rows == 0 ? 4096 : P->opt.split_rows;
-  const int32_t part_rows = P->opt.split_part_rows > 0 ? P->opt.split_part_rows : std::max(64, split_rows / 4);
+  const int32_t part_rows = P->opt.split_part_rows > 0 ? P->opt.split_part_rows : std::max(64, split_rows / 8);
   try {
     for (const auto& c : mols) P->mols.push_back(ilves::plan_molecule(c, pairs, d, po));
     for (size_t i = 0; i < mols.size(); ++i) {
@@ -1921,13 +1991,15 @@ ilves_status_t ilves_plan_create(int32_t n_atoms, int32_t n_constraints, const i
       ilves::SplitPlan sp;
       if (!ilves::plan_split(mols[i], pairs, d, po, part_rows, sp)) continue;
       bool fits = true;
+      int32_t ew_total = 0;
+      for (const auto& M : sp.parts) ew_total += (M.n - M.n_int) * (M.n - M.n_int + 1);
       for (const auto& M : sp.parts) {
         const int32_t nb = M.n - M.n_int;
         const bool wide = static_cast<int64_t>(M.n_up) + M.n_l >= 65535 || M.n >= 65535 || M.n_upd >= 65535;
         const int64_t sb = struct_layout(M.n, M.n_levels, M.n_up, M.n_l, static_cast<int32_t>(M.plist.size()),
                                          M.n_upd, 2).total;
         if (wide || static_cast<int64_t>(align16(sb + value_bytes<double>(M.n, M.n_up, M.n_l))) +
-                            split_lds_bytes(sp.m, nb) > kLdsMax)
+                            split_lds_bytes(sp.m, nb, ew_total, static_cast<int32_t>(sp.sadj_col.size())) > kLdsMax)
           fits = false;
       }
       if (!fits) continue;

@@ -794,6 +794,13 @@ bool plan_split(const std::vector<int32_t>& cons, const int32_t* pairs, const do
   }
   const int32_t m = static_cast<int32_t>(sep.size());
   if (m > kSplitMaxSep) return false;
+  // separator rows ordered by their pair of parts: with groups numbered
+  // along the molecule the separator matrix is then banded
+  std::stable_sort(sep.begin(), sep.end(), [&](int32_t x, int32_t y) {
+    const int32_t x0 = std::min(group[la[x]], group[lb[x]]), x1 = std::max(group[la[x]], group[lb[x]]);
+    const int32_t y0 = std::min(group[la[y]], group[lb[y]]), y1 = std::max(group[la[y]], group[lb[y]]);
+    return x0 != y0 ? x0 < y0 : x1 < y1;
+  });
   for (int32_t g = 0; g < G; ++g)
     if (interior[g].empty() || static_cast<int32_t>(border[g].size()) > kSplitMaxBorder) return false;
   for (int32_t x = 0; x < s; ++x) owned[group[x]].push_back(atoms[x]);  // sorted, as atoms is
@@ -856,6 +863,28 @@ bool plan_split(const std::vector<int32_t>& cons, const int32_t* pairs, const do
           S.sadj_coef.push_back(coupling(x, c, c2));
         }
     S.sadj_ptr.push_back(static_cast<int32_t>(S.sadj_col.size()));
+  }
+  // half-bandwidth of the separator matrix after elimination without
+  // pivoting: entries between rows that share an atom or a part, plus fill
+  {
+    std::vector<std::vector<char>> nz(m, std::vector<char>(m, 0));
+    for (int32_t b = 0; b < m; ++b) {
+      nz[b][b] = 1;
+      for (int32_t a = S.sadj_ptr[b]; a < S.sadj_ptr[b + 1]; ++a) nz[b][S.sadj_col[a]] = 1;
+      for (int32_t c = 0; c < m; ++c)
+        for (int u = 0; u < 2; ++u)
+          for (int v = 0; v < 2; ++v)
+            if (S.sep_part[2 * b + u] == S.sep_part[2 * c + v]) nz[b][c] = 1;
+    }
+    for (int32_t p = 0; p < m; ++p)
+      for (int32_t q = p + 1; q < m; ++q)
+        if (nz[q][p])
+          for (int32_t c = p + 1; c < m; ++c)
+            if (nz[p][c]) nz[q][c] = 1;
+    S.bw = 0;
+    for (int32_t b = 0; b < m; ++b)
+      for (int32_t c = 0; c < m; ++c)
+        if (nz[b][c]) S.bw = std::max(S.bw, std::abs(b - c));
   }
   // rows coupled to a border row that its part does not hold
   S.ext_ptr.resize(G);

@@ -74,7 +74,8 @@ struct PartSpec {
 // complement and to the reduced right-hand side.
 struct SplitPlan {
   std::vector<MolPlan> parts;
-  int32_t m = 0;                        // separator rows
+  int32_t m = 0;                        // separator rows (ordered by their two parts)
+  int32_t bw = 0;                       // half-bandwidth of the separator matrix with its fill
   std::vector<int32_t> sep_cid;         // [m] input constraint
   std::vector<int32_t> sep_ga, sep_gb;  // [m] input atoms a_b, b_b
   std::vector<int32_t> sep_part;        // [2m] the two parts holding row b (owner first)

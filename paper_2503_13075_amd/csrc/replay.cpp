@@ -313,14 +313,18 @@ int32_t replay_split(const ilves::SplitPlan& SP, int32_t S, const double* mass, 
               Sm[b * (m + 1) + c] += E[g][SP.sep_loc[2 * b + u] * nb(g) + SP.sep_loc[2 * c + v]];
         }
   };
-  auto eliminate = [&](int32_t cols) {  // no pivoting; false if a pivot vanished
+  // no pivoting; false if a pivot falls below 1e-13 of its row's largest
+  // entry before the elimination
+  auto eliminate = [&](int32_t cols) {
+    std::vector<double> amax(m, 0.0);
+    for (int32_t p = 0; p < m; ++p)
+      for (int32_t c = 0; c < m; ++c) amax[p] = std::fmax(amax[p], std::fabs(Sm[p * (m + 1) + c]));
     for (int32_t p = 0; p < m; ++p) {
       const double piv = Sm[p * (m + 1) + p];
-      double a0 = 0.0;
-      for (int32_t c = 0; c < m; ++c) a0 = std::fmax(a0, std::fabs(Sm[p * (m + 1) + c]));
-      if (!(std::fabs(piv) > 1e-13 * a0)) return false;
+      if (!(std::fabs(piv) > 1e-13 * amax[p])) return false;
+      const double inv = 1.0 / piv;
       for (int32_t q = p + 1; q < m; ++q) {
-        const double f = Sm[q * (m + 1) + p] / piv;
+        const double f = Sm[q * (m + 1) + p] * inv;
         for (int32_t c = p + 1; c < cols; ++c) Sm[q * (m + 1) + c] -= f * Sm[p * (m + 1) + c];
       }
     }
@@ -455,7 +459,7 @@ ilves_status_t ilves_plan_replay_host(int32_t n_atoms, int32_t n_constraints, co
     if (opt->split_rows != 0) split_rows = opt->split_rows;
     part_rows = opt->split_part_rows;
   }
-  if (part_rows <= 0) part_rows = std::max(64, split_rows / 4);
+  if (part_rows <= 0) part_rows = std::max(64, split_rows / 8);
   std::vector<int32_t> free_atoms;
   auto mols = ilves::split_molecules(n_atoms, n_constraints, pairs, free_atoms);
   *n_molecules = static_cast<int32_t>(mols.size());
