@@ -124,6 +124,9 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="batch4096")
+    ap.add_argument("--split-rows", type=int, default=0,
+                    help="split molecules above this many constraints across workgroups (0 automatic, <0 never)")
+    ap.add_argument("--split-part-rows", type=int, default=0, help="constraints per part of a split molecule")
     ap.add_argument("--seed", type=int, default=2)
     ap.add_argument("--pool", type=int, default=8, help="distinct r_u sets resident in HBM")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -159,7 +162,7 @@ def main():
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
     t1 = time.perf_counter()
-    plan = L.Plan(sm.n_atoms, sm.pairs, sm.d)
+    plan = L.Plan(sm.n_atoms, sm.pairs, sm.d, split_rows=args.split_rows, split_part_rows=args.split_part_rows)
     st = plan.stats()
     log(f"plan: {time.perf_counter() - t1:.1f} s, {st}")
     r = torch.from_numpy(S.soa(sm.r)).to(dev)

@@ -122,9 +122,10 @@ int32_t ilves_plan_num_molecules(ilves_plan_t plan);
  *   LDS (mixed precision), [9] the others, [10] workspace bytes,
  *   [11] plan bytes on the device, [12] molecules split across workgroups,
  *   [13] workgroups (parts) of the split molecules, [14] largest separator
- *   (constraints joining the parts of one molecule).
+ *   (constraints joining the parts of one molecule), [15] split molecules
+ *   whose parts keep only their factor values in LDS (FP64).
  */
-#define ILVES_STAT_COUNT 15
+#define ILVES_STAT_COUNT 16
 ilves_status_t ilves_plan_stats(ilves_plan_t plan, int64_t* stats);
 
 /*

@@ -1270,11 +1270,15 @@ KernelFn pick_kernel(bool fp32, int mode, bool wide, int block) {
   return fp32 ? pick_mode<float>(mode, wide, block) : pick_mode<double>(mode, wide, block);
 }
 
-// parts of split molecules: structure and values in LDS, 16-bit indices
+// parts of split molecules (16-bit indices): structure and values in LDS,
+// or the values only
 constexpr int kSplitBlock = 256;
-KernelFn pick_split(bool fp32) {
-  return fp32 ? solve_kernel<float, uint16_t, ALL_LDS, kSplitBlock, true>
-              : solve_kernel<double, uint16_t, ALL_LDS, kSplitBlock, true>;
+KernelFn pick_split(bool fp32, int mode) {
+  if (mode == ALL_LDS)
+    return fp32 ? solve_kernel<float, uint16_t, ALL_LDS, kSplitBlock, true>
+                : solve_kernel<double, uint16_t, ALL_LDS, kSplitBlock, true>;
+  return fp32 ? solve_kernel<float, uint16_t, VALUES_LDS, kSplitBlock, true>
+              : solve_kernel<double, uint16_t, VALUES_LDS, kSplitBlock, true>;
 }
 
 constexpr int kLdsMax = 160 * 1024 - 1024;  // dynamic LDS a molecule may use
@@ -1300,6 +1304,7 @@ struct SplitLaunch {
   int32_t first = 0, count = 0;  // parts, in the device part array
   int lds_bytes = 0;
   int stream = 0;
+  int mode = ALL_LDS;            // placement of every part of the launch
 };
 
 }  // namespace
@@ -1328,6 +1333,7 @@ struct ilves_plan {
   std::vector<int32_t> split_mol;        // their molecule indices
   std::vector<int32_t> split_first;      // first part (device part index) of each
   std::vector<int> split_lds[2];         // per part: dynamic LDS bytes
+  std::vector<int> split_mode[2];        // per split molecule: ALL_LDS or VALUES_LDS
   std::vector<SplitLaunch> split_launch[2];
   int32_t chunk_first[2] = {0, 0};     // row chunks of the feature passes, by index width
   int32_t chunk_count[2] = {0, 0};
@@ -1524,7 +1530,10 @@ ilves_status_t build_device_plan(ilves_plan* P) {
   std::vector<int32_t> sadj, bsep, ext_ptr, ext_coef;
   std::vector<int64_t> ext_rec;
   P->split_first.clear();
-  for (int prec = 0; prec < 2; ++prec) P->split_lds[prec].clear();
+  for (int prec = 0; prec < 2; ++prec) {
+    P->split_lds[prec].clear();
+    P->split_mode[prec].clear();
+  }
   int64_t max_sep = 0;
   {
     int32_t d0 = nm;  // descriptor of the first part of the current molecule
@@ -1566,6 +1575,20 @@ ilves_status_t build_device_plan(ilves_plan* P) {
         seprows.push_back(R);
       }
       P->split_first.push_back(static_cast<int32_t>(sparts.size()));
+      // placement per precision: structure and values in LDS when every part
+      // fits, else the values only
+      for (int prec = 0; prec < 2; ++prec) {
+        bool all = true;
+        for (int32_t g = 0; g < G; ++g) {
+          const ilves::MolPlan& M = SPL.parts[g];
+          const int64_t sb = struct_layout(M.n, M.n_levels, M.n_up, M.n_l, static_cast<int32_t>(M.plist.size()),
+                                           M.n_upd, 2).total;
+          const int64_t vb = prec == 0 ? value_bytes<double>(M.n, M.n_up, M.n_l) : value_bytes<float>(M.n, M.n_up, M.n_l);
+          if (static_cast<int64_t>(align16(sb + vb)) + split_lds_bytes(m, M.n - M.n_int, ew_total, n_sadj) > kLdsMax)
+            all = false;
+        }
+        P->split_mode[prec].push_back(all ? ALL_LDS : VALUES_LDS);
+      }
       for (int32_t g = 0; g < G; ++g) {
         const ilves::MolPlan& M = SPL.parts[g];
         const int32_t nbg = M.n - M.n_int;
@@ -1604,8 +1627,10 @@ ilves_status_t build_device_plan(ilves_plan* P) {
                                          M.n_upd, 2).total;
         for (int prec = 0; prec < 2; ++prec) {
           const int64_t vb = prec == 0 ? value_bytes<double>(M.n, M.n_up, M.n_l) : value_bytes<float>(M.n, M.n_up, M.n_l);
-          X.lds_extra[prec] = static_cast<int32_t>(align16(sb + vb));
-          P->split_lds[prec].push_back(static_cast<int>(align16(sb + vb) + split_lds_bytes(m, nbg, ew_total, n_sadj)));
+          const int64_t base = P->split_mode[prec].back() == ALL_LDS ? static_cast<int64_t>(align16(sb + vb))
+                                                                     : static_cast<int64_t>(align16(vb));
+          X.lds_extra[prec] = static_cast<int32_t>(base);
+          P->split_lds[prec].push_back(static_cast<int>(base + split_lds_bytes(m, nbg, ew_total, n_sadj)));
         }
         sparts.push_back(X);
       }
@@ -1850,6 +1875,7 @@ ilves_status_t build_device_plan(ilves_plan* P) {
   P->stats[12] = static_cast<int64_t>(P->splits.size());
   P->stats[13] = n_parts;
   P->stats[14] = max_sep;
+  P->stats[15] = std::count(P->split_mode[0].begin(), P->split_mode[0].end(), static_cast<int>(VALUES_LDS));
   return ILVES_OK;
 }
 
@@ -1871,7 +1897,8 @@ ilves_status_t finalize_groups(ilves_plan* P) {
   for (int prec = 0; prec < 2; ++prec) {
     P->split_launch[prec].clear();
     if (P->splits.empty()) continue;
-    const void* k = reinterpret_cast<const void*>(pick_split(prec == 1));
+    for (int mode : {ALL_LDS, VALUES_LDS}) {
+    const void* k = reinterpret_cast<const void*>(pick_split(prec == 1, mode));
     HIP_TRY(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsMax));
     auto capacity = [&](int lds, int64_t& cap) -> ilves_status_t {
       int per_cu = 0;
@@ -1881,7 +1908,9 @@ ilves_status_t finalize_groups(ilves_plan* P) {
     };
     SplitLaunch cur;
     cur.stream = P->split_stream[prec];
+    cur.mode = mode;
     for (size_t si = 0; si < P->splits.size(); ++si) {
+      if (P->split_mode[prec][si] != mode) continue;
       const int32_t first = P->split_first[si];
       const int32_t G = static_cast<int32_t>(P->splits[si].parts.size());
       int lds = 0;
@@ -1898,11 +1927,17 @@ ilves_status_t finalize_groups(ilves_plan* P) {
         cur.count = 0;
         cur.lds_bytes = 0;
       }
+      if (cur.count > 0 && first != cur.first + cur.count) {  // launches cover consecutive parts
+        P->split_launch[prec].push_back(cur);
+        cur.count = 0;
+        cur.lds_bytes = 0;
+      }
       if (cur.count == 0) cur.first = first;
       cur.count += G;
       cur.lds_bytes = std::max(cur.lds_bytes, lds);
     }
-    P->split_launch[prec].push_back(cur);
+    if (cur.count > 0) P->split_launch[prec].push_back(cur);
+    }
   }
   return ILVES_OK;
 }
@@ -1981,7 +2016,7 @@ ilves_status_t ilves_plan_create(int32_t n_atoms, int32_t n_constraints, const i
   po.ordering = P->opt.ordering;
   P->mols.reserve(mols.size());
   // molecules above split_rows constraints are split across workgroups
-  // when every part then fits in LDS with 16-bit indices
+  // when every part's factor values then fit in LDS with 16-bit indices
   const int32_t split_rows = P->opt.split_rows == 0 ? 4096 : P->opt.split_rows;
   const int32_t part_rows = P->opt.split_part_rows > 0 ? P->opt.split_part_rows : std::max(64, split_rows / 8);
   try {
@@ -1996,9 +2031,7 @@ ilves_status_t ilves_plan_create(int32_t n_atoms, int32_t n_constraints, const i
       for (const auto& M : sp.parts) {
         const int32_t nb = M.n - M.n_int;
         const bool wide = static_cast<int64_t>(M.n_up) + M.n_l >= 65535 || M.n >= 65535 || M.n_upd >= 65535;
-        const int64_t sb = struct_layout(M.n, M.n_levels, M.n_up, M.n_l, static_cast<int32_t>(M.plist.size()),
-                                         M.n_upd, 2).total;
-        if (wide || static_cast<int64_t>(align16(sb + value_bytes<double>(M.n, M.n_up, M.n_l))) +
+        if (wide || static_cast<int64_t>(align16(value_bytes<double>(M.n, M.n_up, M.n_l))) +
                             split_lds_bytes(sp.m, nb, ew_total, static_cast<int32_t>(sp.sadj_col.size())) > kLdsMax)
           fits = false;
       }
@@ -2203,7 +2236,7 @@ ilves_status_t solve_impl(ilves_plan_t P, const double* r, const double* r_u, co
   // split molecules first: their parts wait for each other, so they should
   // be dispatched before the persistent groups fill the device
   for (const SplitLaunch& l : P->split_launch[pr]) {
-    KernelFn k = pick_split(pr == 1);
+    KernelFn k = pick_split(pr == 1, l.mode);
     DevPlan dp = P->dp;
     dp.split = P->dp.split + l.first;
     const int32_t* list = nullptr;

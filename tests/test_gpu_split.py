@@ -163,3 +163,21 @@ def test_mixed_system_with_split_molecules():
         assert out["plan"].stats()["split_molecules"] == 2
         _check(sm, out, ref, f"mixed system/{prec}")
         assert np.array_equal(out["r_out"][-1], ru[-1])
+
+
+def test_split_with_values_only_in_lds():
+    """Angle-constrained protein whose parts' update lists do not fit in
+    LDS next to their factor values: the parts keep only the values in LDS
+    and read their structure through L2; FP64 and mixed against the
+    oracle."""
+    print("== split values-only placement", flush=True)
+    sm = S.add_h_angles(S.protein(80, seed=9))
+    ru = S.perturb(sm.r, 0.004, 5)
+    ref = _oracle(sm, ru)
+    for prec in (L.PREC_FP64, L.PREC_MIXED):
+        out = solve_once(sm, ru, TOL, prec, L.VARIANT_NEWTON, split_rows=1000, split_part_rows=512)
+        st = out["plan"].stats()
+        print(f"   {sm.n_constraints} constraints, parts {st['split_parts']}, separator {st['max_separator']}, "
+              f"values-only {st['split_values_lds']}", flush=True)
+        assert st["split_molecules"] == 1 and st["split_values_lds"] == 1, st
+        _check(sm, out, ref, f"h-angle protein values-only/{prec}")
