@@ -85,7 +85,9 @@ typedef struct {
                             Schur complement on the constraints that join the
                             parts); 0 = automatic (4096), < 0 = never          */
   int32_t split_part_rows; /* constraints per part of a split molecule;
-                            0 = automatic (split_rows / 8, at least 64)         */
+                            0 = automatic (about twelve parts of 384 to 1,024
+                            constraints, larger while the split exceeds its
+                            limits)                                             */
 } ilves_options_t;
 
 /* Fills *opt with defaults (FP64 Newton, lambda_0 = 0, automatic schedule). */

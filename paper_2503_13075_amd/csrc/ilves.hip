@@ -2018,13 +2018,13 @@ ilves_status_t ilves_plan_create(int32_t n_atoms, int32_t n_constraints, const i
   // molecules above split_rows constraints are split across workgroups
   // when every part's factor values then fit in LDS with 16-bit indices
   const int32_t split_rows = P->opt.split_rows == 0 ? 4096 : P->opt.split_rows;
-  const int32_t part_rows = P->opt.split_part_rows > 0 ? P->opt.split_part_rows : std::max(64, split_rows / 8);
+  const int32_t part_rows = P->opt.split_part_rows;  // <= 0: automatic
   try {
     for (const auto& c : mols) P->mols.push_back(ilves::plan_molecule(c, pairs, d, po));
     for (size_t i = 0; i < mols.size(); ++i) {
       if (split_rows < 0 || static_cast<int32_t>(mols[i].size()) <= split_rows) continue;
       ilves::SplitPlan sp;
-      if (!ilves::plan_split(mols[i], pairs, d, po, part_rows, sp)) continue;
+      if (!ilves::plan_split_auto(mols[i], pairs, d, po, part_rows, sp)) continue;
       bool fits = true;
       int32_t ew_total = 0;
       for (const auto& M : sp.parts) ew_total += (M.n - M.n_int) * (M.n - M.n_int + 1);

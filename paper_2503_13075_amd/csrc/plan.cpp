@@ -913,4 +913,13 @@ bool plan_split(const std::vector<int32_t>& cons, const int32_t* pairs, const do
   return true;
 }
 
+bool plan_split_auto(const std::vector<int32_t>& cons, const int32_t* pairs, const double* d,
+                     const PlanOptions& opt, int32_t part_rows, SplitPlan& out) {
+  if (part_rows > 0) return plan_split(cons, pairs, d, opt, part_rows, out);
+  const int32_t n = static_cast<int32_t>(cons.size());
+  for (int32_t rows = std::min(1024, std::max(384, n / 12)); rows <= 4096; rows = rows * 3 / 2)
+    if (plan_split(cons, pairs, d, opt, rows, out)) return true;
+  return false;
+}
+
 }  // namespace ilves

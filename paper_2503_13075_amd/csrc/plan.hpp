@@ -117,6 +117,13 @@ MolPlan plan_molecule(const std::vector<int32_t>& cons, const int32_t* pairs, co
 bool plan_split(const std::vector<int32_t>& cons, const int32_t* pairs, const double* d, const PlanOptions& opt,
                 int32_t part_rows, SplitPlan& out);
 
+// Split with an automatic part size when part_rows <= 0: about twelve parts
+// (measured best: fewer parts leave long per-part sweeps, more parts a large
+// separator system), 384 to 1,024 constraints each, then 1.5x larger parts
+// while the split exceeds the limits.
+bool plan_split_auto(const std::vector<int32_t>& cons, const int32_t* pairs, const double* d,
+                     const PlanOptions& opt, int32_t part_rows, SplitPlan& out);
+
 // Orderings of a graph given as sorted adjacency lists (exposed for tests).
 std::vector<int32_t> order_min_degree(const std::vector<std::vector<int32_t>>& adj);
 std::vector<int32_t> order_nested_dissection(const std::vector<std::vector<int32_t>>& adj, int leaf);

@@ -459,7 +459,6 @@ ilves_status_t ilves_plan_replay_host(int32_t n_atoms, int32_t n_constraints, co
     if (opt->split_rows != 0) split_rows = opt->split_rows;
     part_rows = opt->split_part_rows;
   }
-  if (part_rows <= 0) part_rows = std::max(64, split_rows / 8);
   std::vector<int32_t> free_atoms;
   auto mols = ilves::split_molecules(n_atoms, n_constraints, pairs, free_atoms);
   *n_molecules = static_cast<int32_t>(mols.size());
@@ -475,7 +474,7 @@ ilves_status_t ilves_plan_replay_host(int32_t n_atoms, int32_t n_constraints, co
     int32_t it = 0, st = 0;
     ilves::SplitPlan SP;
     if (split_rows > 0 && static_cast<int32_t>(mols[i].size()) > split_rows &&
-        ilves::plan_split(mols[i], pairs, d, po, part_rows, SP)) {
+        ilves::plan_split_auto(mols[i], pairs, d, po, part_rows, SP)) {
       ++n_split;
       for (const auto& M : SP.parts) {
         nslots += static_cast<int64_t>(M.n) + M.n_up + M.n_l;
