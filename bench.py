@@ -73,12 +73,12 @@ def measured_traffic(workload, variant, tuning):
     WRITE_SIZE runs, if they were taken from the current kernel sources with
     the same launch tuning (otherwise None)."""
     path = os.path.join(ROOT, "profiles", f"solve_kernel_{workload}_traffic.json")
-    if variant != "mixed" or not os.path.exists(path):
+    if not os.path.exists(path):
         return None
     from paper_2503_13075_amd.build import kernel_source_hash
     with open(path) as f:
         rec = json.load(f)
-    if rec.get("kernel_source_sha256_16") != kernel_source_hash():
+    if rec.get("variant", "mixed") != variant or rec.get("kernel_source_sha256_16") != kernel_source_hash():
         return None
     t = rec.get("tuning")
     if t is None or tuning is None or t["band_block"] != list(tuning["band_block"]) or \
@@ -131,7 +131,9 @@ def main():
     ap.add_argument("--pool", type=int, default=8, help="distinct r_u sets resident in HBM")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
-    ap.add_argument("--variants", default="fp64,mixed,learned", help="comma list of fp64,mixed,learned")
+    ap.add_argument("--variants", default="fp64,mixed,decoupled,learned",
+                    help="comma list of fp64, mixed, decoupled (mixed, each constraint's decoupled solution as "
+                         "lambda_0), learned (mixed, network lambda_0)")
     ap.add_argument("--eager", action="store_true", help="launch every step instead of replaying HIP graphs")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch tuning")
     ap.add_argument("--tuning", default=None,
@@ -175,7 +177,7 @@ def main():
     ncon_mol = torch.from_numpy(mol["n_con"].astype(np.int64)).to(dev)
     stream = torch.cuda.current_stream()
 
-    def run(precision, steps, warmup, learned=False):
+    def run(precision, steps, warmup, learned=False, warm=L.WARM_ZERO):
         iters = torch.zeros((steps, nm), dtype=torch.int32, device=dev)
         status = torch.full((steps, nm), -1, dtype=torch.int32, device=dev)
         fallback = torch.zeros((steps, nm), dtype=torch.int32, device=dev)
@@ -186,7 +188,8 @@ def main():
             if learned:
                 plan.solve_learned(r, pool[k % len(pool)], mass, 1e-12, r_out, lam, it, stt, fb, precision=precision)
             else:
-                plan.solve(r, pool[k % len(pool)], mass, 1e-12, r_out, lam, it, stt, precision=precision)
+                plan.solve(r, pool[k % len(pool)], mass, 1e-12, r_out, lam, it, stt, precision=precision,
+                           warm_start=warm)
 
         for w in range(warmup):
             one(w, wi, ws, None)
@@ -235,7 +238,7 @@ def main():
         viol = float(np.max(O.relative_violation(rp, sm.pairs, sm.d)))
         return viol
 
-    def rng_graph(steps, precision, learned):
+    def rng_graph(steps, precision, learned, warm=L.WARM_ZERO):
         """Many solves without the host: one captured graph draws the step's
         r_u on the device (Philox4x32-10 + Box-Muller, step index in device
         memory), solves, folds status and iterations into device
@@ -256,7 +259,7 @@ def main():
             if learned:
                 plan.solve_learned(r, ru, mass, 1e-12, r_out, lam, it, stt, precision=precision)
             else:
-                plan.solve(r, ru, mass, 1e-12, r_out, lam, it, stt, precision=precision)
+                plan.solve(r, ru, mass, 1e-12, r_out, lam, it, stt, precision=precision, warm_start=warm)
             torch.maximum(worst, stt, out=worst)
             it_sum.add_(it)
             L.counter_add(step, 1)
@@ -297,7 +300,8 @@ def main():
                 "ms_per_step_solve": solve_ms,
                 "constraints_per_s_solve": (sm.n_constraints / (solve_ms / 1e3)) if ok else 0.0,
                 "all_ok": ok, "newton_iters_mean_per_molecule": iters, "max_rel_violation_last": viol,
-                "variant": "learned" if learned else "mixed", "seed": 1, "sigma_nm": sigma}
+                "variant": "learned" if learned else ("decoupled" if warm == L.WARM_DECOUPLED else "mixed"),
+                "seed": 1, "sigma_nm": sigma}
 
     if args.calibrate_copy > 0:
         nb = args.calibrate_copy * (1 << 20)
@@ -341,11 +345,13 @@ def main():
         tunings[prec] = t
         return t
 
-    for name, prec in (("fp64", L.PREC_FP64), ("mixed", L.PREC_MIXED), ("learned", L.PREC_MIXED)):
+    for name, prec in (("fp64", L.PREC_FP64), ("mixed", L.PREC_MIXED), ("decoupled", L.PREC_MIXED),
+                       ("learned", L.PREC_MIXED)):
         if name not in wanted:
             continue
         tuning = tune(prec)
-        res = run(prec, args.steps, args.warmup, learned=(name == "learned"))
+        res = run(prec, args.steps, args.warmup, learned=(name == "learned"),
+                  warm=L.WARM_DECOUPLED if name == "decoupled" else L.WARM_ZERO)
         res["tuning"] = tuning
         res["max_rel_violation_last"] = check_last(res)
         ms = res["gpu_ms"] / args.steps
@@ -355,11 +361,11 @@ def main():
         log(f"{name}: {ms:.3f} ms/step, {res['constraints_per_s']:.3e} constraints/s, all ok {res['all_ok']}, "
             f"iters mean {res['iters_mean']:.2f} max {res['iters_max']}, last violation {res['max_rel_violation_last']:.2e}")
 
-    if "fp64" not in results or ("mixed" not in results and "learned" not in results):
+    heads = [k for k in ("mixed", "decoupled", "learned") if k in results and results[k]["all_ok"]]
+    if "fp64" not in results or not heads:
         print(json.dumps(results), flush=True)
         return
-    head_name = max((k for k in ("mixed", "learned") if k in results),
-                    key=lambda k: results[k]["constraints_per_s"])
+    head_name = max(heads, key=lambda k: results[k]["constraints_per_s"])
     head = results[head_name]
     abytes = algorithmic_bytes(sm, st)
     achieved = abytes / (head["ms_per_step"] / 1e3) / 1e9
@@ -384,8 +390,9 @@ def main():
         "data": "synthetic",
         "graph_replay": not args.eager,
         "config": dict(cfg, atoms=sm.n_atoms, constraints=sm.n_constraints,
-                       variant=("mixed precision Newton, learned lambda_0" if head_name == "learned"
-                                else "mixed precision Newton, lambda_0 = 0"),
+                       variant={"learned": "mixed precision Newton, learned lambda_0",
+                                "decoupled": "mixed precision Newton, lambda_0 = each constraint's decoupled solution",
+                                "mixed": "mixed precision Newton, lambda_0 = 0"}[head_name],
                        sigma_nm=sigma, tol=1e-12, split_molecules=st["split_molecules"],
                        split_parts=st["split_parts"]),
         "newton_iters": {k: v["iters_mean"] for k, v in results.items()},
@@ -398,7 +405,8 @@ def main():
                      "algorithmic_bytes_per_step": abytes, "kernel": "solve_kernel (all launch groups of one solve)"},
     }
     if args.rng_steps > 0:
-        out["rng_graph"] = rng_graph(args.rng_steps, L.PREC_MIXED, head_name == "learned")
+        out["rng_graph"] = rng_graph(args.rng_steps, L.PREC_MIXED, head_name == "learned",
+                                     L.WARM_DECOUPLED if head_name == "decoupled" else L.WARM_ZERO)
         log(f"rng graph: {out['rng_graph']}")
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")

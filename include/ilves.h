@@ -61,7 +61,7 @@ typedef enum {
 
 enum { ILVES_PREC_FP64 = 0, ILVES_PREC_MIXED = 1 };
 enum { ILVES_VARIANT_NEWTON = 0, ILVES_VARIANT_CHORD = 1 };
-enum { ILVES_WARM_ZERO = 0, ILVES_WARM_MLP = 1, ILVES_WARM_CALLER = 2 };
+enum { ILVES_WARM_ZERO = 0, ILVES_WARM_MLP = 1, ILVES_WARM_CALLER = 2, ILVES_WARM_DECOUPLED = 3 };
 
 typedef struct {
   int32_t precision;     /* ILVES_PREC_FP64: factor and solves in FP64;
@@ -74,7 +74,13 @@ typedef struct {
   int32_t warm_start;    /* ILVES_WARM_ZERO: lambda_0 = 0; ILVES_WARM_CALLER:
                             lambda_0 read from the lambda argument;
                             ILVES_WARM_MLP: lambda_0 from the loaded network
-                            (see ilves_solve_learned)                           */
+                            (see ilves_solve_learned);
+                            ILVES_WARM_DECOUPLED: lambda_0 of each constraint
+                            from its own quadratic |u_k - lambda C_kk e_k|^2 =
+                            d_k^2 (the constraint taken alone, root nearest 0;
+                            the Newton step from 0 when there is none),
+                            computed in the solve; a molecule restarts from 0
+                            when that start is not better than 0 (as for MLP) */
   int32_t block_threads; /* cap on the threads per workgroup of molecules kept in
                             LDS (64..1024); 0 = automatic; molecules that do not
                             fit in LDS always use 512 or 1024                   */
@@ -212,7 +218,8 @@ ilves_status_t ilves_plan_tune(ilves_plan_t plan, const ilves_tuning_t* t);
  *   r_out      device double [3][n_atoms]  constrained positions; atoms in no
  *              constraint get r_u.  May alias neither r nor r_u.
  *   lambda     device double [n_constraints] multipliers in input order; read
- *              as lambda_0 when warm_start = ILVES_WARM_CALLER or MLP
+ *              as lambda_0 when warm_start = ILVES_WARM_CALLER or MLP (not
+ *              read for ILVES_WARM_ZERO or ILVES_WARM_DECOUPLED)
  *   iters      device int32 [num_molecules] linear solves per molecule
  *   status     device int32 [num_molecules] ILVES_OK, ILVES_ERR_SINGULAR,
  *              ILVES_ERR_NOT_CONVERGED or ILVES_ERR_NONFINITE per molecule

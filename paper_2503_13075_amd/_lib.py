@@ -20,7 +20,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "ilves.h")
 OK, ERR_ARG, ERR_TOPOLOGY, ERR_HIP, ERR_NOMEM, ERR_SINGULAR, ERR_NOT_CONVERGED, ERR_NONFINITE, ERR_UNSUPPORTED, ERR_TIMEOUT = range(10)
 PREC_FP64, PREC_MIXED = 0, 1
 VARIANT_NEWTON, VARIANT_CHORD = 0, 1
-WARM_ZERO, WARM_MLP, WARM_CALLER = 0, 1, 2
+WARM_ZERO, WARM_MLP, WARM_CALLER, WARM_DECOUPLED = 0, 1, 2, 3
 STAT_NAMES = ["molecules", "constraints", "atoms", "factor_entries", "fill", "updates", "max_levels",
               "sum_levels", "mol_lds", "mol_workspace", "workspace_bytes", "plan_bytes", "split_molecules",
               "split_parts", "max_separator", "split_values_lds"]

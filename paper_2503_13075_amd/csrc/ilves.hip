@@ -87,7 +87,8 @@ struct SolveArgs {
   double tol;
   int32_t n_atoms;
   int32_t max_iter;
-  int32_t warm;      // 0: lambda_0 = 0, 1: read lambda, 2: read the network's lambda (with fallback)
+  int32_t warm;      // 0: lambda_0 = 0, 1: read lambda, 2: read the network's lambda (with fallback),
+                     // 3: each constraint's decoupled solution (with fallback)
   int32_t chord;     // 0: Newton, 1: chord
 };
 
@@ -275,6 +276,21 @@ __device__ __forceinline__ double recip(double a) {
   return __builtin_fma(__builtin_fma(-a, r, 1.0), r, r);
 }
 
+// Decoupled start: the multiplier of constraint k taken alone, the root
+// nearest 0 of |u - lambda cd e|^2 = d^2, i.e. a l^2 + b l + c = 0 with
+// a = cd^2 |e|^2, b = -2 cd (u . e), c = |u|^2 - d^2, in the cancellation-free
+// form c / q, q = (-b + sqrt(b^2 - 4ac)) / 2; without a real root (or with
+// u . e <= 0) the Newton step from 0, -c / b (0 if b = 0).
+__device__ inline double decoupled_lambda(double u0, double u1, double u2, double e0, double e1, double e2,
+                                          double cd, double d2) {
+  const double c = u0 * u0 + u1 * u1 + u2 * u2 - d2;
+  const double b = -2.0 * cd * (u0 * e0 + u1 * e1 + u2 * e2);
+  const double a = cd * cd * (e0 * e0 + e1 * e1 + e2 * e2);
+  const double disc = b * b - 4.0 * a * c;
+  if (b < 0.0 && disc >= 0.0) return c / (0.5 * (-b + sqrt(disc)));
+  return b != 0.0 ? -c / b : 0.0;
+}
+
 // integer min by value (no reference to a temporary, which would keep
 // small arrays out of registers)
 __device__ __forceinline__ int32_t imin(int32_t a, int32_t b) { return a < b ? a : b; }
@@ -432,7 +448,10 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(const DevPlan P, const int
     const int32_t ga = rga[k], gb = rgb[k];
     const double a0 = ux[ga] - ux[gb], a1 = ux[S + ga] - ux[S + gb], a2 = ux[2 * S + ga] - ux[2 * S + gb];
     const double e0 = rx[ga] - rx[gb], e1 = rx[S + ga] - rx[S + gb], e2 = rx[2 * S + ga] - rx[2 * S + gb];
-    st_rec(er + 4 * k, e0, e1, e2, A.warm ? A.lambda[cid[k]] : 0.0);
+    const double cdk = 1.0 / A.mass[ga] + 1.0 / A.mass[gb];
+    const double lam0 = A.warm == 3 ? decoupled_lambda(a0, a1, a2, e0, e1, e2, cdk, d2[k])
+                                    : (A.warm ? A.lambda[cid[k]] : 0.0);
+    st_rec(er + 4 * k, e0, e1, e2, lam0);
     if constexpr (SPLIT) {
       if (k >= ni) {
         const int32_t v = P.bsep[sp.bsep_off + (k - ni)];
@@ -447,7 +466,7 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(const DevPlan P, const int
     u_x[k] = a0;
     u_y[k] = a1;
     u_z[k] = a2;
-    cd[k] = 1.0 / A.mass[ga] + 1.0 / A.mass[gb];
+    cd[k] = cdk;
     v0 = fmax(v0, fabs(a0 * a0 + a1 * a1 + a2 * a2 - d2[k]) / (2.0 * d2[k]));
   }
   const int32_t* __restrict__ gcoef = P.gcoef + md.coef_off;
@@ -980,8 +999,8 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(const DevPlan P, const int
       gmax = uni(gm);
       sing_all = uni(sing_all);
     }
-    if (A.warm == 2 && !fell_back) {
-      // learned start: keep it only while it beats lambda = 0 and the
+    if (A.warm >= 2 && !fell_back) {
+      // learned or decoupled start: keep it only while it beats lambda = 0 and the
       // residual does not rise twice in a row; otherwise restart from 0
       rises = (it > 0 && gmax > prev_gmax) ? rises + 1 : 0;
       if ((it == 0 && !(gmax < rel_zero)) || rises >= 2) {
@@ -1099,8 +1118,10 @@ __global__ void __launch_bounds__(256) small_kernel(const SmallMol* __restrict__
       e[k][c] = A.r[c * S + ga] - A.r[c * S + gb];
       u[k][c] = ru[a][c] - ru[b][c];
     }
-    lam[k] = (k < nc && A.warm) ? A.lambda[M.cid[k]] : 0.0;
     cdiag[k] = invm[a] + invm[b];
+    lam[k] = k >= nc ? 0.0
+             : A.warm == 3 ? decoupled_lambda(u[k][0], u[k][1], u[k][2], e[k][0], e[k][1], e[k][2], cdiag[k], M.d2[k])
+             : A.warm ? A.lambda[M.cid[k]] : 0.0;
     if (k < nc)
       v0 = fmax(v0, fabs(u[k][0] * u[k][0] + u[k][1] * u[k][1] + u[k][2] * u[k][2] - M.d2[k]) / (2.0 * M.d2[k]));
   }
@@ -1140,7 +1161,7 @@ __global__ void __launch_bounds__(256) small_kernel(const SmallMol* __restrict__
       if (!(rel <= DBL_MAX)) rel = INFINITY;
       if (k < nc) gmax = fmax(gmax, rel);
     }
-    if (A.warm == 2 && !fell_back) {
+    if (A.warm >= 2 && !fell_back) {
       rises = (it > 0 && gmax > prev) ? rises + 1 : 0;
       if ((it == 0 && !(gmax < v0)) || rises >= 2) {
         fell_back = 1;
@@ -2296,8 +2317,10 @@ ilves_status_t ilves_solve_ex(ilves_plan_t P, const double* r, const double* r_u
   if (warm_start == ILVES_WARM_MLP)
     return ilves_solve_learned(P, r, r_u, mass, tol, precision, variant, max_iter, r_out, lambda, iters, status,
                                nullptr, hip_stream);
-  if (warm_start != ILVES_WARM_ZERO && warm_start != ILVES_WARM_CALLER) return fail(ILVES_ERR_ARG, "bad warm_start");
-  return solve_impl(P, r, r_u, mass, tol, precision, variant, warm_start == ILVES_WARM_CALLER ? 1 : 0, max_iter,
+  if (warm_start != ILVES_WARM_ZERO && warm_start != ILVES_WARM_CALLER && warm_start != ILVES_WARM_DECOUPLED)
+    return fail(ILVES_ERR_ARG, "bad warm_start");
+  return solve_impl(P, r, r_u, mass, tol, precision, variant,
+                    warm_start == ILVES_WARM_CALLER ? 1 : warm_start == ILVES_WARM_DECOUPLED ? 3 : 0, max_iter,
                     r_out, lambda, iters, status, nullptr, stream);
 }
 

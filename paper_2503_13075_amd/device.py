@@ -33,7 +33,7 @@ class DeviceSystem:
 
 
 def solve_once(sysm, r_u, tol=1e-12, precision=L.PREC_FP64, variant=L.VARIANT_NEWTON, max_iter=0,
-               lam0=None, plan=None, **plan_kw):
+               lam0=None, plan=None, warm=None, **plan_kw):
     """Plans (unless given), uploads, solves once, and returns host arrays."""
     import torch
     own = plan is None
@@ -41,7 +41,7 @@ def solve_once(sysm, r_u, tol=1e-12, precision=L.PREC_FP64, variant=L.VARIANT_NE
         plan = L.Plan(sysm.n_atoms, sysm.pairs, sysm.d, **plan_kw)
     ds = DeviceSystem(sysm).alloc_status(plan.n_molecules)
     ru = ds.upload_ru(r_u)
-    warm = L.WARM_ZERO
+    warm = L.WARM_ZERO if warm is None else warm
     if lam0 is not None:
         ds.lam.copy_(torch.from_numpy(np.asarray(lam0, dtype=np.float64)))
         warm = L.WARM_CALLER
