@@ -2,7 +2,7 @@
 
     python -m paper_2503_13075_amd.rocprof_summary trace <dir>
     python -m paper_2503_13075_amd.rocprof_summary traffic <fetch dir> <write dir> <solves> <copy MiB> \
-        <algorithmic bytes per solve> [json out] [launch tuning as JSON]
+        <algorithmic bytes per solve> [json out] [launch tuning as JSON] [bench variant]
 
 ``trace`` prints the kernel statistics of a ``--kernel-trace --stats`` run as
 a markdown table.  ``traffic`` turns two ``--pmc FETCH_SIZE`` / ``--pmc
@@ -114,6 +114,8 @@ def main(argv=None):
         res["kernel_source_sha256_16"] = kernel_source_hash()
         if len(a) > 7:
             res["tuning"] = json.loads(a[7])
+        if len(a) > 8:
+            res["variant"] = a[8]
         text = json.dumps(res, indent=1)
         if len(a) > 6:
             with open(a[6], "w") as f:
