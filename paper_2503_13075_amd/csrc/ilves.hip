@@ -92,7 +92,7 @@ struct SolveArgs {
   int32_t chord;     // 0: Newton, 1: chord
 };
 
-// FP64 workspace of a molecule: per row {e, lambda} (4n), u (3n), C_kk (n),
+// FP64 workspace of a molecule: per row {e, lambda} (4n) and {u, C_kk} (4n),
 // the couplings of every off-diagonal slot, 1/m (s + 1)
 __host__ __device__ inline size_t ws_vec_bytes(int32_t n, int32_t s, int32_t n_up, int32_t n_l) {
   return align16(8 * (8 * static_cast<size_t>(n) + n_up + n_l + s + 1));
@@ -385,11 +385,8 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(const DevPlan P, const int
   // ---- workspace and values
   unsigned char* wsb = A.ws + md.ws_off;
   double* __restrict__ er = reinterpret_cast<double*>(wsb);  // per row {e_x, e_y, e_z, lambda}
-  double* __restrict__ u_x = er + 4 * static_cast<int64_t>(n);
-  double* __restrict__ u_y = u_x + n;
-  double* __restrict__ u_z = u_y + n;
-  double* __restrict__ cd = u_z + n;
-  double* __restrict__ cf = cd + n;
+  double* __restrict__ uc = er + 4 * static_cast<int64_t>(n);  // per row {u_x, u_y, u_z, C_kk}
+  double* __restrict__ cf = uc + 4 * static_cast<int64_t>(n);
   double* __restrict__ invm = cf + n_up + n_l;
   T* __restrict__ F;
   if (MODE == ALL_LDS) F = reinterpret_cast<T*>(smem + Lo.total);
@@ -463,10 +460,7 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(const DevPlan P, const int
         }
       }
     }
-    u_x[k] = a0;
-    u_y[k] = a1;
-    u_z[k] = a2;
-    cd[k] = cdk;
+    st_rec(uc + 4 * k, a0, a1, a2, cdk);
     v0 = fmax(v0, fabs(a0 * a0 + a1 * a1 + a2 * a2 - d2[k]) / (2.0 * d2[k]));
   }
   const int32_t* __restrict__ gcoef = P.gcoef + md.coef_off;
@@ -539,7 +533,7 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(const DevPlan P, const int
   // batch discarded) so that their loads are issued together.
   auto build_row = [&](int32_t k, double px, double py, double pz) {
     const Rec ek = ld_rec(er + 4 * k);
-    set_diag(k, static_cast<T>(cd[k] * (px * ek.x + py * ek.y + pz * ek.z)));
+    set_diag(k, static_cast<T>(uc[4 * k + 3] * (px * ek.x + py * ek.y + pz * ek.z)));
     const int32_t q0 = up_start[k], nq = up_start[k + 1] - q0;
     const int32_t t0 = l_start[k], tot = nq + (l_start[k + 1] - t0);
     for (int32_t b = 0; b < tot; b += kBatchN) {
@@ -897,10 +891,11 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(const DevPlan P, const int
     double vmax = 0.0;
     for (int32_t k = tid; k < n; k += BLOCK) {
       const Rec ek = ld_rec(er + 4 * k);
-      const double lk = ek.l * cd[k];
-      double px = u_x[k] - lk * ek.x;
-      double py = u_y[k] - lk * ek.y;
-      double pz = u_z[k] - lk * ek.z;
+      const Rec uk = ld_rec(uc + 4 * k);
+      const double lk = ek.l * uk.l;
+      double px = uk.x - lk * ek.x;
+      double py = uk.y - lk * ek.y;
+      double pz = uk.z - lk * ek.z;
       const int32_t q0 = up_start[k], nq = up_start[k + 1] - q0;
       const int32_t t0 = l_start[k], tot = nq + (l_start[k + 1] - t0);
       int32_t sb[kBatchN];
@@ -959,7 +954,7 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(const DevPlan P, const int
       }
       if (!A.chord) {
         if (tot <= kBatchN) {
-          set_diag(k, static_cast<T>(cd[k] * (px * ek.x + py * ek.y + pz * ek.z)));
+          set_diag(k, static_cast<T>(uk.l * (px * ek.x + py * ek.y + pz * ek.z)));
 #pragma unroll
           for (int i = 0; i < kBatchN; ++i)
             if (i < tot) F[sb[i]] = static_cast<T>(cb[i] * (px * nb[i].x + py * nb[i].y + pz * nb[i].z));
