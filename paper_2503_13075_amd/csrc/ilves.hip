@@ -1270,6 +1270,7 @@ KernelFn pick_big(int block) {
 // Block size a kernel is compiled for: every launch uses exactly this.
 int kernel_block(int mode, bool wide, int block) {
   if (mode == ALL_LDS && !wide) return block <= 64 ? 64 : block <= 128 ? 128 : block <= 256 ? 256 : block <= 512 ? 512 : 1024;
+  if (mode == VALUES_LDS && !wide) return block <= 256 ? 256 : block <= 512 ? 512 : 1024;
   return block <= 512 ? 512 : 1024;
 }
 
@@ -1278,7 +1279,7 @@ KernelFn pick_mode(int mode, bool wide, int block) {
   if (wide) return mode == VALUES_LDS ? pick_big<T, int32_t, VALUES_LDS>(block) : pick_big<T, int32_t, GLOBAL>(block);
   if (mode == ALL_LDS) return pick_block<T, uint16_t, ALL_LDS>(block);
   if (mode == STRUCT_LDS) return pick_big<T, uint16_t, STRUCT_LDS>(block);
-  if (mode == VALUES_LDS) return pick_big<T, uint16_t, VALUES_LDS>(block);
+  if (mode == VALUES_LDS) return block <= 256 ? solve_kernel<T, uint16_t, VALUES_LDS, 256> : pick_big<T, uint16_t, VALUES_LDS>(block);
   return pick_big<T, uint16_t, GLOBAL>(block);
 }
 
@@ -1757,7 +1758,7 @@ ilves_status_t build_device_plan(ilves_plan* P) {
       Group g;
       g.mode = b.first.mode;
       g.wide = b.first.wide;
-      // large molecules run with 512 or 1024 threads whatever the cap
+      // molecules outside LDS run with 512 or 1024 threads whatever the cap
       g.block = kernel_block(g.mode, g.wide, std::min(band_block[b.first.band], cap));
       int mx = 0;
       for (int32_t i : b.second) mx = std::max(mx, lds_of[i]);
