@@ -322,36 +322,38 @@ def main():
         plan.load_mlp(params, norm)
     tunings = {}
 
-    def tune(prec):
-        """Autotunes the launch of this precision once (untimed)."""
+    def tune(prec, warm=L.WARM_ZERO):
+        """Autotunes the launch of this precision and start once (untimed):
+        the fastest launch depends on the iteration counts the start gives."""
         if args.tuning or args.no_autotune:
             t = json.loads(args.tuning) if args.tuning else {"band_block": [64, 128, 256, 512, 1024], "lds_limit": 0}
             plan.tune(band_block=t["band_block"], lds_limit=t["lds_limit"])
             return {"band_block": t["band_block"], "lds_limit": t["lds_limit"], "autotuned": False}
-        if prec in tunings:
-            plan.tune(band_block=tunings[prec]["band_block"], lds_limit=tunings[prec]["lds_limit"])
-            return tunings[prec]
+        if (prec, warm) in tunings:
+            plan.tune(band_block=tunings[(prec, warm)]["band_block"], lds_limit=tunings[(prec, warm)]["lds_limit"])
+            return tunings[(prec, warm)]
         from paper_2503_13075_amd import autotune as AT
         it = torch.zeros(nm, dtype=torch.int32, device=dev)
         stt = torch.zeros(nm, dtype=torch.int32, device=dev)
-        key = AT.plan_key(plan, prec, L.VARIANT_NEWTON)
-        run_one = lambda: plan.solve(r, pool[0], mass, 1e-12, r_out, lam, it, stt, precision=prec)  # noqa: E731
+        key = AT.plan_key(plan, prec, L.VARIANT_NEWTON, "decoupled" if warm == L.WARM_DECOUPLED else "zero")
+        run_one = lambda: plan.solve(r, pool[0], mass, 1e-12, r_out, lam, it, stt, precision=prec,  # noqa: E731
+                                     warm_start=warm)
         if args.retune:
             t = dict(AT.autotune(plan, run_one, reps=10), cached=False)
         else:
             t = AT.tuned(plan, run_one, key, path=args.tuning_file, reps=10,
                          store_path=os.path.join(ROOT, "gpurun_out", "tuning_new.json"))
-        log(f"tuning precision {prec} (key {key}): {t}")
-        tunings[prec] = t
+        log(f"tuning precision {prec} start {warm} (key {key}): {t}")
+        tunings[(prec, warm)] = t
         return t
 
     for name, prec in (("fp64", L.PREC_FP64), ("mixed", L.PREC_MIXED), ("decoupled", L.PREC_MIXED),
                        ("learned", L.PREC_MIXED)):
         if name not in wanted:
             continue
-        tuning = tune(prec)
-        res = run(prec, args.steps, args.warmup, learned=(name == "learned"),
-                  warm=L.WARM_DECOUPLED if name == "decoupled" else L.WARM_ZERO)
+        warm = L.WARM_DECOUPLED if name == "decoupled" else L.WARM_ZERO
+        tuning = tune(prec, warm)
+        res = run(prec, args.steps, args.warmup, learned=(name == "learned"), warm=warm)
         res["tuning"] = tuning
         res["max_rel_violation_last"] = check_last(res)
         ms = res["gpu_ms"] / args.steps

@@ -4,8 +4,8 @@ The plan's launch groups have two kinds of knobs that change speed but not
 the arithmetic: the threads per workgroup of each LDS band and the LDS a
 molecule may use (which moves molecules between the all-in-LDS kernel and the
 partly-in-LDS ones).  ``autotune`` times the solve of a representative input
-for each candidate by coordinate descent over the bands, then over the LDS
-limit, keeps the fastest and records it in a JSON cache keyed by the device,
+for each candidate by coordinate descent over the LDS limit and the bands,
+repeated while it gains, keeps the fastest and records it in a JSON cache keyed by the device,
 the plan's shape and the solve options, so that later runs on the same
 workload apply it without timing again.
 """
@@ -49,39 +49,44 @@ def _timer(run, reps):
     return best
 
 
-def autotune(plan: L.Plan, run, reps: int = 10, log=None) -> dict:
+def autotune(plan: L.Plan, run, reps: int = 10, log=None, passes: int = 3) -> dict:
     """Coordinate descent over the plan's tuning.  ``run()`` enqueues one
     solve on torch's current stream with the plan; it is timed ``reps`` times
-    per candidate (best of two rounds).  Leaves the plan on the fastest
-    tuning and returns it with the default and tuned times (ms)."""
+    per candidate (best of two rounds).  A pass tries every LDS limit, then
+    every block size band by band, keeping a change when it saves more than
+    1%; passes repeat (the best block sizes depend on which molecules the
+    LDS limit keeps in LDS, and back) until one brings no gain.  Leaves the
+    plan on the fastest tuning and returns it with the default and tuned
+    times (ms)."""
     cur = plan.get_tuning()
     cur = {"band_block": list(cur["band_block"]), "lds_limit": 0}
     plan.tune(**cur)
     base = best = _timer(run, reps)
     if log:
         log(f"autotune: default {cur} {base:.4f} ms")
-    for band, cands in enumerate(BAND_CANDIDATES):
-        for c in cands:
-            if c == cur["band_block"][band]:
-                continue
-            trial = {"band_block": list(cur["band_block"]), "lds_limit": cur["lds_limit"]}
-            trial["band_block"][band] = c
-            plan.tune(**trial)
-            t = _timer(run, reps)
-            if log:
-                log(f"autotune: band {band} block {c}: {t:.4f} ms")
-            if t < best * 0.99:
-                best, cur = t, trial
-    for lim in LDS_CANDIDATES:
-        if lim == cur["lds_limit"]:
-            continue
-        trial = {"band_block": list(cur["band_block"]), "lds_limit": lim}
+
+    def consider(trial, what):
+        nonlocal best, cur
         plan.tune(**trial)
         t = _timer(run, reps)
         if log:
-            log(f"autotune: lds_limit {lim}: {t:.4f} ms")
+            log(f"autotune: {what}: {t:.4f} ms")
         if t < best * 0.99:
             best, cur = t, trial
+
+    for _ in range(passes):
+        start = best
+        for lim in LDS_CANDIDATES:
+            if lim != cur["lds_limit"]:
+                consider({"band_block": list(cur["band_block"]), "lds_limit": lim}, f"lds_limit {lim}")
+        for band, cands in enumerate(BAND_CANDIDATES):
+            for c in cands:
+                if c != cur["band_block"][band]:
+                    trial = {"band_block": list(cur["band_block"]), "lds_limit": cur["lds_limit"]}
+                    trial["band_block"][band] = c
+                    consider(trial, f"band {band} block {c}")
+        if not best < start * 0.99:
+            break
     plan.tune(**cur)
     return {"band_block": cur["band_block"], "lds_limit": cur["lds_limit"], "ms_default": base, "ms_tuned": best}
 
