@@ -407,8 +407,9 @@ def main():
                      "algorithmic_bytes_per_step": abytes, "kernel": "solve_kernel (all launch groups of one solve)"},
     }
     if args.rng_steps > 0:
-        out["rng_graph"] = rng_graph(args.rng_steps, L.PREC_MIXED, head_name == "learned",
-                                     L.WARM_DECOUPLED if head_name == "decoupled" else L.WARM_ZERO)
+        head_warm = L.WARM_DECOUPLED if head_name == "decoupled" else L.WARM_ZERO
+        tune(L.PREC_MIXED, head_warm)  # the head variant's launch tuning
+        out["rng_graph"] = rng_graph(args.rng_steps, L.PREC_MIXED, head_name == "learned", head_warm)
         log(f"rng graph: {out['rng_graph']}")
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
