@@ -7,7 +7,10 @@ main text's section on constrained dynamics, Eqs. (nonlinear:1a)-(1c)):
 
 Every step runs in the library's kernels (kick/drift, solve, finish); this
 module only holds the device buffers and the order of the calls.  Forces are
-the caller's (a device tensor, or a callable returning one).
+the caller's (a device tensor, or a callable returning one).  The solve of a
+step may start from lambda = 0, from each constraint's decoupled solution, or
+from the previous step's multipliers (which change little from one step to
+the next; the first step then starts from 0).
 """
 from __future__ import annotations
 
@@ -19,7 +22,7 @@ from .synth import System, soa
 
 class ConstrainedLeapfrog:
     def __init__(self, sysm: System, v0: np.ndarray, h: float, tol: float = 1e-12, precision: int = L.PREC_FP64,
-                 variant: int = L.VARIANT_NEWTON, device: str = "cuda", plan: L.Plan = None):
+                 variant: int = L.VARIANT_NEWTON, device: str = "cuda", plan: L.Plan = None, warm: str = "zero"):
         import torch
         self.torch = torch
         self.sysm = sysm
@@ -27,6 +30,10 @@ class ConstrainedLeapfrog:
         self.tol = float(tol)
         self.precision = precision
         self.variant = variant
+        if warm not in ("zero", "decoupled", "previous"):
+            raise ValueError("warm must be 'zero', 'decoupled' or 'previous'")
+        self.warm = warm
+        self.steps = 0
         self.plan = plan or L.Plan(sysm.n_atoms, sysm.pairs, sysm.d)
         dev = device
         self.r = torch.from_numpy(soa(sysm.r)).to(dev)
@@ -45,8 +52,11 @@ class ConstrainedLeapfrog:
         every solve is folded into ``worst`` (elementwise maximum)."""
         torch = self.torch
         L.md_kick_drift(self.r, self.v, f, self.mass, self.h, self.r_u, stream)
+        warm = {"zero": L.WARM_ZERO, "decoupled": L.WARM_DECOUPLED,
+                "previous": L.WARM_CALLER if self.steps > 0 else L.WARM_ZERO}[self.warm]
         self.plan.solve(self.r, self.r_u, self.mass, self.tol, self.r_new, self.lam, self.iters, self.status,
-                        precision=self.precision, variant=self.variant, stream=stream)
+                        precision=self.precision, variant=self.variant, warm_start=warm, stream=stream)
+        self.steps += 1
         L.md_finish(self.r, self.r_new, self.h, self.v, stream)
         torch.maximum(self.worst, self.status, out=self.worst)
 

@@ -153,3 +153,28 @@ def test_leapfrog_matches_cpu_integration():
         assert np.max(np.abs(v_gpu - v_cpu)) <= 1e-10 / h, step
         r_cpu, v_cpu = r_gpu, v_gpu      # continue from the device state (compare one step at a time)
     assert np.all(ig.worst.cpu().numpy() == L.OK)
+
+
+def test_leapfrog_warm_starts_agree_and_save_iterations():
+    """The same trajectory (to the solve tolerance) from lambda_0 = 0, from
+    the decoupled start and from the previous step's multipliers; the
+    previous step's multipliers need fewer Newton iterations."""
+    import torch
+    sm = S.concat([S.random_tree(60, seed=71), S.protein(20, seed=72)], spacing=2.0)
+    rng = np.random.default_rng(73)
+    v0 = rng.normal(0.0, 0.3, size=(sm.n_atoms, 3))
+    h, k_trap = 2e-3, 50.0
+    runs = {}
+    for warm in ("zero", "decoupled", "previous"):
+        ig = MD.ConstrainedLeapfrog(sm, v0, h, tol=1e-12, warm=warm)
+        its = []
+        for step in range(20):
+            r, _ = ig.state()
+            ig.step(torch.from_numpy(S.soa(-k_trap * r)).cuda())
+            its.append(ig.iters[:ig.plan.n_molecules].cpu().numpy().mean())
+        assert np.all(ig.worst.cpu().numpy() == L.OK)
+        runs[warm] = (ig.state()[0], np.mean(its[1:]))
+        print(f"warm {warm}: mean Newton iterations (steps 2-20) {runs[warm][1]:.2f}", flush=True)
+    for warm in ("decoupled", "previous"):
+        assert np.max(np.abs(runs[warm][0] - runs["zero"][0])) <= 1e-9
+    assert runs["previous"][1] < runs["zero"][1]
