@@ -123,6 +123,18 @@ ilves_status_t ilves_plan_destroy(ilves_plan_t plan);
 int32_t ilves_plan_num_molecules(ilves_plan_t plan);
 
 /*
+ * Bound on the polls of a split molecule's barrier wait (the workgroups of
+ * a split molecule meet twice per Newton iteration; every wait polls a
+ * counter in device memory with a short sleep).  Default 2^22 polls
+ * (seconds).  A workgroup whose wait runs out marks the molecule poisoned,
+ * which releases every other waiter; the molecule reports ILVES_ERR_TIMEOUT
+ * in this and every later solve of the plan.  A small limit forces that
+ * path (used to test it).  Takes effect at the next solve enqueued.
+ * Errors: ILVES_ERR_ARG (NULL plan, polls < 0).
+ */
+ilves_status_t ilves_plan_set_wait_limit(ilves_plan_t plan, int32_t polls);
+
+/*
  * Plan statistics, host int64 array of ILVES_STAT_COUNT entries:
  *   [0] molecules, [1] constraints, [2] atoms in constraints,
  *   [3] stored factor entries, [4] fill entries, [5] factor updates,

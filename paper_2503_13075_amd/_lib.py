@@ -81,6 +81,8 @@ def lib() -> ctypes.CDLL:
     L.ilves_plan_destroy.restype = ctypes.c_int
     L.ilves_plan_num_molecules.argtypes = [_P]
     L.ilves_plan_num_molecules.restype = ctypes.c_int32
+    L.ilves_plan_set_wait_limit.argtypes = [_P, ctypes.c_int32]
+    L.ilves_plan_set_wait_limit.restype = ctypes.c_int
     L.ilves_plan_stats.argtypes = [_P, _I64P]
     L.ilves_plan_stats.restype = ctypes.c_int
     L.ilves_plan_molecules.argtypes = [_P, _I32P, _I32P, _I32P, _I32P]
@@ -215,6 +217,11 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+    def set_wait_limit(self, polls: int):
+        """Bound on the polls of a split molecule's barrier wait (see
+        ilves_plan_set_wait_limit)."""
+        check(self._L.ilves_plan_set_wait_limit(self._h, int(polls)))
 
     def stats(self) -> dict:
         st = np.zeros(len(STAT_NAMES), np.int64)

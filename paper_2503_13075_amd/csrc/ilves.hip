@@ -90,6 +90,7 @@ struct SolveArgs {
   int32_t warm;      // 0: lambda_0 = 0, 1: read lambda, 2: read the network's lambda (with fallback),
                      // 3: each constraint's decoupled solution (with fallback)
   int32_t chord;     // 0: Newton, 1: chord
+  int32_t wait_limit;  // polls of a split molecule's barrier wait before it gives up
 };
 
 // FP64 workspace of a molecule: per row {e, lambda} (4n) and {u, C_kk} (4n),
@@ -205,11 +206,10 @@ __device__ __forceinline__ int32_t ld_coh(const int32_t* p) {
 // per workgroup arrives on the counter, the last arrival resets it and
 // advances the generation, the others wait for the generation to change.
 // Readers use ld_coh for data written by other workgroups, so no acquire
-// invalidation is needed.  The wait is bounded: after kSpinCap polls
-// (seconds) the workgroup marks the molecule poisoned, which also releases
-// every other waiter, and reports false.
-constexpr int32_t kSpinCap = 1 << 22;
-__device__ bool grid_barrier(uint32_t* bar, int32_t n_parts, int32_t* flag) {
+// invalidation is needed.  The wait is bounded: after wait_limit polls
+// (2^22 by default, seconds) the workgroup marks the molecule poisoned,
+// which also releases every other waiter, and reports false.
+__device__ bool grid_barrier(uint32_t* bar, int32_t n_parts, int32_t wait_limit, int32_t* flag) {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -227,7 +227,7 @@ __device__ bool grid_barrier(uint32_t* bar, int32_t n_parts, int32_t* flag) {
             good = 0;
             break;
           }
-          if (i >= kSpinCap) {
+          if (i >= wait_limit) {
             __hip_atomic_store(bar + 2, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             good = 0;
             break;
@@ -862,7 +862,7 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(const DevPlan P, const int
       pxa[sp.part].rel0 = rel_zero;
       pxa[sp.part].singular = singular;
     }
-    bool stop = !grid_barrier(bar, sp.n_parts, &next_slot);
+    bool stop = !grid_barrier(bar, sp.n_parts, A.wait_limit, &next_slot);
     if (stop) {
       st_code = ILVES_ERR_TIMEOUT;
     } else {
@@ -985,7 +985,7 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(const DevPlan P, const int
         pxa[sp.part].viol = gmax;
         pxa[sp.part].singular = singular;
       }
-      if (!grid_barrier(bar, sp.n_parts, &next_slot)) { st_code = ILVES_ERR_TIMEOUT; break; }
+      if (!grid_barrier(bar, sp.n_parts, A.wait_limit, &next_slot)) { st_code = ILVES_ERR_TIMEOUT; break; }
       double gm = 0.0;
       for (int32_t q = 0; q < sp.n_parts; ++q) {
         gm = fmax(gm, ld_coh(&pxa[q].viol));
@@ -1004,7 +1004,7 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(const DevPlan P, const int
         for (int32_t k = tid; k < n; k += BLOCK) er[4 * k + 3] = 0.0;
         __syncthreads();
         if constexpr (SPLIT) {
-          if (!grid_barrier(bar, sp.n_parts, &next_slot)) { st_code = ILVES_ERR_TIMEOUT; break; }
+          if (!grid_barrier(bar, sp.n_parts, A.wait_limit, &next_slot)) { st_code = ILVES_ERR_TIMEOUT; break; }
         }
         continue;
       }
@@ -1040,7 +1040,7 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(const DevPlan P, const int
     for (int32_t k = tid; k < n; k += BLOCK) er[4 * k + 3] += static_cast<double>(y[k]);
     __syncthreads();
     if constexpr (SPLIT) {
-      if (!grid_barrier(bar, sp.n_parts, &next_slot)) { st_code = ILVES_ERR_TIMEOUT; break; }
+      if (!grid_barrier(bar, sp.n_parts, A.wait_limit, &next_slot)) { st_code = ILVES_ERR_TIMEOUT; break; }
     }
     ++it;
   }
@@ -1359,6 +1359,7 @@ struct ilves_plan {
   int32_t n_small = 0;
   int small_stream = 0;                // stream of the small-molecule kernel
   int split_stream[2] = {0, 0};        // stream of the split-molecule launches
+  int32_t wait_limit = 1 << 22;        // polls of a split barrier's wait
   float* d_mlp = nullptr;              // network parameters then normalisation block
   float* d_feat = nullptr;             // [n_constraints][16] features (plan row order)
   float* d_w = nullptr;                // [n_constraints] 1/m_a + 1/m_b
@@ -2162,6 +2163,13 @@ ilves_status_t ilves_plan_tune(ilves_plan_t P, const ilves_tuning_t* t) {
 
 int32_t ilves_plan_num_molecules(ilves_plan_t P) { return P ? static_cast<int32_t>(P->mols.size()) : -1; }
 
+ilves_status_t ilves_plan_set_wait_limit(ilves_plan_t P, int32_t polls) {
+  if (!P) return fail(ILVES_ERR_ARG, "plan must not be NULL");
+  if (polls < 0) return fail(ILVES_ERR_ARG, "polls must be >= 0");
+  P->wait_limit = polls;
+  return ILVES_OK;
+}
+
 ilves_status_t ilves_plan_stats(ilves_plan_t P, int64_t* stats) {
   if (!P || !stats) return fail(ILVES_ERR_ARG, "plan and stats must not be NULL");
   std::memcpy(stats, P->stats, sizeof(P->stats));
@@ -2231,6 +2239,7 @@ ilves_status_t solve_impl(ilves_plan_t P, const double* r, const double* r_u, co
                             : (precision == ILVES_PREC_FP64 && variant == ILVES_VARIANT_NEWTON ? 20 : 40);
   A.warm = warm;
   A.chord = variant == ILVES_VARIANT_CHORD ? 1 : 0;
+  A.wait_limit = P->wait_limit;
   if (P->n_free > 0) {
     const int tb = 256;
     hipLaunchKernelGGL(copy_free_atoms, dim3((P->n_free + tb - 1) / tb), dim3(tb), 0, stream, P->d_free, P->n_free,

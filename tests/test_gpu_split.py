@@ -181,3 +181,31 @@ def test_split_with_values_only_in_lds():
               f"values-only {st['split_values_lds']}", flush=True)
         assert st["split_molecules"] == 1 and st["split_values_lds"] == 1, st
         _check(sm, out, ref, f"h-angle protein values-only/{prec}")
+
+
+def test_split_wait_limit_reports_timeout_and_poisons_the_plan():
+    """Failure handling of the split barriers, forced from the host: with a
+    wait limit of zero polls a workgroup that has to wait gives up at once,
+    marks the molecule poisoned and every part leaves; the split molecule
+    reports ILVES_ERR_TIMEOUT (the whole molecules of the system still solve),
+    and so does every later solve of that plan, whatever the limit."""
+    import torch
+    print("== split wait limit", flush=True)
+    sm = S.concat([S.protein(60, seed=3), S.random_tree(200, seed=4)], spacing=2.0)
+    ru = S.perturb(sm.r, 0.002, 5)
+    plan = L.Plan(sm.n_atoms, sm.pairs, sm.d, split_rows=500, split_part_rows=50)
+    assert plan.stats()["split_molecules"] == 1
+    mol = plan.molecules()
+    split_idx = int(np.argmax(mol["n_con"]))
+    ds = DeviceSystem(sm).alloc_status(plan.n_molecules)
+    rud = ds.upload_ru(ru)
+    plan.set_wait_limit(0)
+    for rep in range(2):
+        plan.solve(ds.r, rud, ds.mass, TOL, ds.r_out, ds.lam, ds.iters, ds.status)
+        torch.cuda.synchronize()
+        st = ds.status.cpu().numpy()[:plan.n_molecules]
+        assert st[split_idx] == L.ERR_TIMEOUT, (rep, st)
+        assert np.all(np.delete(st, split_idx) == L.OK), (rep, st)
+        plan.set_wait_limit(1 << 22)
+    with pytest.raises(L.IlvesError):
+        plan.set_wait_limit(-1)
