@@ -1289,7 +1289,7 @@ KernelFn pick_kernel(bool fp32, int mode, bool wide, int block) {
 
 // parts of split molecules (16-bit indices): structure and values in LDS,
 // or the values only
-constexpr int kSplitBlock = 256;
+constexpr int kSplitBlock = 512;
 KernelFn pick_split(bool fp32, int mode) {
   if (mode == ALL_LDS)
     return fp32 ? solve_kernel<float, uint16_t, ALL_LDS, kSplitBlock, true>
