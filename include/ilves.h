@@ -245,6 +245,29 @@ ilves_status_t ilves_solve(ilves_plan_t plan, const double* r, const double* r_u
                            double tol, double* r_out, double* lambda, int32_t* iters, int32_t* status,
                            void* hip_stream);
 
+/*
+ * Velocity constraints (the velocity half of RATTLE): projects velocities v
+ * onto the tangent space of the constraints at positions r,
+ *   v_out = v - M^{-1} G(r)^T mu   with   G(r) v_out = 0,
+ * i.e. A(r, r) mu = G(r) v with A = G M^{-1} G^T -- the linearisation of the
+ * position constraints (Eq. defA at r' = r) with the velocity differences of
+ * each constraint's atoms in place of the unconstrained bond vectors.  It
+ * runs the chord iteration of the solve (one step is exact in FP64; the FP32
+ * factor of the mixed precision refines in a second step).
+ *   r, v, v_out  device double [3][n_atoms]; atoms in no constraint keep v.
+ *                v_out may alias neither r nor v.
+ *   mass         device double [n_atoms]
+ *   tol          bound on max |e_k . (v_a - v_b)| / (|e_k| |v_a - v_b|)
+ *   precision    ILVES_PREC_FP64 or ILVES_PREC_MIXED
+ *   mu           device double [n_constraints] multipliers (input order)
+ *   iters, status  as for ilves_solve
+ * Asynchronous on hip_stream, allocates nothing, graph-capturable; one solve
+ * or projection per plan in flight.  Errors as ilves_solve.
+ */
+ilves_status_t ilves_project_velocities(ilves_plan_t plan, const double* r, const double* v, const double* mass,
+                                        double tol, int32_t precision, double* v_out, double* mu, int32_t* iters,
+                                        int32_t* status, void* hip_stream);
+
 /* Same as ilves_solve with explicit precision / variant / warm start /
  * iteration cap, overriding the plan's options for this call. */
 ilves_status_t ilves_solve_ex(ilves_plan_t plan, const double* r, const double* r_u, const double* mass,

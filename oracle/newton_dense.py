@@ -178,3 +178,32 @@ def solve(pairs, d, mass, r, r_u, tol=1e-12, max_iter=20, lam0=None, variant="ne
         hists.append(h)
     return {"r_new": r_new, "lam": lam, "iters": iters, "status": status, "max_rel": viol,
             "molecules": mols, "history": hists}
+
+
+def project_velocities(pairs, mass, r, v):
+    """Velocity constraints (the velocity half of RATTLE; the derivative of
+    g(r) = 0 along the motion, G(r) v = 0, with the multiplier term of the
+    equations of motion, Supplement section 2): the velocity closest to v in
+    the kinetic metric among those tangent to the constraints,
+
+      v_out = v - M^{-1} G(r)^T mu,   G(r) M^{-1} G(r)^T mu = G(r) v,
+
+    solved per molecule with a dense LAPACK solve.  Atoms in no constraint
+    keep v.  Returns (v_out [s, 3], mu [n])."""
+    pairs = np.asarray(pairs, dtype=np.int64).reshape(-1, 2)
+    mass = np.asarray(mass, dtype=np.float64)
+    r = np.asarray(r, dtype=np.float64)
+    v = np.asarray(v, dtype=np.float64)
+    v_out = v.copy()
+    mu = np.zeros(pairs.shape[0])
+    for atoms, cons in molecules(r.shape[0], pairs):
+        local = np.full(r.shape[0], -1, np.int64)
+        local[atoms] = np.arange(atoms.size)
+        lp = local[pairs[cons]]
+        inv_m = 1.0 / mass[atoms]
+        G = jacobian(r[atoms], lp, atoms.size)
+        A = newton_matrix(r[atoms], r[atoms], lp, inv_m)
+        m_loc = np.linalg.solve(A, G @ v[atoms].ravel())
+        v_out[atoms] = v[atoms] - (np.repeat(inv_m, 3) * (G.T @ m_loc)).reshape(-1, 3)
+        mu[cons] = m_loc
+    return v_out, mu

@@ -81,6 +81,8 @@ def lib() -> ctypes.CDLL:
     L.ilves_plan_destroy.restype = ctypes.c_int
     L.ilves_plan_num_molecules.argtypes = [_P]
     L.ilves_plan_num_molecules.restype = ctypes.c_int32
+    L.ilves_project_velocities.argtypes = [_P, _P, _P, _P, ctypes.c_double, ctypes.c_int32, _P, _P, _P, _P, _P]
+    L.ilves_project_velocities.restype = ctypes.c_int
     L.ilves_plan_set_wait_limit.argtypes = [_P, ctypes.c_int32]
     L.ilves_plan_set_wait_limit.restype = ctypes.c_int
     L.ilves_plan_stats.argtypes = [_P, _I64P]
@@ -217,6 +219,27 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+    def project_velocities(self, r, v, mass, tol, v_out, mu, iters, status, precision=PREC_FP64, stream=None):
+        """Velocity constraints (RATTLE's velocity half): v_out = v - M^-1
+        G(r)^T mu with G(r) v_out = 0.  Device tensors as for solve (v, v_out
+        float64 [3, n_atoms], mu float64 [n_constraints])."""
+        import torch
+        for t, dt in ((r, torch.float64), (v, torch.float64), (mass, torch.float64), (v_out, torch.float64),
+                      (mu, torch.float64), (iters, torch.int32), (status, torch.int32)):
+            if not t.is_cuda or t.dtype != dt or not t.is_contiguous():
+                raise ValueError("project_velocities expects contiguous device tensors of the documented dtypes")
+        if r.shape != (3, self.n_atoms) or v.shape != (3, self.n_atoms) or v_out.shape != (3, self.n_atoms):
+            raise ValueError("positions and velocities must have shape [3, n_atoms]")
+        if mass.shape != (self.n_atoms,) or mu.shape != (self.n_constraints,):
+            raise ValueError("mass / mu have the wrong length")
+        if iters.numel() < self.n_molecules or status.numel() < self.n_molecules:
+            raise ValueError("iters / status need one entry per molecule")
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        check(self._L.ilves_project_velocities(self._h, r.data_ptr(), v.data_ptr(), mass.data_ptr(), float(tol),
+                                               precision, v_out.data_ptr(), mu.data_ptr(), iters.data_ptr(),
+                                               status.data_ptr(), ctypes.c_void_p(stream.cuda_stream)))
 
     def set_wait_limit(self, polls: int):
         """Bound on the polls of a split molecule's barrier wait (see

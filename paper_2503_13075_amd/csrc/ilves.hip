@@ -91,6 +91,7 @@ struct SolveArgs {
                      // 3: each constraint's decoupled solution (with fallback)
   int32_t chord;     // 0: Newton, 1: chord
   int32_t wait_limit;  // polls of a split molecule's barrier wait before it gives up
+  int32_t project;   // 1: velocity projection (r_u holds velocities, residual e_k . p_k, chord)
 };
 
 // FP64 workspace of a molecule: per row {e, lambda} (4n) and {u, C_kk} (4n),
@@ -934,8 +935,14 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(const DevPlan P, const int
         }
       }
       const double pp = px * px + py * py + pz * pz;
-      const double g = 0.5 * (pp - d2[k]);
-      double rel = (fabs(g) + sqrt(pp) * delta + delta2) / d2[k];
+      double g, rel;
+      if (A.project) {  // velocity constraint e_k . (v_a - v_b), relative to |e_k| |v_a - v_b|
+        g = px * ek.x + py * ek.y + pz * ek.z;
+        rel = fabs(g) / fmax(sqrt(pp * (ek.x * ek.x + ek.y * ek.y + ek.z * ek.z)), DBL_MIN);
+      } else {
+        g = 0.5 * (pp - d2[k]);
+        rel = (fabs(g) + sqrt(pp) * delta + delta2) / d2[k];
+      }
       if (!(rel <= DBL_MAX)) rel = INFINITY;  // NaN or Inf
       vmax = fmax(vmax, rel);
       y[k] = static_cast<T>(g);
@@ -1083,6 +1090,9 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(const DevPlan P, const int
 // molecule, the same constraint-space Newton iteration in FP64 registers,
 // the dense 3x3 system solved by elimination without pivoting.
 
+// PROJECT: velocity projection (residual e_k . p_k; compiled apart so that
+// the solve keeps its registers)
+template <bool PROJECT>
 __global__ void __launch_bounds__(256) small_kernel(const SmallMol* __restrict__ sm, int32_t count,
                                                    const SolveArgs A) {
   const int32_t t = blockIdx.x * 256 + threadIdx.x;
@@ -1151,8 +1161,14 @@ __global__ void __launch_bounds__(256) small_kernel(const SmallMol* __restrict__
         ep[k][c] = x;
       }
       const double pp = ep[k][0] * ep[k][0] + ep[k][1] * ep[k][1] + ep[k][2] * ep[k][2];
-      g[k] = 0.5 * (pp - M.d2[k]);
-      double rel = (fabs(g[k]) + sqrt(pp) * delta + delta2) / M.d2[k];
+      double rel;
+      if (PROJECT) {
+        g[k] = ep[k][0] * e[k][0] + ep[k][1] * e[k][1] + ep[k][2] * e[k][2];
+        rel = fabs(g[k]) / fmax(sqrt(pp * (e[k][0] * e[k][0] + e[k][1] * e[k][1] + e[k][2] * e[k][2])), DBL_MIN);
+      } else {
+        g[k] = 0.5 * (pp - M.d2[k]);
+        rel = (fabs(g[k]) + sqrt(pp) * delta + delta2) / M.d2[k];
+      }
       if (!(rel <= DBL_MAX)) rel = INFINITY;
       if (k < nc) gmax = fmax(gmax, rel);
     }
@@ -2222,7 +2238,8 @@ ilves_status_t run_features(ilves_plan_t P, const double* r, const double* r_u, 
 
 ilves_status_t solve_impl(ilves_plan_t P, const double* r, const double* r_u, const double* mass, double tol,
                           int32_t precision, int32_t variant, int32_t warm, int32_t max_iter, double* r_out,
-                          double* lambda, int32_t* iters, int32_t* status, int32_t* fallback, hipStream_t stream) {
+                          double* lambda, int32_t* iters, int32_t* status, int32_t* fallback, hipStream_t stream,
+                          int32_t project = 0) {
   SolveArgs A;
   A.r = r;
   A.r_u = r_u;
@@ -2240,6 +2257,7 @@ ilves_status_t solve_impl(ilves_plan_t P, const double* r, const double* r_u, co
   A.warm = warm;
   A.chord = variant == ILVES_VARIANT_CHORD ? 1 : 0;
   A.wait_limit = P->wait_limit;
+  A.project = project;
   if (P->n_free > 0) {
     const int tb = 256;
     hipLaunchKernelGGL(copy_free_atoms, dim3((P->n_free + tb - 1) / tb), dim3(tb), 0, stream, P->d_free, P->n_free,
@@ -2287,8 +2305,12 @@ ilves_status_t solve_impl(ilves_plan_t P, const double* r, const double* r_u, co
                             static_cast<size_t>(g.lds_bytes), s));
   }
   if (P->n_small > 0) {
-    hipLaunchKernelGGL(small_kernel, dim3((P->n_small + 255) / 256), dim3(256), 0, P->streams[P->small_stream],
-                       P->d_small, P->n_small, A);
+    if (A.project)
+      hipLaunchKernelGGL(small_kernel<true>, dim3((P->n_small + 255) / 256), dim3(256), 0,
+                         P->streams[P->small_stream], P->d_small, P->n_small, A);
+    else
+      hipLaunchKernelGGL(small_kernel<false>, dim3((P->n_small + 255) / 256), dim3(256), 0,
+                         P->streams[P->small_stream], P->d_small, P->n_small, A);
     HIP_TRY(hipGetLastError());
   }
   for (int i = 0; i < ns; ++i) {
@@ -2342,6 +2364,15 @@ ilves_status_t ilves_solve_learned(ilves_plan_t P, const double* r, const double
   if (st != ILVES_OK) return st;
   return solve_impl(P, r, r_u, mass, tol, precision, variant, 2, max_iter, r_out, lambda, iters, status, fallback,
                     stream);
+}
+
+ilves_status_t ilves_project_velocities(ilves_plan_t P, const double* r, const double* v, const double* mass,
+                                        double tol, int32_t precision, double* v_out, double* mu, int32_t* iters,
+                                        int32_t* status, void* hip_stream) {
+  ilves_status_t st = check_solve_args(P, r, v, mass, tol, precision, ILVES_VARIANT_CHORD, v_out, mu, iters, status);
+  if (st != ILVES_OK) return st;
+  return solve_impl(P, r, v, mass, tol, precision, ILVES_VARIANT_CHORD, 0, 0, v_out, mu, iters, status, nullptr,
+                    static_cast<hipStream_t>(hip_stream), 1);
 }
 
 ilves_status_t ilves_mlp_predict(ilves_plan_t P, const double* r, const double* r_u, const double* mass,

@@ -64,6 +64,21 @@ class ConstrainedLeapfrog:
         """Host copies (AoS) of positions and half-step velocities."""
         return self.r.cpu().numpy().T.copy(), self.v.cpu().numpy().T.copy()
 
+    def tangent_velocities(self, stream=None):
+        """The current half-step velocities projected onto the tangent space of
+        the constraints at the current positions (RATTLE's velocity
+        constraint, ilves_project_velocities); returns the device tensor
+        [3, n_atoms] and the per-molecule status."""
+        torch = self.torch
+        if not hasattr(self, "v_tan"):
+            self.v_tan = torch.empty_like(self.v)
+            self.mu = torch.zeros_like(self.lam)
+            self.p_iters = torch.zeros_like(self.iters)
+            self.p_status = torch.zeros_like(self.status)
+        self.plan.project_velocities(self.r, self.v, self.mass, 1e-12, self.v_tan, self.mu, self.p_iters,
+                                     self.p_status, precision=self.precision, stream=stream)
+        return self.v_tan, self.p_status
+
 
 def pendulum(length: float = 1.0, mass: float = 1.0, pivot_mass: float = 1e20, v0: float = 1.0):
     """The simple pendulum of the supplement's table: bob of mass 1 at the
