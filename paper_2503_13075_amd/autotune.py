@@ -18,7 +18,7 @@ import os
 from . import _lib as L
 
 BAND_CANDIDATES = [[64, 128, 256, 512, 1024]] * 3 + [[256, 512, 1024]] * 2
-LDS_CANDIDATES = [0, 96 * 1024, 64 * 1024, 32 * 1024]
+LDS_CANDIDATES = [0, 120 * 1024, 112 * 1024, 96 * 1024, 80 * 1024, 64 * 1024, 48 * 1024, 32 * 1024]
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "ilves_tuning.json")
 
 
