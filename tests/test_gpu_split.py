@@ -209,3 +209,38 @@ def test_split_wait_limit_reports_timeout_and_poisons_the_plan():
         plan.set_wait_limit(1 << 22)
     with pytest.raises(L.IlvesError):
         plan.set_wait_limit(-1)
+
+
+def test_giant_molecule_full_size_properties():
+    """One 26,389-constraint molecule (the size of the paper's largest single
+    molecule) at the bench's automatic split, where the oracle's dense LU is
+    out of reach: properties that hold at any size -- every constraint within
+    1e-12; the correction m_i (r'_i - r_u,i) sums to zero and has no moment
+    about the origin when taken at the old positions (the multiplier forces
+    are central pair forces along the old bond vectors); and the same result
+    as the molecule solved whole by one workgroup."""
+    print("== giant molecule full size", flush=True)
+    sm = S.protein_system(seed=1, n_res=1650)
+    ru = S.perturb(sm.r, 0.002, 3)
+    for prec in (L.PREC_FP64, L.PREC_MIXED):
+        out = solve_once(sm, ru, TOL, prec, L.VARIANT_NEWTON)
+        st = out["plan"].stats()
+        assert st["split_molecules"] == 1 and st["split_parts"] >= 8, st
+        assert np.all(out["status"] == L.OK)
+        viol = np.max(O.relative_violation(out["r_out"], sm.pairs, sm.d))
+        corr = sm.mass[:, None] * (out["r_out"] - ru)
+        scale = np.abs(corr).sum()
+        dp = np.abs(corr.sum(0)).max() / scale
+        # moment of the multiplier forces about the origin, taken at the old positions
+        lam = out["lam"]
+        e = sm.r[sm.pairs[:, 0]] - sm.r[sm.pairs[:, 1]]
+        f = np.zeros_like(sm.r)
+        np.add.at(f, sm.pairs[:, 0], -lam[:, None] * e)
+        np.add.at(f, sm.pairs[:, 1], lam[:, None] * e)
+        assert np.max(np.abs(f - corr)) <= 1e-12 * np.abs(corr).max()
+        dl = np.abs(np.cross(sm.r, f).sum(0)).max() / (np.abs(np.cross(sm.r, f)).sum())
+        whole = solve_once(sm, ru, TOL, prec, L.VARIANT_NEWTON, split_rows=-1)
+        dw = np.max(np.abs(out["r_out"] - whole["r_out"]))
+        print(f"   prec {prec}: parts {st['split_parts']}, violation {viol:.2e}, momentum {dp:.1e}, "
+              f"moment {dl:.1e}, |split - whole| {dw:.1e} nm, iters {out['iters']} / {whole['iters']}", flush=True)
+        assert viol <= TOL and dp <= 1e-12 and dl <= 1e-12 and dw <= 1e-10
