@@ -430,10 +430,27 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(const DevPlan P, const int
   // (the loops read input atom indices prepared with the plan, so each
   // entry takes one round of gathers)
   double rmax = 0.0;
-  for (int32_t a = tid; a < s; a += BLOCK) {
-    const int32_t g = atom_gid[a];
-    invm[a] = 1.0 / A.mass[g];
-    rmax = fmax(rmax, fmax(fabs(ux[g]), fmax(fabs(ux[S + g]), fabs(ux[2 * S + g]))));
+  // atoms four per lane at a time (index, then mass and position gathers
+  // in flight together)
+  for (int32_t a0 = tid; a0 < s; a0 += 4 * BLOCK) {
+    int32_t g[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) g[i] = atom_gid[imin(a0 + i * BLOCK, s - 1)];
+    double m[4], x[4], yv[4], z[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      m[i] = A.mass[g[i]];
+      x[i] = ux[g[i]];
+      yv[i] = ux[S + g[i]];
+      z[i] = ux[2 * S + g[i]];
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      if (a0 + i * BLOCK < s) {
+        invm[a0 + i * BLOCK] = 1.0 / m[i];
+        rmax = fmax(rmax, fmax(fabs(x[i]), fmax(fabs(yv[i]), fabs(z[i]))));
+      }
+    }
   }
   if (tid == 0) {
     invm[s] = 0.0;  // fill entries point here: zero coupling
@@ -464,11 +481,24 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(const DevPlan P, const int
     st_rec(uc + 4 * k, a0, a1, a2, cdk);
     v0 = fmax(v0, fabs(a0 * a0 + a1 * a1 + a2 * a2 - d2[k]) / (2.0 * d2[k]));
   }
+  // slot couplings, four slots per lane at a time so that their two rounds
+  // of gathers (coupling code, then the shared atom's mass) overlap
   const int32_t* __restrict__ gcoef = P.gcoef + md.coef_off;
-  for (int32_t q = tid; q < n_up + n_l; q += BLOCK) {
-    const int32_t c = gcoef[q];
-    const double v = c < 0 ? 0.0 : 1.0 / A.mass[c >> 1];
-    cf[q] = (c & 1) ? -v : v;
+  const int32_t n_slots = n_up + n_l;
+  for (int32_t q0 = tid; q0 < n_slots; q0 += 4 * BLOCK) {
+    int32_t c[4];
+    double m[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) c[i] = gcoef[imin(q0 + i * BLOCK, n_slots - 1)];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) m[i] = A.mass[c[i] < 0 ? 0 : c[i] >> 1];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      if (q0 + i * BLOCK < n_slots) {
+        const double v = c[i] < 0 ? 0.0 : 1.0 / m[i];
+        cf[q0 + i * BLOCK] = (c[i] & 1) ? -v : v;
+      }
+    }
   }
   int32_t adj0 = 0;  // first separator coupling of the molecule
   if constexpr (SPLIT) {
