@@ -1090,20 +1090,31 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(const DevPlan P, const int
   const int32_t* __restrict__ inc = P.inc + md.inc_off;
   const int32_t s_out = SPLIT ? sp.s_own : s;
   for (int32_t a = tid; a < s_out; a += BLOCK) {
-    double dx = 0.0, dy = 0.0, dz = 0.0;
-    for (int32_t q = inc_ptr[a]; q < inc_ptr[a + 1]; ++q) {
-      const int32_t e = inc[q];
-      const Rec ek = ld_rec(er + 4 * (e >> 1));
-      const double l = (e & 1) ? -ek.l : ek.l;
-      dx += l * ek.x;
-      dy += l * ek.y;
-      dz += l * ek.z;
-    }
+    // the atom's own data first, then its constraints two at a time, so
+    // that each round of loads is issued together
     const int32_t g = atom_gid[a];
     const double im = invm[a];
-    A.r_out[g] = ux[g] - im * dx;
-    A.r_out[S + g] = ux[S + g] - im * dy;
-    A.r_out[2 * S + g] = ux[2 * S + g] - im * dz;
+    const double u0 = ux[g], u1 = ux[S + g], u2 = ux[2 * S + g];
+    const int32_t q0 = inc_ptr[a], q1 = inc_ptr[a + 1];
+    double dx = 0.0, dy = 0.0, dz = 0.0;
+    for (int32_t q = q0; q < q1; q += 2) {
+      const int32_t e0 = inc[q], e1 = inc[imin(q + 1, q1 - 1)];
+      const Rec r0 = ld_rec(er + 4 * (e0 >> 1));
+      const Rec r1 = ld_rec(er + 4 * (e1 >> 1));
+      const double l0 = (e0 & 1) ? -r0.l : r0.l;
+      dx += l0 * r0.x;
+      dy += l0 * r0.y;
+      dz += l0 * r0.z;
+      if (q + 1 < q1) {
+        const double l1 = (e1 & 1) ? -r1.l : r1.l;
+        dx += l1 * r1.x;
+        dy += l1 * r1.y;
+        dz += l1 * r1.z;
+      }
+    }
+    A.r_out[g] = u0 - im * dx;
+    A.r_out[S + g] = u1 - im * dy;
+    A.r_out[2 * S + g] = u2 - im * dz;
   }
   if (tid == 0 && (!SPLIT || sp.part == 0)) {
     A.iters[report] = it;
