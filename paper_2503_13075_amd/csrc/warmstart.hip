@@ -11,7 +11,7 @@
 //   lambda_0 = (t0 + scale * MLP((f - mean) / std)) / w,  w = 1/m_a + 1/m_b.
 //
 // Inference runs in BF16 on the matrix cores (v_mfma_f32_16x16x16_bf16,
-// FP32 accumulation).  Every layer is computed transposed (hidden x rows),
+// FP32 accumulation, the tanh form of GELU).  Every layer is computed transposed (hidden x rows),
 // so the accumulator tile of one layer is already the B operand of the
 // next: no LDS round trip between layers.  Training kernels are FP32
 // VALU: a 64-sample workgroup computes forward and backward passes with
@@ -32,27 +32,25 @@ __device__ inline float gelu_grad(float x) {
   return 0.5f * (1.0f + erff(x * 0.70710678118654752f)) + x * expf(-0.5f * x * x) * 0.39894228040143268f;
 }
 
-// GELU for BF16 inference: x Phi(x) with erf from Abramowitz & Stegun
-// 7.1.26 (absolute error below 1.5e-7, far under the BF16 rounding of the
-// activations that follows); training keeps the library erf.
+// GELU for BF16 inference: the tanh form of Hendrycks and Gimpel,
+// 0.5 x (1 + tanh(sqrt(2/pi) (x + 0.044715 x^3))) = x / (1 + exp(-2 sqrt(2/pi) (x + 0.044715 x^3))),
+// one exp2 and one reciprocal.  Its absolute distance from the exact
+// x Phi(x) is below 4.8e-4 (largest near |x| = 2.7), under the BF16
+// rounding of the activations that follows (half an ulp is 7.8e-3 there);
+// training keeps the library erf.  Saturates to 0 and x for large |x|.
 __device__ inline float gelu_fast(float x) {
-  const float z = fabsf(x) * 0.70710678118654752f;
-  const float t = __builtin_amdgcn_rcpf(1.0f + 0.3275911f * z);
-  const float poly = t * (0.254829592f + t * (-0.284496736f + t * (1.421413741f + t * (-1.453152027f + t * 1.061405429f))));
-  const float erf_abs = 1.0f - poly * __expf(-z * z);
-  const float e = x < 0.0f ? -erf_abs : erf_abs;
-  return 0.5f * x * (1.0f + e);
-}
-
-// float -> bfloat16 bits, round to nearest even
-__device__ inline short to_bf16(float f) {
-  unsigned int u = __float_as_uint(f);
-  u += 0x7FFFu + ((u >> 16) & 1u);
-  return static_cast<short>(u >> 16);
+  constexpr float c = -2.0f * 0.79788456080286536f * 1.4426950408889634f;  // -2 sqrt(2/pi) log2(e)
+  const float y = x * __builtin_fmaf(0.044715f * c, x * x, c);
+  return x * __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(y));
 }
 
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bfv4 __attribute__((ext_vector_type(4)));
+
+// four floats -> bfloat16, round to nearest even (two packed hardware
+// conversions on gfx950)
+__device__ inline bf16x4 to_bf16x4(f32x4 v) { return __builtin_bit_cast(bf16x4, __builtin_convertvector(v, bfv4)); }
 
 // ---------------------------------------------------------------------------
 // features: two passes over all rows, one thread per row.  A workgroup takes
@@ -87,12 +85,12 @@ __global__ void __launch_bounds__(kChunk) features_own_kernel(const DevPlan P, c
   const MolDesc& md = c.md;
   const int32_t k = c.k, n = md.n;
   if (k >= n) return;
-  const int32_t* atom_gid = P.atom_gid + md.atom_off;
   const int32_t* inc_ptr = P.inc_ptr + md.incp_off;
   const int64_t R0 = md.row_off;
-  double* ex = reinterpret_cast<double*>(ws + md.ws_off);
+  double4* er = reinterpret_cast<double4*>(ws + md.ws_off);
+  // input atoms (plan-time copies) and local atoms (for the valences) are independent loads
+  const int32_t ga = P.ga[R0 + k], gb = P.gb[R0 + k];
   const int32_t la = P.ra[R0 + k], lb = P.rb[R0 + k];
-  const int32_t ga = atom_gid[la], gb = atom_gid[lb];
   const double d2 = P.d2[R0 + k];
   const double e0 = r[ga] - r[gb], e1 = r[S + ga] - r[S + gb], e2 = r[2 * S + ga] - r[2 * S + gb];
   const double u0 = ru[ga] - ru[gb], u1 = ru[S + ga] - ru[S + gb], u2 = ru[2 * S + ga] - ru[2 * S + gb];
@@ -110,20 +108,18 @@ __global__ void __launch_bounds__(kChunk) features_own_kernel(const DevPlan P, c
   f[1] = make_float4(static_cast<float>(fabs(ia - ib) / w), static_cast<float>((dega + degb - 2) * 0.25),
                      static_cast<float>(abs(dega - degb) * 0.25), 0.0f);
   wout[R0 + k] = static_cast<float>(w);
-  ex[k] = e0;
-  ex[n + k] = e1;
-  ex[2 * n + k] = e2;
+  // the row's old bond vector and w, one 32-byte record for the second pass
+  er[k] = make_double4(e0, e1, e2, w);
 }
 
 template <typename Idx>
 __global__ void __launch_bounds__(kChunk) features_sum_kernel(const DevPlan P, const int2* __restrict__ chunks,
                                                             const double* __restrict__ mass, int32_t S,
                                                             const unsigned char* __restrict__ ws,
-                                                            float* __restrict__ feat,
-                                                            const float* __restrict__ wout) {
+                                                            float* __restrict__ feat) {
   const RowCtx c = row_ctx<Idx>(P, chunks);
   const MolDesc& md = c.md;
-  const int32_t k = c.k, n = md.n, s = md.s;
+  const int32_t k = c.k, n = md.n;
   if (k >= n) return;
   (void)S;
   const Layout Lo = struct_layout(n, md.n_levels, md.n_up, md.n_l, md.n_pl, md.n_upd, static_cast<int>(sizeof(Idx)));
@@ -133,26 +129,24 @@ __global__ void __launch_bounds__(kChunk) features_sum_kernel(const DevPlan P, c
   const Idx* ucol = reinterpret_cast<const Idx*>(st + Lo.ucol);
   // lower-slot records {column, transpose}, indexed by F index t
   const Idx* lpair = reinterpret_cast<const Idx*>(st + Lo.lpair) - 2 * static_cast<int64_t>(md.n_up);
-  const int32_t* coef = P.coef + md.coef_off;
-  const int32_t* atom_gid = P.atom_gid + md.atom_off;
+  // per slot: (input index of the shared atom << 1) | (sign < 0), -1 for fill
+  const int32_t* gcoef = P.gcoef + md.coef_off;
   const int64_t R0 = md.row_off;
-  const double* ex = reinterpret_cast<const double*>(ws + md.ws_off);
-  const double* ey = ex + n;
-  const double* ez = ey + n;
-  const double e0 = ex[k], e1 = ey[k], e2 = ez[k];
+  const double4* er = reinterpret_cast<const double4*>(ws + md.ws_off);
+  const double4 ek = er[k];
+  const double e0 = ek.x, e1 = ek.y, e2 = ek.z, wk = ek.w;
   const double ee = e0 * e0 + e1 * e1 + e2 * e2;
-  const double wk = static_cast<double>(wout[R0 + k]);
   double s7 = 0, s8 = 0, s9 = 0, s10 = 0, s11 = 0, s12 = 0, s14 = 0, s15 = 0, cnt = 0;
   auto visit = [&](int32_t t, int32_t j) {
-    const int32_t cf = coef[t];
-    const int32_t x = cf >> 1;
-    if (x >= s) return;  // fill entry
+    const int32_t cf = gcoef[t];
+    if (cf < 0) return;  // fill entry
     const double sg = (cf & 1) ? -1.0 : 1.0;
-    const double fx = ex[j], fy = ey[j], fz = ez[j];
-    const double dot = e0 * fx + e1 * fy + e2 * fz;
-    const double rho = sg * dot / (mass[atom_gid[x]] * wk * ee);
-    const double q = wk / static_cast<double>(wout[R0 + j]);
+    const double4 ej = er[j];
     const float4 fj = *reinterpret_cast<const float4*>(feat + (R0 + j) * N_FEAT);
+    const double fx = ej.x, fy = ej.y, fz = ej.z;
+    const double dot = e0 * fx + e1 * fy + e2 * fz;
+    const double rho = sg * dot / (mass[cf >> 1] * wk * ee);
+    const double q = wk / ej.w;
     s7 += rho * q * fj.x;
     s8 += fabs(rho);
     s9 = fmax(s9, fabs(rho));
@@ -207,39 +201,52 @@ __global__ void __launch_bounds__(256) mlp_infer_kernel(const float* __restrict_
   float bias1[4][4], bias2[4][4], w3[4][4];
 #pragma unroll
   for (int hb = 0; hb < 4; ++hb) {
+    f32x4 a;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      A1[hb][i] = to_bf16(W1[(4 * kq + i) * N_HID + 16 * hb + col]);
+      a[i] = W1[(4 * kq + i) * N_HID + 16 * hb + col];
       bias1[hb][i] = b1[16 * hb + 4 * kq + i];
       bias2[hb][i] = b2[16 * hb + 4 * kq + i];
       w3[hb][i] = W3[16 * hb + 4 * kq + i];
     }
+    A1[hb] = to_bf16x4(a);
   }
 #pragma unroll
   for (int ob = 0; ob < 4; ++ob)
 #pragma unroll
-    for (int kb = 0; kb < 4; ++kb)
+    for (int kb = 0; kb < 4; ++kb) {
+      f32x4 a;
 #pragma unroll
-      for (int i = 0; i < 4; ++i) A2[ob][kb][i] = to_bf16(W2[(16 * kb + 4 * kq + i) * N_HID + 16 * ob + col]);
+      for (int i = 0; i < 4; ++i) a[i] = W2[(16 * kb + 4 * kq + i) * N_HID + 16 * ob + col];
+      A2[ob][kb] = to_bf16x4(a);
+    }
+  // this lane's four features are normalised as (f - mean) * (1 / std)
+  f32x4 fmean, finv;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    fmean[i] = mean[4 * kq + i];
+    finv[i] = 1.0f / sdev[4 * kq + i];
+  }
 
   const int n_tiles = (n_rows + 15) / 16;
   for (int tile = blockIdx.x * 4 + wave; tile < n_tiles; tile += gridDim.x * 4) {
     const int row = tile * 16 + col;
     const bool valid = row < n_rows;
-    bf16x4 xb;
+    f32x4 x = {0.0f, 0.0f, 0.0f, 0.0f};
+    if (valid) {
+      x = *reinterpret_cast<const f32x4*>(feat + static_cast<int64_t>(row) * N_FEAT + 4 * kq);
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int f = 4 * kq + i;
-      const float v = valid ? (feat[static_cast<int64_t>(row) * N_FEAT + f] - mean[f]) / sdev[f] : 0.0f;
-      xb[i] = to_bf16(v);
+      for (int i = 0; i < 4; ++i) x[i] = (x[i] - fmean[i]) * finv[i];
     }
+    const bf16x4 xb = to_bf16x4(x);
     bf16x4 h1[4];
 #pragma unroll
     for (int hb = 0; hb < 4; ++hb) {
       f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
       acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A1[hb], xb, acc, 0, 0, 0);
 #pragma unroll
-      for (int i = 0; i < 4; ++i) h1[hb][i] = to_bf16(gelu_fast(acc[i] + bias1[hb][i]));
+      for (int i = 0; i < 4; ++i) acc[i] = gelu_fast(acc[i] + bias1[hb][i]);
+      h1[hb] = to_bf16x4(acc);
     }
     float part = 0.0f;
 #pragma unroll
@@ -390,12 +397,12 @@ hipError_t launch_features(const DevPlan& P, const int2* chunks, int32_t n_chunk
     hipLaunchKernelGGL(features_own_kernel<int32_t>, dim3(n_chunks), dim3(kChunk), 0, stream, P, chunks, r, r_u,
                        mass, n_atoms, ws, feat, w);
     hipLaunchKernelGGL(features_sum_kernel<int32_t>, dim3(n_chunks), dim3(kChunk), 0, stream, P, chunks, mass,
-                       n_atoms, ws, feat, w);
+                       n_atoms, ws, feat);
   } else {
     hipLaunchKernelGGL(features_own_kernel<uint16_t>, dim3(n_chunks), dim3(kChunk), 0, stream, P, chunks, r, r_u,
                        mass, n_atoms, ws, feat, w);
     hipLaunchKernelGGL(features_sum_kernel<uint16_t>, dim3(n_chunks), dim3(kChunk), 0, stream, P, chunks, mass,
-                       n_atoms, ws, feat, w);
+                       n_atoms, ws, feat);
   }
   return hipGetLastError();
 }
