@@ -137,28 +137,48 @@ __global__ void __launch_bounds__(kChunk) features_sum_kernel(const DevPlan P, c
   const double e0 = ek.x, e1 = ek.y, e2 = ek.z, wk = ek.w;
   const double ee = e0 * e0 + e1 * e1 + e2 * e2;
   double s7 = 0, s8 = 0, s9 = 0, s10 = 0, s11 = 0, s12 = 0, s14 = 0, s15 = 0, cnt = 0;
-  auto visit = [&](int32_t t, int32_t j) {
-    const int32_t cf = gcoef[t];
-    if (cf < 0) return;  // fill entry
-    const double sg = (cf & 1) ? -1.0 : 1.0;
-    const double4 ej = er[j];
-    const float4 fj = *reinterpret_cast<const float4*>(feat + (R0 + j) * N_FEAT);
-    const double fx = ej.x, fy = ej.y, fz = ej.z;
-    const double dot = e0 * fx + e1 * fy + e2 * fz;
-    const double rho = sg * dot / (mass[cf >> 1] * wk * ee);
-    const double q = wk / ej.w;
-    s7 += rho * q * fj.x;
-    s8 += fabs(rho);
-    s9 = fmax(s9, fabs(rho));
-    s10 += rho * q * fj.y;
-    s11 += rho * rho;
-    s12 += sg * dot / sqrt(ee * (fx * fx + fy * fy + fz * fz));
-    s14 += rho * q * fj.z;
-    s15 += rho * q * fj.w;
-    cnt += 1.0;
-  };
-  for (int32_t q = up_start[k]; q < up_start[k + 1]; ++q) visit(q, ucol[q]);
-  for (int32_t t = l_start[k]; t < l_start[k + 1]; ++t) visit(t, lpair[2 * t]);
+  // the row's neighbours: its upper slots, then its lower slots, four at a
+  // time with all their loads issued before the sums (same summation order)
+  const int32_t q0 = up_start[k], nu = up_start[k + 1] - q0;
+  const int32_t t0 = l_start[k], tot = nu + (l_start[k + 1] - t0);
+  for (int32_t b = 0; b < tot; b += 4) {
+    int32_t cf[4], jj[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int32_t idx = b + i;
+      const int32_t slot = idx < nu ? q0 + idx : t0 + (idx - nu);
+      const bool ok = idx < tot;
+      jj[i] = !ok ? k : (idx < nu ? static_cast<int32_t>(ucol[slot]) : static_cast<int32_t>(lpair[2 * slot]));
+      cf[i] = ok ? gcoef[slot] : -1;
+    }
+    double4 ej[4];
+    float4 fj[4];
+    double mj[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      ej[i] = er[jj[i]];
+      fj[i] = *reinterpret_cast<const float4*>(feat + (R0 + jj[i]) * N_FEAT);
+      mj[i] = mass[cf[i] < 0 ? 0 : cf[i] >> 1];
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      if (cf[i] < 0) continue;  // fill entry or past the row's last slot
+      const double sg = (cf[i] & 1) ? -1.0 : 1.0;
+      const double fx = ej[i].x, fy = ej[i].y, fz = ej[i].z;
+      const double dot = e0 * fx + e1 * fy + e2 * fz;
+      const double rho = sg * dot / (mj[i] * wk * ee);
+      const double q = wk / ej[i].w;
+      s7 += rho * q * fj[i].x;
+      s8 += fabs(rho);
+      s9 = fmax(s9, fabs(rho));
+      s10 += rho * q * fj[i].y;
+      s11 += rho * rho;
+      s12 += sg * dot / sqrt(ee * (fx * fx + fy * fy + fz * fz));
+      s14 += rho * q * fj[i].z;
+      s15 += rho * q * fj[i].w;
+      cnt += 1.0;
+    }
+  }
   float* f = feat + (R0 + k) * N_FEAT;
   f[7] = static_cast<float>(s7);
   reinterpret_cast<float4*>(f)[2] = make_float4(static_cast<float>(s8), static_cast<float>(s9),
