@@ -235,6 +235,8 @@ ilves_status_t ilves_plan_tune(ilves_plan_t plan, const ilves_tuning_t* t);
  *   iters      device int32 [num_molecules] linear solves per molecule
  *   status     device int32 [num_molecules] ILVES_OK, ILVES_ERR_SINGULAR,
  *              ILVES_ERR_NOT_CONVERGED or ILVES_ERR_NONFINITE per molecule
+ *              (ILVES_ERR_TIMEOUT for a split molecule whose barrier wait
+ *              hit the plan's wait limit)
  *   hip_stream hipStream_t (NULL = the null stream)
  * The call allocates nothing, never synchronises the host and may be
  * captured in a HIP graph.  One solve per plan may be in flight at a time.
@@ -282,8 +284,9 @@ ilves_status_t ilves_solve_ex(ilves_plan_t plan, const double* r, const double* 
  * ilves_features).  With w_k = 1/m_a + 1/m_b and t0_k the decoupled
  * (diatomic) solution of constraint k,
  *   lambda_0,k = (t0_k + scale * MLP((f_k - mean) / std)) / w_k,
- * MLP = [16 -> 64 -> 64 -> 1] with exact GELU, evaluated in BF16 on the
- * matrix cores with FP32 accumulation.  Parameters are a flat float array
+ * MLP = [16 -> 64 -> 64 -> 1], trained with the exact GELU x Phi(x) and
+ * evaluated in BF16 on the matrix cores with FP32 accumulation and the tanh
+ * form of GELU (within 4.8e-4 of the exact one).  Parameters are a flat float array
  * of ilves_mlp_param_count() values: W1 [16][64] row-major (input x hidden),
  * b1 [64], W2 [64][64], b2 [64], W3 [64], b3 [1]; the normalisation block
  * has ilves_mlp_norm_count() values: mean [16], std [16] (> 0), scale.
