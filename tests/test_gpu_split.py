@@ -2,7 +2,8 @@
 Schur complement on the separator rows, one workgroup per part, device-wide
 barriers between the phases of a Newton iteration): parity with the oracle
 and with the host replay of the same schedule, for FP64 / mixed precision,
-Newton / chord, caller's warm start; repeated solves on one plan (the
+Newton / chord, caller's warm start, the learned start (and its features,
+computed over the whole molecule); repeated solves on one plan (the
 barrier state carries over), graph replay, status reporting, and a system
 that mixes split, whole and small molecules with free atoms."""
 import numpy as np
@@ -76,6 +77,40 @@ def test_split_matches_oracle_and_replay(cases, case, name, prec, variant):
     assert np.max(np.abs(out["r_out"] - rep["r_out"].T)) <= POS_TOL
     if variant == L.VARIANT_NEWTON:
         assert abs(int(out["iters"][0]) - int(rep["iters"][0])) <= 1
+
+
+def test_split_learned_start_and_features(cases):
+    """The learned start on a split molecule: the feature passes run over the
+    whole molecule (a border row's neighbours in other parts included), so
+    its features equal the oracle's; the warm-started split solve matches
+    the oracle in both precisions."""
+    import torch
+    from oracle import mlp as M
+    from paper_2503_13075_amd import warmstart as WS
+    sm, ru, rows, part, ref = cases["protein"]
+    print("== split learned start", flush=True)
+    plan = L.Plan(sm.n_atoms, sm.pairs, sm.d, split_rows=rows, split_part_rows=part)
+    assert plan.stats()["split_molecules"] == 1
+    params, norm, _ = WS.load(WS.WEIGHTS["trees"])
+    plan.load_mlp(params, norm)
+    ds = DeviceSystem(sm).alloc_status(plan.n_molecules)
+    rud = ds.upload_ru(ru)
+    feat = torch.empty((sm.n_constraints, 16), dtype=torch.float32, device="cuda")
+    w = torch.empty(sm.n_constraints, dtype=torch.float32, device="cuda")
+    plan.features(ds.r, rud, ds.mass, feat, w)
+    torch.cuda.synchronize()
+    fref, wref = M.features(sm.pairs, sm.d, sm.mass, sm.r, ru)
+    exp = fref[plan.row_constraints()]
+    err = np.abs(feat.cpu().numpy() - exp) / np.maximum(np.abs(exp).max(0), 1e-6)
+    print(f"   max feature error / column scale {err.max():.1e}", flush=True)
+    assert err.max() < 1e-5
+    fb = torch.zeros(plan.n_molecules, dtype=torch.int32, device="cuda")
+    for prec in (L.PREC_FP64, L.PREC_MIXED):
+        plan.solve_learned(ds.r, rud, ds.mass, TOL, ds.r_out, ds.lam, ds.iters, ds.status, fb, precision=prec)
+        torch.cuda.synchronize()
+        out = {"r_out": ds.r_out.cpu().numpy().T, "lam": ds.lam.cpu().numpy(),
+               "iters": ds.iters.cpu().numpy()[:plan.n_molecules], "status": ds.status.cpu().numpy()[:plan.n_molecules]}
+        _check(sm, out, ref, f"protein/learned/{prec} (fallback {int(fb[0].item())})")
 
 
 def test_split_warm_start_and_repeated_solves(cases):
