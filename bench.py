@@ -68,6 +68,28 @@ def algorithmic_bytes(sm, plan_stats):
     return 80 * s + 24 * n + 4 * nnz_l + 8 * n
 
 
+def copy_bandwidth_gbs(dev, mib=1024, reps=10):
+    """Bandwidth of a plain device-to-device copy (bytes read + written per
+    second), the practical HBM ceiling to set beside the published peak."""
+    import torch
+    src = torch.empty(mib * (1 << 20) // 8, dtype=torch.float64, device=dev).uniform_()
+    dst = torch.empty_like(src)
+    for _ in range(2):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    ev1.record()
+    torch.cuda.synchronize()
+    gbs = 2.0 * src.numel() * 8 * reps / (ev0.elapsed_time(ev1) / 1e3) / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+    return gbs
+
+
 def measured_traffic(workload, variant, tuning):
     """HBM bytes per solve from the committed rocprofv3 FETCH_SIZE /
     WRITE_SIZE runs, if they were taken from the current kernel sources with
@@ -406,6 +428,12 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "algorithmic_bytes_per_step": abytes, "kernel": "solve_kernel (all launch groups of one solve)"},
     }
+    copy_gbs = copy_bandwidth_gbs(dev)
+    out["roofline"]["copy_gbs"] = copy_gbs                      # measured 1 GiB device copy
+    out["roofline"]["frac_of_copy"] = achieved / copy_gbs
+    if traffic is not None:
+        out["roofline"]["traffic_gbs"] = traffic / (head["ms_per_step"] / 1e3) / 1e9
+    log(f"roofline: {achieved:.0f} GB/s algorithmic, copy {copy_gbs:.0f} GB/s, peak {HBM_PEAK_GBS:.0f} GB/s")
     if args.rng_steps > 0:
         head_warm = L.WARM_DECOUPLED if head_name == "decoupled" else L.WARM_ZERO
         tune(L.PREC_MIXED, head_warm)  # the head variant's launch tuning
