@@ -156,6 +156,8 @@ def main():
     ap.add_argument("--variants", default="fp64,mixed,decoupled,learned",
                     help="comma list of fp64, mixed, decoupled (mixed, each constraint's decoupled solution as "
                          "lambda_0), learned (mixed, network lambda_0)")
+    ap.add_argument("--ordering", type=int, default=0,
+                    help="fill-reducing ordering: 0 automatic, 1 minimum deficiency, 2 nested dissection")
     ap.add_argument("--eager", action="store_true", help="launch every step instead of replaying HIP graphs")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch tuning")
     ap.add_argument("--tuning", default=None,
@@ -186,7 +188,8 @@ def main():
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
     t1 = time.perf_counter()
-    plan = L.Plan(sm.n_atoms, sm.pairs, sm.d, split_rows=args.split_rows, split_part_rows=args.split_part_rows)
+    plan = L.Plan(sm.n_atoms, sm.pairs, sm.d, split_rows=args.split_rows, split_part_rows=args.split_part_rows,
+                  ordering=args.ordering)
     st = plan.stats()
     log(f"plan: {time.perf_counter() - t1:.1f} s, {st}")
     r = torch.from_numpy(S.soa(sm.r)).to(dev)
