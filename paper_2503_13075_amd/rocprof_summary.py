@@ -3,6 +3,7 @@
     python -m paper_2503_13075_amd.rocprof_summary trace <dir>
     python -m paper_2503_13075_amd.rocprof_summary traffic <fetch dir> <write dir> <solves> <copy MiB> \
         <algorithmic bytes per solve> [json out] [launch tuning as JSON] [bench variant]
+    python -m paper_2503_13075_amd.rocprof_summary valu <solves> <ms per solve> <dir> [<dir> ...]
 
 ``trace`` prints the kernel statistics of a ``--kernel-trace --stats`` run as
 a markdown table.  ``traffic`` turns two ``--pmc FETCH_SIZE`` / ``--pmc
@@ -10,7 +11,11 @@ WRITE_SIZE`` runs of ``bench.py --calibrate-copy MiB`` into HBM bytes per
 solve: the counters of every dispatch of the solve kernels are summed and
 divided by the number of solves, and each counter is scaled by what it reads
 for the plain device copy of known size that bench.py runs first (the
-largest ``__amd_rocclr_copyBuffer`` dispatch).
+largest ``__amd_rocclr_copyBuffer`` dispatch).  ``valu`` sums the SQ / GRBM
+counters of the solve kernels' dispatches in one or more ``--pmc`` runs per
+solve and derives the FP64 / FP32 VALU flop rates (at the solve's duration,
+against MI355X's vector peaks) and the fraction of SIMD cycles issuing VALU
+work.
 """
 from __future__ import annotations
 
@@ -102,6 +107,48 @@ def traffic(fetch_dir: str, write_dir: str, solves: int, copy_mib: int, algorith
             "traffic_over_algorithmic": (fetch + write) / algorithmic}
 
 
+N_SIMD = 4 * 256                       # MI355X: 256 CUs of 4 SIMDs
+PEAK_F64_VEC_TFLOPS = 78.6             # published vector FP64 peak
+PEAK_F32_VEC_TFLOPS = 157.3            # published vector FP32 peak (packed)
+CLOCK_HZ = 2.4e9                       # MI355X peak engine clock
+
+
+def valu(dirs, solves: int, ms_per_solve: float) -> dict:
+    """Per-solve counter sums of the solve kernels and derived rates.  Flops
+    count every lane of a wave64 instruction (64 per add / mul /
+    transcendental, 128 per fma), an upper bound when lanes are masked.  The
+    rates use ``ms_per_solve``, the solve's duration measured outside the
+    profiler (counter collection serialises the dispatches).  The VALU issue
+    fraction is the share of the SIMDs' cycles over that duration that the
+    solve's VALU instructions would occupy at 4 cycles each (a wave64
+    instruction on a 16-lane SIMD): SQ_INSTS_VALU x 4 / (SIMDs x clock x
+    duration)."""
+    tot = {}
+    for d in dirs:
+        for r in _csv(os.path.join(d, "**", "*counter_collection.csv")):
+            if any(k in r["Kernel_Name"] for k in SOLVE_KERNELS):
+                tot[r["Counter_Name"]] = tot.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+    per = {k: v / solves for k, v in tot.items()}
+    out = {"counters_per_solve": per, "ms_per_solve": ms_per_solve}
+    sec = ms_per_solve / 1e3
+
+    def flops(kind):
+        keys = [f"SQ_INSTS_VALU_{op}_{kind}" for op in ("ADD", "MUL", "TRANS", "FMA")]
+        if not all(k in per for k in keys):
+            return None
+        return 64.0 * (per[keys[0]] + per[keys[1]] + per[keys[2]] + 2.0 * per[keys[3]])
+
+    for kind, peak in (("F64", PEAK_F64_VEC_TFLOPS), ("F32", PEAK_F32_VEC_TFLOPS)):
+        f = flops(kind)
+        if f is not None:
+            out[f"{kind.lower()}_flops_per_solve"] = f
+            out[f"{kind.lower()}_tflops"] = f / sec / 1e12
+            out[f"{kind.lower()}_frac_of_peak"] = f / sec / 1e12 / peak
+    if "SQ_INSTS_VALU" in per:
+        out["valu_issue_fraction"] = per["SQ_INSTS_VALU"] * 4.0 / (N_SIMD * CLOCK_HZ * sec)
+    return out
+
+
 def main(argv=None):
     a = sys.argv[1:] if argv is None else argv
     if a and a[0] == "trace":
@@ -121,6 +168,11 @@ def main(argv=None):
             with open(a[6], "w") as f:
                 f.write(text + "\n")
         print(text)
+    elif a and a[0] == "valu":
+        res = valu(a[3:], int(a[1]), float(a[2]))
+        from .build import kernel_source_hash
+        res["kernel_source_sha256_16"] = kernel_source_hash()
+        print(json.dumps(res, indent=1))
     else:
         print(__doc__)
         return 2
