@@ -252,8 +252,10 @@ def main():
         ok = (status == 0)
         solved = int((ok.to(torch.int64) * ncon_mol[None, :]).sum().item())
         it = iters.to(torch.float64)
+        q = np.percentile(iters.cpu().numpy().ravel(), [50, 99]).tolist()
         return {"gpu_ms": gpu_ms, "wall_s": wall, "solved": solved, "all_ok": bool(ok.all().item()),
                 "iters_mean": float(it.mean().item()), "iters_max": int(iters.max().item()),
+                "iters_p50": q[0], "iters_p99": q[1],
                 "fallback_rate": float(fallback.to(torch.float64).mean().item()),
                 "last_index": (steps - 1) % len(pool)}
 
@@ -399,6 +401,7 @@ def main():
     traffic = measured_traffic(args.workload, head_name, head["tuning"])
     variants = {k: {"value": v["constraints_per_s"], "ms_per_step": v["ms_per_step"], "all_ok": v["all_ok"],
                     "newton_iters_mean": v["iters_mean"], "newton_iters_max": v["iters_max"],
+                    "newton_iters_p50": v["iters_p50"], "newton_iters_p99": v["iters_p99"],
                     "fallback_rate": v["fallback_rate"] if k == "learned" else None,
                     "max_rel_violation_last": v["max_rel_violation_last"],
                     "tuning": v["tuning"]} for k, v in results.items()}
