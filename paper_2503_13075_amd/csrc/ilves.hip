@@ -258,8 +258,12 @@ __device__ __forceinline__ void st_rec(double* p, double x, double y, double z, 
   *reinterpret_cast<double2*>(p + 2) = make_double2(z, l);
 }
 // entries gathered per batch: row neighbours (global memory, FP64),
-// lower / upper entries of the factor, factor updates
+// lower / upper entries of the factor, factor updates.  kBatchNWide
+// neighbours per batch for launches whose workgroups need more than half
+// of a CU's LDS: one of them runs per CU whatever its registers, so the
+// wider batch (more loads in flight, more registers) costs no occupancy.
 constexpr int kBatchN = 2;
+constexpr int kBatchNWide = 4;
 constexpr int kBatch = 2;
 constexpr int kBatchU = 1;
 // 1/a from the hardware reciprocal refined by Newton steps (one in FP32,
@@ -319,7 +323,7 @@ template <> __device__ inline float pivot_eps<float>() { return 1e-6f; }
 // published border data in the same order, and solves it; each part then
 // sets its border unknowns to z_S, substitutes backward through its interior
 // levels and updates lambda; a second barrier publishes the new lambdas.
-template <typename T, typename Idx, int MODE, int BLOCK, bool SPLIT = false>
+template <typename T, typename Idx, int MODE, int BLOCK, bool SPLIT = false, int NB = kBatchN>
 __global__ void __launch_bounds__(BLOCK) solve_kernel(const DevPlan P, const int32_t* __restrict__ mols,
                                                       const int32_t count, int32_t* __restrict__ counter,
                                                       const SolveArgs A) {
@@ -560,26 +564,26 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(const DevPlan P, const int
     }
   };
   // row k of A(x, r), x having bond vector (px, py, pz).  Entries are taken
-  // kBatchN at a time (indices clamped to the last entry, extra lanes of a
+  // NB at a time (indices clamped to the last entry, extra lanes of a
   // batch discarded) so that their loads are issued together.
   auto build_row = [&](int32_t k, double px, double py, double pz) {
     const Rec ek = ld_rec(er + 4 * k);
     set_diag(k, static_cast<T>(uc[4 * k + 3] * (px * ek.x + py * ek.y + pz * ek.z)));
     const int32_t q0 = up_start[k], nq = up_start[k + 1] - q0;
     const int32_t t0 = l_start[k], tot = nq + (l_start[k + 1] - t0);
-    for (int32_t b = 0; b < tot; b += kBatchN) {
-      int32_t sb[kBatchN];
-      Rec nb[kBatchN];
-      double cb[kBatchN];
+    for (int32_t b = 0; b < tot; b += NB) {
+      int32_t sb[NB];
+      Rec nb[NB];
+      double cb[NB];
 #pragma unroll
-      for (int i = 0; i < kBatchN; ++i) {
+      for (int i = 0; i < NB; ++i) {
         int32_t j;
         slot_of(imin(b + i, tot - 1), q0, nq, t0, sb[i], j);
         nb[i] = ld_rec(er + 4 * j);
         cb[i] = cf[sb[i]];
       }
 #pragma unroll
-      for (int i = 0; i < kBatchN; ++i)
+      for (int i = 0; i < NB; ++i)
         if (b + i < tot) F[sb[i]] = static_cast<T>(cb[i] * (px * nb[i].x + py * nb[i].y + pz * nb[i].z));
     }
   };
@@ -917,8 +921,8 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(const DevPlan P, const int
   if (!SPLIT && chord_singular) st_code = ILVES_ERR_SINGULAR;
   while (!chord_singular) {
     // ---- residual at the current lambda; Newton: rebuild the matrix rows.
-    //      The neighbour entries are gathered kBatchN at a time; when a row
-    //      has at most kBatchN of them they stay in registers for the build.
+    //      The neighbour entries are gathered NB at a time; when a row
+    //      has at most NB of them they stay in registers for the build.
     double vmax = 0.0;
     for (int32_t k = tid; k < n; k += BLOCK) {
       const Rec ek = ld_rec(er + 4 * k);
@@ -929,19 +933,19 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(const DevPlan P, const int
       double pz = uk.z - lk * ek.z;
       const int32_t q0 = up_start[k], nq = up_start[k + 1] - q0;
       const int32_t t0 = l_start[k], tot = nq + (l_start[k + 1] - t0);
-      int32_t sb[kBatchN];
-      Rec nb[kBatchN];
-      double cb[kBatchN];
-      for (int32_t b = 0; b < tot; b += kBatchN) {
+      int32_t sb[NB];
+      Rec nb[NB];
+      double cb[NB];
+      for (int32_t b = 0; b < tot; b += NB) {
 #pragma unroll
-        for (int i = 0; i < kBatchN; ++i) {
+        for (int i = 0; i < NB; ++i) {
           int32_t j;
           slot_of(imin(b + i, tot - 1), q0, nq, t0, sb[i], j);
           nb[i] = ld_rec(er + 4 * j);
           cb[i] = cf[sb[i]];
         }
 #pragma unroll
-        for (int i = 0; i < kBatchN; ++i) {
+        for (int i = 0; i < NB; ++i) {
           if (b + i < tot) {
             const double c = cb[i] * nb[i].l;
             px -= c * nb[i].x;
@@ -990,10 +994,10 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(const DevPlan P, const int
         }
       }
       if (!A.chord) {
-        if (tot <= kBatchN) {
+        if (tot <= NB) {
           set_diag(k, static_cast<T>(uk.l * (px * ek.x + py * ek.y + pz * ek.z)));
 #pragma unroll
-          for (int i = 0; i < kBatchN; ++i)
+          for (int i = 0; i < NB; ++i)
             if (i < tot) F[sb[i]] = static_cast<T>(cb[i] * (px * nb[i].x + py * nb[i].y + pz * nb[i].z));
         } else {
           build_row(k, px, py, pz);
@@ -1332,7 +1336,8 @@ int kernel_block(int mode, bool wide, int block) {
 }
 
 template <typename T>
-KernelFn pick_mode(int mode, bool wide, int block) {
+KernelFn pick_mode(int mode, bool wide, int block, bool heavy) {
+  if (heavy && mode == ALL_LDS && !wide && block == 512) return solve_kernel<T, uint16_t, ALL_LDS, 512, false, kBatchNWide>;
   if (wide) return mode == VALUES_LDS ? pick_big<T, int32_t, VALUES_LDS>(block) : pick_big<T, int32_t, GLOBAL>(block);
   if (mode == ALL_LDS) return pick_block<T, uint16_t, ALL_LDS>(block);
   if (mode == STRUCT_LDS) return pick_big<T, uint16_t, STRUCT_LDS>(block);
@@ -1340,8 +1345,8 @@ KernelFn pick_mode(int mode, bool wide, int block) {
   return pick_big<T, uint16_t, GLOBAL>(block);
 }
 
-KernelFn pick_kernel(bool fp32, int mode, bool wide, int block) {
-  return fp32 ? pick_mode<float>(mode, wide, block) : pick_mode<double>(mode, wide, block);
+KernelFn pick_kernel(bool fp32, int mode, bool wide, int block, bool heavy = false) {
+  return fp32 ? pick_mode<float>(mode, wide, block, heavy) : pick_mode<double>(mode, wide, block, heavy);
 }
 
 // parts of split molecules (16-bit indices): structure and values in LDS,
@@ -1369,6 +1374,7 @@ struct Group {
   int32_t counter = 0;  // index of the group's queue counter
   int stream = 0;       // index into the plan's streams
   int64_t work = 0;     // sum over its molecules of rows + off-diagonal slots
+  bool heavy = false;   // one workgroup per CU by LDS: the wide-batch kernel
 };
 constexpr int kMaxGroups = 64;
 
@@ -1958,6 +1964,7 @@ ilves_status_t build_device_plan(ilves_plan* P) {
 ilves_status_t finalize_groups(ilves_plan* P) {
   for (int prec = 0; prec < 2; ++prec)
     for (Group& g : P->groups[prec]) {
+      g.heavy = false;
       const void* k = reinterpret_cast<const void*>(pick_kernel(prec == 1, g.mode, g.wide, g.block));
       // the attribute is per kernel and process-wide: always raise it to the
       // largest size any plan may use, never lower it
@@ -1965,6 +1972,15 @@ ilves_status_t finalize_groups(ilves_plan* P) {
       int per_cu = 0;
       HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, g.block, static_cast<size_t>(g.lds_bytes)));
       if (per_cu < 1) return fail(ILVES_ERR_HIP, "a solve kernel cannot be resident on a compute unit");
+      // one workgroup per CU by LDS: the wide-batch kernel costs no occupancy
+      // (512 threads: at 1024 the launch bounds leave 128 registers, too few)
+      if (per_cu == 1 && g.mode == ALL_LDS && !g.wide && g.block == 512) {
+        const void* kh = reinterpret_cast<const void*>(pick_kernel(prec == 1, g.mode, g.wide, g.block, true));
+        HIP_TRY(hipFuncSetAttribute(kh, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsMax));
+        int per_cu_h = 0;
+        HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_h, kh, g.block, static_cast<size_t>(g.lds_bytes)));
+        if (per_cu_h >= 1) g.heavy = true;
+      }
       g.grid = static_cast<int32_t>(std::min<int64_t>(g.count, static_cast<int64_t>(per_cu) * P->n_cu));
     }
   // split molecules: launches of whole molecules whose parts can all be
@@ -2334,7 +2350,7 @@ ilves_status_t solve_impl(ilves_plan_t P, const double* r, const double* r_u, co
   }
   for (size_t gi = 0; gi < groups.size(); ++gi) {
     const Group& g = groups[gi];
-    KernelFn k = pick_kernel(precision == ILVES_PREC_MIXED, g.mode, g.wide, g.block);
+    KernelFn k = pick_kernel(precision == ILVES_PREC_MIXED, g.mode, g.wide, g.block, g.heavy);
     hipStream_t s = P->streams[g.stream];
     DevPlan dp = P->dp;
     const int32_t* list = P->d_lists + g.first;
