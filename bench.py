@@ -24,6 +24,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+AT_DEFAULT_STORE = os.path.join(os.path.expanduser("~"), ".cache", "ilves_tuning_new.json")
 
 
 def log(*a):
@@ -164,7 +165,9 @@ def main():
                     help='apply this launch tuning instead of autotuning, JSON: {"band_block": [5 ints], "lds_limit": n}')
     ap.add_argument("--tuning-file", default=os.path.join(ROOT, "paper_2503_13075_amd", "tuning.json"),
                     help="launch tunings recorded per device and workload; a miss autotunes and records the result "
-                         "in gpurun_out/tuning_new.json")
+                         "in --tuning-store")
+    ap.add_argument("--tuning-store", default=AT_DEFAULT_STORE,
+                    help="file that receives tunings found by autotuning (the recorded file is left unchanged)")
     ap.add_argument("--retune", action="store_true", help="autotune even when the tuning file has an entry")
     ap.add_argument("--rng-steps", type=int, default=1000,
                     help="also replay a graph of [device Philox inputs, solve, step += 1] this many times (0: skip)")
@@ -173,7 +176,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: the solve works on one GPU's share of molecules and "
-              "this build has no multi-GPU path", file=sys.stderr)
+              "this library has no multi-GPU path", file=sys.stderr)
         sys.exit(2)
 
     t0 = time.perf_counter()
@@ -369,7 +372,7 @@ def main():
             t = dict(AT.autotune(plan, run_one, reps=10), cached=False)
         else:
             t = AT.tuned(plan, run_one, key, path=args.tuning_file, reps=10,
-                         store_path=os.path.join(ROOT, "gpurun_out", "tuning_new.json"))
+                         store_path=args.tuning_store)
         log(f"tuning precision {prec} start {warm} (key {key}): {t}")
         tunings[(prec, warm)] = t
         return t

@@ -1,7 +1,7 @@
 // Device kernels and the C ABI of the constraint solver (gfx950 / CDNA4).
 //
-// Method (Supplement section 2.3 and 3 of the ILVES paper, spec sign
-// convention, see include/ilves.h):
+// Method (Supplement section 2.3 and 3 of the ILVES paper, with lambda
+// entering as r' = r_u - M^{-1} G(r)^T lambda, see include/ilves.h):
 //   r'(lambda) = r_u - M^{-1} G(r)^T lambda                     (Eq. 6)
 //   Newton: A(r', r) z = g(r'), lambda += z, A = G(r') M^{-1} G(r)^T (Eq. defA)
 //   chord:  the same with the constant A(r, r)                   (ILVES-F)
