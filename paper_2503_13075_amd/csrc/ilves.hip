@@ -822,11 +822,15 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(const DevPlan P, const int
           break;
         }
         const double inv = 1.0 / piv;
-        const int32_t q = p + 1 + tid, c1 = p + bw < ms - 1 ? p + bw : ms - 1;
-        if (tid < bw && q < ms) {
-          const double f = Sm[q * (ms + 1) + p] * inv;
-          for (int32_t c = p + 1; c <= c1; ++c) Sm[q * (ms + 1) + c] -= f * Sm[p * (ms + 1) + c];
-          if (cols > ms) Sm[q * (ms + 1) + ms] -= f * Sm[p * (ms + 1) + ms];
+        // rows p + 1 .. p + nr, columns p + 1 .. c1 (and the right-hand side
+        // column): one (row, column) entry per lane; column p and row p are
+        // only read in this step, so every entry has one writer
+        const int32_t c1 = p + bw < ms - 1 ? p + bw : ms - 1;
+        const int32_t nr = c1 - p, w = nr + (cols > ms ? 1 : 0);
+        for (int32_t l = tid; l < nr * w; l += 64) {
+          const int32_t r = l / w, cc = l - r * w;
+          const int32_t q = p + 1 + r, c = cc < nr ? p + 1 + cc : ms;
+          Sm[q * (ms + 1) + c] -= Sm[q * (ms + 1) + p] * inv * Sm[p * (ms + 1) + c];
         }
         __builtin_amdgcn_wave_barrier();
       }
