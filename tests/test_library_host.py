@@ -1,7 +1,6 @@
 """Host-side checks of the C-ABI library (no GPU): it loads, exports every
 function include/ilves.h declares, validates topologies, and its planner's
 schedule, replayed on the host, reproduces the oracle."""
-import ctypes
 
 import numpy as np
 import pytest
