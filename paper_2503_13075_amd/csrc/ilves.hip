@@ -260,8 +260,10 @@ __device__ __forceinline__ void st_rec(double* p, double x, double y, double z, 
 // entries gathered per batch: row neighbours (global memory, FP64),
 // lower / upper entries of the factor, factor updates.  kBatchNWide
 // neighbours per batch for launches whose workgroups need more than half
-// of a CU's LDS: one of them runs per CU whatever its registers, so the
-// wider batch (more loads in flight, more registers) costs no occupancy.
+// of a CU's LDS, and for the parts of split molecules whose structure is
+// read from global memory: one of them runs per CU whatever its registers,
+// so the wider batch (more loads in flight, more registers) costs no
+// occupancy.
 constexpr int kBatchN = 2;
 constexpr int kBatchNWide = 4;
 constexpr int kBatch = 2;
@@ -328,6 +330,11 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(const DevPlan P, const int
                                                       const int32_t count, int32_t* __restrict__ counter,
                                                       const SolveArgs A) {
   extern __shared__ __align__(16) unsigned char smem[];
+  // factor entries / updates per batch: wider where the structure is read
+  // from global memory, so that several of its records are in flight
+  constexpr bool kStructGlobal = MODE == VALUES_LDS || MODE == GLOBAL;
+  constexpr int KB = kStructGlobal ? 4 : kBatch;
+  constexpr int KU = kStructGlobal ? 8 : kBatchU;
   __shared__ double red[BLOCK / 64];
   __shared__ double red0[BLOCK / 64];
   __shared__ int32_t singular;
@@ -590,7 +597,7 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(const DevPlan P, const int
 
   // one elimination level: diagonal entries (forward substitution fused
   // when FORWARD) and, when FACTOR, the upper entries with updates.  The
-  // entries of an item are taken kBatch (updates kBatchU) at a time, indices
+  // entries of an item are taken KB (updates KU) at a time, indices
   // clamped to the last entry and the extra lanes of a batch discarded, so
   // that the loads of a batch are issued together.
   auto factor_level = [&](int32_t h, auto factor_tag, auto forward_tag) {
@@ -610,20 +617,20 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(const DevPlan P, const int
         T acc = D[j], yj = y[j];
         const T a0 = acc;
         const int32_t t0 = l_start[j], nt = l_start[j + 1] - t0;
-        for (int32_t b = 0; b < nt; b += kBatch) {
-          int32_t ii[kBatch], ss[kBatch];
-          T f[kBatch], di[kBatch], fs[kBatch], yi[kBatch];
+        for (int32_t b = 0; b < nt; b += KB) {
+          int32_t ii[KB], ss[KB];
+          T f[KB], di[KB], fs[KB], yi[KB];
 #pragma unroll
-          for (int i = 0; i < kBatch; ++i) ld2(lpair + 2 * (t0 + imin(b + i, nt - 1)), ii[i], ss[i]);
+          for (int i = 0; i < KB; ++i) ld2(lpair + 2 * (t0 + imin(b + i, nt - 1)), ii[i], ss[i]);
 #pragma unroll
-          for (int i = 0; i < kBatch; ++i) {
+          for (int i = 0; i < KB; ++i) {
             f[i] = F[t0 + imin(b + i, nt - 1)];
             di[i] = D[ii[i]];
             if (FACTOR) fs[i] = F[ss[i]];
             if (FORWARD) yi[i] = y[ii[i]];
           }
 #pragma unroll
-          for (int i = 0; i < kBatch; ++i) {
+          for (int i = 0; i < KB; ++i) {
             if (b + i < nt) {
               const T l = f[i] * di[i];
               if (FACTOR) acc -= l * fs[i];
@@ -640,17 +647,17 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(const DevPlan P, const int
         int32_t q, tr, u0, nu;
         ld4(prec + 4 * (p0 + idx - nr), q, tr, u0, nu);
         T au = F[q], aw = F[tr];
-        for (int32_t b = 0; b < nu; b += kBatchU) {
-          int32_t pa[kBatchU], pb[kBatchU], s1[kBatchU], s2[kBatchU], ui[kBatchU];
+        for (int32_t b = 0; b < nu; b += KU) {
+          int32_t pa[KU], pb[KU], s1[KU], s2[KU], ui[KU];
 #pragma unroll
-          for (int i = 0; i < kBatchU; ++i) {
+          for (int i = 0; i < KU; ++i) {
             const int32_t u = u0 + imin(b + i, nu - 1);
             ld4(upd + 4 * u, pa[i], pb[i], s1[i], s2[i]);
             ui[i] = updi[u];
           }
-          T fa[kBatchU], fb[kBatchU], f1[kBatchU], f2[kBatchU], di[kBatchU];
+          T fa[KU], fb[KU], f1[KU], f2[KU], di[KU];
 #pragma unroll
-          for (int i = 0; i < kBatchU; ++i) {
+          for (int i = 0; i < KU; ++i) {
             fa[i] = F[pa[i]];
             fb[i] = F[pb[i]];
             f1[i] = F[s1[i]];
@@ -658,7 +665,7 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(const DevPlan P, const int
             di[i] = D[ui[i]];
           }
 #pragma unroll
-          for (int i = 0; i < kBatchU; ++i) {
+          for (int i = 0; i < KU; ++i) {
             if (b + i < nu) {
               au -= fa[i] * di[i] * f1[i];
               aw -= fb[i] * di[i] * f2[i];
@@ -684,18 +691,18 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(const DevPlan P, const int
         T acc = y[k];
         const T dk = D[k];
         const int32_t q0 = up_start[k], nq = up_start[k + 1] - q0;
-        for (int32_t b = 0; b < nq; b += kBatch) {
-          int32_t c[kBatch];
-          T f[kBatch], yc[kBatch];
+        for (int32_t b = 0; b < nq; b += KB) {
+          int32_t c[KB];
+          T f[KB], yc[KB];
 #pragma unroll
-          for (int i = 0; i < kBatch; ++i) c[i] = ucol[q0 + imin(b + i, nq - 1)];
+          for (int i = 0; i < KB; ++i) c[i] = ucol[q0 + imin(b + i, nq - 1)];
 #pragma unroll
-          for (int i = 0; i < kBatch; ++i) {
+          for (int i = 0; i < KB; ++i) {
             f[i] = F[q0 + imin(b + i, nq - 1)];
             yc[i] = y[c[i]];
           }
 #pragma unroll
-          for (int i = 0; i < kBatch; ++i)
+          for (int i = 0; i < KB; ++i)
             if (b + i < nq) acc -= f[i] * yc[i];
         }
         y[k] = acc * dk;
@@ -1360,8 +1367,8 @@ KernelFn pick_split(bool fp32, int mode) {
   if (mode == ALL_LDS)
     return fp32 ? solve_kernel<float, uint16_t, ALL_LDS, kSplitBlock, true>
                 : solve_kernel<double, uint16_t, ALL_LDS, kSplitBlock, true>;
-  return fp32 ? solve_kernel<float, uint16_t, VALUES_LDS, kSplitBlock, true>
-              : solve_kernel<double, uint16_t, VALUES_LDS, kSplitBlock, true>;
+  return fp32 ? solve_kernel<float, uint16_t, VALUES_LDS, kSplitBlock, true, kBatchNWide>
+              : solve_kernel<double, uint16_t, VALUES_LDS, kSplitBlock, true, kBatchNWide>;
 }
 
 constexpr int kLdsMax = 160 * 1024 - 1024;  // dynamic LDS a molecule may use
