@@ -809,6 +809,13 @@ bool plan_split(const std::vector<int32_t>& cons, const int32_t* pairs, const do
   S.m = m;
   S.parts.resize(G);
   std::vector<std::vector<int32_t>> row_of(G);  // per part: local constraint -> local row (or -1)
+  // Parts take nested dissection unless an ordering is forced: every part of
+  // a molecule waits at the barriers for the one with the most levels, and
+  // the parts whose factor does not fit in LDS read their structure from
+  // global memory level by level, where the level count dominates more than
+  // the cost model (fitted to molecules held in LDS) assumes.
+  PlanOptions part_opt = opt;
+  if (part_opt.ordering == 0) part_opt.ordering = 2;
   for (int32_t g = 0; g < G; ++g) {
     std::vector<int32_t> pc;
     for (int32_t c : interior[g]) pc.push_back(cons[c]);
@@ -816,7 +823,7 @@ bool plan_split(const std::vector<int32_t>& cons, const int32_t* pairs, const do
     PartSpec spec;
     spec.n_tail = static_cast<int32_t>(border[g].size());
     spec.owned = &owned[g];
-    S.parts[g] = plan_molecule(pc, pairs, d, opt, &spec);
+    S.parts[g] = plan_molecule(pc, pairs, d, part_opt, &spec);
     const MolPlan& M = S.parts[g];
     if (M.n_int != static_cast<int32_t>(interior[g].size())) throw std::logic_error("part row count");
     row_of[g].assign(n, -1);
