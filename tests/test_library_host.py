@@ -110,3 +110,14 @@ def test_nested_dissection_shortens_chains():
     t = S.random_tree(300, seed=1, ring_frac=0.0)
     h = L.replay_host(t.n_atoms, t.pairs, t.d, t.mass, S.soa(t.r), S.soa(t.r), 1e-12, ordering=1)
     assert h["stats"]["fill"] == 0
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    """Without the built HIP library nothing falls back to a CPU path: loading
+    it, and planning through it, raise."""
+    monkeypatch.setattr(L, "LIB_PATH", str(tmp_path / "libilves.so"))
+    monkeypatch.setattr(L, "_lib", None)
+    with pytest.raises(ImportError):
+        L.lib()
+    with pytest.raises(ImportError):
+        L.Plan(2, np.array([[0, 1]], np.int32), np.array([0.1]))
