@@ -232,3 +232,29 @@ def test_native_library_is_loaded_once():
     assert "libilves.so" in maps
     hip = {line.split()[-1] for line in maps.splitlines() if "libamdhip64" in line}
     assert len(hip) == 1, hip
+
+
+def test_plain_entry_point_takes_the_plan_options(batch_case):
+    """ilves_solve (no per-call options) runs with the precision, variant and
+    start the plan was created with: same result as the explicit call."""
+    import ctypes
+
+    import torch
+
+    from paper_2503_13075_amd.device import DeviceSystem
+    sm, ru, ref = batch_case
+    for prec, warm in ((L.PREC_FP64, L.WARM_ZERO), (L.PREC_MIXED, L.WARM_DECOUPLED)):
+        plan = L.Plan(sm.n_atoms, sm.pairs, sm.d, precision=prec, warm_start=warm)
+        ds = DeviceSystem(sm).alloc_status(plan.n_molecules)
+        rud = ds.upload_ru(ru)
+        code = plan._L.ilves_solve(plan._h, ds.r.data_ptr(), rud.data_ptr(), ds.mass.data_ptr(), TOL,
+                                   ds.r_out.data_ptr(), ds.lam.data_ptr(), ds.iters.data_ptr(), ds.status.data_ptr(),
+                                   ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+        assert code == L.OK
+        torch.cuda.synchronize()
+        out = {"r_out": ds.r_out.cpu().numpy().T.copy(), "lam": ds.lam.cpu().numpy().copy(),
+               "iters": ds.iters[:plan.n_molecules].cpu().numpy().copy(),
+               "status": ds.status[:plan.n_molecules].cpu().numpy().copy()}
+        _check(sm, ru, out, ref, f"batch16/ilves_solve prec {prec} warm {warm}")
+        ex = solve_once(sm, ru, TOL, prec, L.VARIANT_NEWTON, plan=plan, warm=warm)
+        assert np.array_equal(out["r_out"], ex["r_out"]) and np.array_equal(out["iters"], ex["iters"])
