@@ -4,10 +4,15 @@ workgroups) plus 1,000 lipid chains, 253,926 constraints, with bench.py's
 seed, first perturbed input (sigma 0.006 nm) and default launch.  Every
 constraint is checked (violation <= 1e-12; the correction conserves linear
 and angular momentum and is the sum of pair forces along the old bond
-vectors); sampled molecules small enough for the dense oracle (the smallest,
-random lipids) are compared with it one by one; the split proteins, too
-large for the dense oracle at this size, are compared with the same system
-solved with every molecule whole on one workgroup."""
+vectors).  The first protein (10,519 constraints, split across workgroups)
+is compared element by element with the dense CPU oracle's solution stored
+in tests/golden/angles_protein0.npz (written by
+tests/golden/make_angles_protein.py, which calls only the oracle); sampled
+lipids are solved by the oracle in the test; the split proteins are also
+compared with the same system solved with every molecule whole on one
+workgroup."""
+import os
+
 import numpy as np
 import pytest
 
@@ -17,6 +22,8 @@ from paper_2503_13075_amd import synth as S
 from paper_2503_13075_amd.device import solve_once
 
 pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "angles_protein0.npz")
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -59,6 +66,17 @@ def test_angles_full_size(system, name, prec, warm):
     assert viol <= 1e-12 and dp <= 1e-12 and df <= 1e-12 and dl <= 1e-12
 
     mols = O.molecules(sm.n_atoms, sm.pairs)
+    # the first protein against the dense oracle's stored solution
+    gold = np.load(GOLDEN)
+    atoms, cons = mols[0]
+    assert np.array_equal(atoms, gold["atoms"]) and np.array_equal(cons, gold["cons"])
+    dr = np.max(np.abs(out["r_out"][atoms] - gold["r_new"]))
+    dlam = np.max(np.abs(out["lam"][cons] - gold["lam"])) / np.max(np.abs(gold["lam"]))
+    vmol = np.max(O.relative_violation(out["r_out"], sm.pairs[cons], sm.d[cons]))
+    print(f"   protein 0 ({len(cons)} constraints) vs dense oracle: |dr'| {dr:.1e} nm, |dlambda| rel {dlam:.1e}, "
+          f"violation {vmol:.1e} (oracle {float(gold['violation']):.1e}, {int(gold['iters'])} iterations)", flush=True)
+    assert dr <= 1e-10 and dlam <= 1e-9 and vmol <= 1e-12
+
     sizes = np.array([len(c) for _, c in mols])
     small = np.flatnonzero(sizes < 1000)
     rng = np.random.default_rng(0)
@@ -72,7 +90,7 @@ def test_angles_full_size(system, name, prec, warm):
         dr = np.max(np.abs(out["r_out"][atoms] - rp))
         dlam = np.max(np.abs(out["lam"][cons] - lam)) / np.max(np.abs(lam))
         print(f"   molecule {i} ({len(cons)} constraints): |dr'| {dr:.1e} nm, |dlambda| rel {dlam:.1e}", flush=True)
-        assert dr <= 1e-10 and dlam <= 1e-6
+        assert dr <= 1e-10 and dlam <= 1e-9
 
     whole = solve_once(sm, ru, 1e-12, prec, L.VARIANT_NEWTON, warm=warm, split_rows=-1)
     assert whole["plan"].stats()["split_molecules"] == 0

@@ -20,6 +20,8 @@ pytestmark = pytest.mark.gpu
 
 TOL = 1e-12
 POS_TOL = 1e-10
+# lambda against the oracle, relative to the largest |lambda| (observed <= 1.5e-11)
+LAM_TOL = 1e-9
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -45,7 +47,7 @@ def _check(sm, ru, out, ref, label):
           f"iters {np.unique(out['iters'], return_counts=True)}", flush=True)
     assert viol <= TOL, (label, viol)
     assert dpos <= POS_TOL, (label, dpos)
-    assert dlam <= 1e-6, (label, dlam)
+    assert dlam <= LAM_TOL, (label, dlam)
 
 
 VARIANTS = [("fp64", L.PREC_FP64, L.VARIANT_NEWTON), ("mixed", L.PREC_MIXED, L.VARIANT_NEWTON),

@@ -40,7 +40,7 @@ def _check(sm, out, ref, label):
     dlam = np.max(np.abs(out["lam"] - ref["lam"])) / np.max(np.abs(ref["lam"]))
     print(f"{label}: violation {viol:.2e}, |dr'| {dpos:.2e} nm, |dlambda| rel {dlam:.2e}, iters {out['iters']}",
           flush=True)
-    assert viol <= TOL and dpos <= POS_TOL and dlam <= 1e-6, label
+    assert viol <= TOL and dpos <= POS_TOL and dlam <= 1e-9, label
 
 
 CASES = {

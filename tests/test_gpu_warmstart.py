@@ -159,6 +159,7 @@ def test_learned_start_solve_matches_oracle(torch, precision):
     assert np.all(status == L.OK)
     assert viol <= 1e-12
     assert dpos <= 1e-10
+    assert dlam <= 1e-9
 
 
 def test_corrupted_network_falls_back_and_converges(torch):

@@ -88,3 +88,83 @@ def test_neighbour_ratio_is_newton_matrix_ratio(seed):
     A = O.newton_matrix(sm.r, sm.r, sm.pairs, 1.0 / sm.mass)
     off = np.abs(A - np.diag(np.diag(A))).sum(1) / np.diag(A)
     assert np.allclose(f[:, 8], off, rtol=1e-12, atol=1e-15)
+
+
+# --------------------------------------------------------------------------- forward pass
+
+def _gelu_by_quadrature(x):
+    """x Phi(x) with Phi integrated numerically (independent of the oracle's
+    erf-based GELU)."""
+    return x * quad(lambda t: math.exp(-t * t / 2) / math.sqrt(2 * math.pi), -np.inf, x)[0]
+
+
+def _routing_network():
+    """A network with a handful of non-zero weights placed by the documented
+    flat layout (W1 [16, 64] row-major, b1 [64], W2 [64, 64] row-major, b2,
+    W3 [64], b3), so that each output is a known composition of GELUs:
+      h1_0 = G(1.5 x_2),  h1_1 = G(0.3 - x_7)
+      h2_4 = G(h1_0 + 2 h1_1 - 0.1),  h2_9 = G(h1_1)
+      out  = 3 h2_4 - 0.5 h2_9 + 0.25
+    (every other hidden unit is G(0) = 0)."""
+    F, H = M.N_FEAT, M.N_HID
+    o_b1 = F * H
+    o_W2 = o_b1 + H
+    o_b2 = o_W2 + H * H
+    o_W3 = o_b2 + H
+    o_b3 = o_W3 + H
+    p = np.zeros(M.N_PARAMS)
+    p[2 * H + 0] = 1.5
+    p[7 * H + 1] = -1.0
+    p[o_b1 + 1] = 0.3
+    p[o_W2 + 0 * H + 4] = 1.0
+    p[o_W2 + 1 * H + 4] = 2.0
+    p[o_b2 + 4] = -0.1
+    p[o_W2 + 1 * H + 9] = 1.0
+    p[o_W3 + 4] = 3.0
+    p[o_W3 + 9] = -0.5
+    p[o_b3] = 0.25
+    assert o_b3 + 1 == M.N_PARAMS
+    return p
+
+
+def _routing_expected(x):
+    G = _gelu_by_quadrature
+    out = []
+    for row in x:
+        h0, h1 = G(1.5 * row[2]), G(0.3 - row[7])
+        out.append(3.0 * G(h0 + 2.0 * h1 - 0.1) - 0.5 * G(h1) + 0.25)
+    return np.array(out)
+
+
+def test_forward_pass_of_a_routing_network():
+    """The forward pass against a hand-built network evaluated with a
+    quadrature GELU.  Transposed weight matrices, a dropped bias or a
+    missing activation route or shift the output and fail."""
+    rng = np.random.default_rng(8)
+    x = rng.normal(0, 1.5, size=(9, M.N_FEAT))
+    p = _routing_network()
+    got = M.forward(p, x)
+    exp = _routing_expected(x)
+    assert np.allclose(got, exp, rtol=1e-12, atol=1e-13), np.abs(got - exp).max()
+    # inputs the network does not read leave the output unchanged
+    x2 = x.copy()
+    x2[:, [0, 1, 3, 4, 5, 6, 8, 15]] += 3.0
+    assert np.array_equal(M.forward(p, x2), got)
+    # the training path's own forward pass: its loss at y = 0 is mean(out^2) / 2
+    loss, _ = M.loss_and_grad(p, x, np.zeros(x.shape[0]))
+    assert abs(loss - 0.5 * np.mean(exp ** 2)) <= 1e-12 * loss
+
+
+def test_predict_lambda_composition():
+    """lambda_0 = (t0 + scale * MLP((f - mean) / std)) / w with the routing
+    network: normalisation, scale, the decoupled base term f_0 and the
+    division by w each enter as stated."""
+    rng = np.random.default_rng(9)
+    f = rng.normal(0, 1.0, size=(6, M.N_FEAT))
+    mean = rng.normal(0, 0.3, M.N_FEAT)
+    std = rng.uniform(0.5, 2.0, M.N_FEAT)
+    w = rng.uniform(0.05, 1.0, 6)
+    scale = 0.037
+    lam = M.predict_lambda(_routing_network(), mean, std, scale, f, w)
+    exp = (f[:, 0] + scale * _routing_expected((f - mean) / std)) / w
+    assert np.allclose(lam, exp, rtol=1e-12, atol=1e-14), np.abs(lam - exp).max()

@@ -304,3 +304,73 @@ def test_planted_mistakes_are_caught(monkeypatch):
     out = O.solve([[0, 1], [2, 1]], [d, d], m, r, ru3, tol=1e-15, until_stagnation=True, max_iter=8)
     lam = P.symmetric_triatomic_lambda(r[0], r[1], r[2], ru3[0], ru3[1], m[0], m[1], d)
     assert np.max(np.abs(out["lam"] - lam)) > 1e-6 * abs(lam)
+
+
+# --------------------------------------------------------------------------- the violation measure
+
+# Two atoms a distance L apart under a constraint of length d: the constraint
+# value is (L^2 - d^2) / 2 and the relative violation that the stopping rule
+# bounds (Supplement section 4, read with an absolute value) is
+# |L^2 - d^2| / (2 d^2).  Values worked out by hand:
+#   (L, d, g, relative violation)
+VIOLATION_CASES = [
+    (2.0, 1.0, 1.5, 1.5),
+    (0.5, 1.0, -0.375, 0.375),
+    (0.11, 0.1, 0.00105, 0.105),
+    (0.09, 0.1, -0.00095, 0.095),
+    (0.0, 0.25, -0.03125, 0.5),
+    (0.153, 0.153, 0.0, 0.0),
+]
+
+
+def violation_pin_error():
+    """Largest deviation of the oracle's constraint values and relative
+    violations from the hand-computed cases.  Each pair sits at an arbitrary
+    centre and orientation; all pairs are in one system so that the output
+    order is checked too."""
+    rng = np.random.default_rng(21)
+    k = len(VIOLATION_CASES)
+    x = np.zeros((2 * k, 3))
+    pairs = np.zeros((k, 2), np.int64)
+    d = np.zeros(k)
+    for i, (L, dd, _, _) in enumerate(VIOLATION_CASES):
+        c = rng.uniform(-5, 5, 3)
+        u = P.random_rotation(rng)[:, 0]
+        x[2 * i], x[2 * i + 1] = c + 0.5 * L * u, c - 0.5 * L * u
+        pairs[i] = (2 * i + 1, 2 * i) if i % 2 else (2 * i, 2 * i + 1)
+        d[i] = dd
+    g = O.constraint_values(x, pairs, d)
+    rel = O.relative_violation(x, pairs, d)
+    err = 0.0
+    for i, (L, dd, gv, rv) in enumerate(VIOLATION_CASES):
+        err = max(err, abs(g[i] - gv) / max(abs(gv), dd * dd), abs(rel[i] - rv) / max(rv, 1.0))
+    return err
+
+
+def test_relative_violation_hand_computed():
+    assert violation_pin_error() <= 1e-12
+
+
+def test_planted_violation_mistakes_are_caught(monkeypatch):
+    """Dividing by d instead of d^2 (0.0105 instead of 0.105), dropping the
+    factor 1/2 (0.21) or the absolute value (-0.375) fails the pin."""
+    good_cv = O.constraint_values
+    for bad in (lambda x, p, d: np.abs(good_cv(x, p, d)) / d,
+                lambda x, p, d: 2.0 * np.abs(good_cv(x, p, d)) / (d * d),
+                lambda x, p, d: good_cv(x, p, d) / (d * d)):
+        monkeypatch.setattr(O, "relative_violation", bad)
+        assert violation_pin_error() > 1e-3
+
+
+def test_relative_violation_of_a_stretched_chain():
+    """Every bond of a straight 5-atom chain stretched by 1%: each bond's
+    relative violation is (1.01^2 - 1) / 2 = 0.01005; the 1-3 distance of a
+    straight chain is exactly twice the bond, so a 1-3 constraint of length
+    2 d also reads 0.01005."""
+    d = 0.153
+    x = np.zeros((5, 3))
+    x[:, 0] = np.arange(5) * 1.01 * d
+    pairs = np.array([[0, 1], [1, 2], [2, 3], [3, 4], [0, 2]])
+    dd = np.array([d, d, d, d, 2 * d])
+    rel = O.relative_violation(x, pairs, dd)
+    assert np.allclose(rel, 0.01005, rtol=1e-12, atol=0.0), rel
