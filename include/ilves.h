@@ -55,8 +55,8 @@ typedef enum {
   ILVES_ERR_NONFINITE = 7,      /* per molecule: NaN or Inf met in the residual             */
   ILVES_ERR_UNSUPPORTED = 8,    /* option combination not built into this library           */
   ILVES_ERR_TIMEOUT = 9         /* per molecule: the workgroups of a split molecule did not
-                                   meet at a barrier within its wait limit; the plan must be
-                                   recreated                                                */
+                                   meet at a barrier within its wait limit; later solves of
+                                   the plan report it too until ilves_plan_reset_barriers  */
 } ilves_status_t;
 
 enum { ILVES_PREC_FP64 = 0, ILVES_PREC_MIXED = 1 };
@@ -96,7 +96,8 @@ typedef struct {
                             limits)                                             */
 } ilves_options_t;
 
-/* Fills *opt with defaults (FP64 Newton, lambda_0 = 0, automatic schedule). */
+/* Fills *opt with defaults (FP64 Newton, lambda_0 = 0, automatic schedule).
+ * Defined by: Supplement section 2.3 (Newton from lambda_0 = 0). */
 void ilves_default_options(ilves_options_t* opt);
 
 /*
@@ -111,15 +112,22 @@ void ilves_default_options(ilves_options_t* opt);
  *   opt            host options (NULL = defaults)
  *   out            receives the plan handle
  * The topology is copied; the caller may free it afterwards.
+ * Defined by: Supplement section 2.2 (constraints g_k, Eq. ecconstr) and
+ * section 3 (the graph G of constrained bonds, its line graph L(G) whose
+ * adjacency is the pattern of A, the fill-reducing ordering and the
+ * initialisation done once before the Newton iterations).
  * Errors: ILVES_ERR_ARG, ILVES_ERR_TOPOLOGY, ILVES_ERR_NOMEM, ILVES_ERR_HIP.
  */
 ilves_status_t ilves_plan_create(int32_t n_atoms, int32_t n_constraints, const int32_t* pairs,
                                  const double* d, const ilves_options_t* opt, ilves_plan_t* out);
 
-/* Releases the plan and its device memory.  NULL is accepted. */
+/* Releases the plan and its device memory.  NULL is accepted.  Errors: none
+ * (ILVES_OK).  No defining passage (resource management). */
 ilves_status_t ilves_plan_destroy(ilves_plan_t plan);
 
-/* Number of molecules (components with at least one constraint). */
+/* Number of molecules: connected components of G with at least one
+ * constraint (Supplement section 3, G is usually disconnected); -1 for a
+ * NULL plan. */
 int32_t ilves_plan_num_molecules(ilves_plan_t plan);
 
 /*
@@ -130,9 +138,23 @@ int32_t ilves_plan_num_molecules(ilves_plan_t plan);
  * which releases every other waiter; the molecule reports ILVES_ERR_TIMEOUT
  * in this and every later solve of the plan.  A small limit forces that
  * path (used to test it).  Takes effect at the next solve enqueued.
+ * Defined by: Supplement section 3 (shared and private partitions of L(G),
+ * the shared part's Schur complement solved between the partitions' own
+ * eliminations); the barrier itself is this library's design.
  * Errors: ILVES_ERR_ARG (NULL plan, polls < 0).
  */
 ilves_status_t ilves_plan_set_wait_limit(ilves_plan_t plan, int32_t polls);
+
+/*
+ * Clears the barrier state of every split molecule of the plan (arrival
+ * count, generation and poisoned flag), so that molecules that reported
+ * ILVES_ERR_TIMEOUT solve again.  Synchronises the device first (no solve of
+ * any plan may be left in flight; the call waits for all of them) and
+ * again after clearing.  The current device must be the plan's.  Host call,
+ * not graph-capturable.  Defined by: as ilves_plan_set_wait_limit.
+ * Errors: ILVES_ERR_ARG (NULL plan, other device), ILVES_ERR_HIP.
+ */
+ilves_status_t ilves_plan_reset_barriers(ilves_plan_t plan);
 
 /*
  * Plan statistics, host int64 array of ILVES_STAT_COUNT entries:
@@ -144,6 +166,8 @@ ilves_status_t ilves_plan_set_wait_limit(ilves_plan_t plan, int32_t polls);
  *   [13] workgroups (parts) of the split molecules, [14] largest separator
  *   (constraints joining the parts of one molecule), [15] split molecules
  *   whose parts keep only their factor values in LDS (FP64).
+ * Defined by: Supplement section 3 (L(G), ordering, fill of the factors).
+ * Errors: ILVES_ERR_ARG (NULL plan or stats).
  */
 #define ILVES_STAT_COUNT 16
 ilves_status_t ilves_plan_stats(ilves_plan_t plan, int64_t* stats);
@@ -152,6 +176,8 @@ ilves_status_t ilves_plan_stats(ilves_plan_t plan, int64_t* stats);
  * Per-molecule description, host arrays of length num_molecules (any may be
  * NULL): constraint count, atom count, level count, and the first input
  * constraint index of each molecule in the plan's molecule order.
+ * Defined by: Supplement section 3 (molecules, levels of the elimination).
+ * Errors: ILVES_ERR_ARG (NULL plan).
  */
 ilves_status_t ilves_plan_molecules(ilves_plan_t plan, int32_t* n_con, int32_t* n_atoms,
                                     int32_t* n_levels, int32_t* first_constraint);
@@ -167,6 +193,8 @@ ilves_status_t ilves_plan_molecules(ilves_plan_t plan, int32_t* n_con, int32_t* 
  * sin(2 pi u2); z_z is the first normal of the counter {i, 1, ...}.
  * r, r_u: device SoA [3][n_atoms] FP64 (may not alias); step: device
  * uint64, read when the kernel runs.  Asynchronous on hip_stream.
+ * Defined by: no passage of the paper (input generation for benchmarks
+ * and tests; the generator follows Salmon et al.).
  * Errors: ILVES_ERR_ARG (negative n_atoms or sigma, null pointers),
  * ILVES_ERR_HIP.
  */
@@ -175,6 +203,7 @@ ilves_status_t ilves_perturb_normal(const double* r, int32_t n_atoms, double sig
 
 /* *counter += delta on the device (advances the step of
  * ilves_perturb_normal inside a captured graph).  counter: device uint64.
+ * Defined by: no passage (input generation).
  * Errors: ILVES_ERR_ARG (null), ILVES_ERR_HIP. */
 ilves_status_t ilves_counter_add(uint64_t* counter, uint64_t delta, void* hip_stream);
 
@@ -188,6 +217,8 @@ ilves_status_t ilves_counter_add(uint64_t* counter, uint64_t delta, void* hip_st
  * All arrays are device SoA [3][n_atoms] FP64 (mass [n_atoms]); v holds the
  * half-step velocities.  r_u and r_new must not alias r.  Units: nm, ps,
  * amu, forces in amu nm ps^-2.  Asynchronous on hip_stream, graph-capturable.
+ * Defined by: Supplement section 2.3, Eqs. nonlinear:1a-1c (the constrained
+ * leapfrog whose position step is the constraint solve).
  * Errors: ILVES_ERR_ARG (n_atoms < 0, h not positive, null pointers),
  * ILVES_ERR_HIP.
  */
@@ -204,7 +235,9 @@ ilves_status_t ilves_md_finish(double* r, const double* r_new, double h, int32_t
  * fall in band 3 up to 4096 constraints and in band 4 above.  The partly-LDS
  * kernels exist with 512 and 1024 threads only; smaller requests round up to
  * 512.  lds_limit caps the LDS one molecule may use (0 = all of it); lowering
- * it moves molecules out of LDS.
+ * it moves molecules out of LDS.  Defined by: no passage (a launch knob of
+ * this library; the ordering and factorisation it schedules are those of
+ * Supplement section 3).
  */
 typedef struct {
   int32_t band_block[5];   /* 64, 128, 256, 512 or 1024 */
@@ -212,7 +245,7 @@ typedef struct {
   int32_t reserved[2];
 } ilves_tuning_t;
 
-/* Current tuning of the plan. */
+/* Current tuning of the plan.  Errors: ILVES_ERR_ARG (NULL plan or t). */
 ilves_status_t ilves_plan_get_tuning(ilves_plan_t plan, ilves_tuning_t* t);
 
 /* Re-derives the placement and launch groups of the plan from a tuning
@@ -242,6 +275,11 @@ ilves_status_t ilves_plan_tune(ilves_plan_t plan, const ilves_tuning_t* t);
  * captured in a HIP graph.  One solve per plan may be in flight at a time.
  * The return code reports argument and launch errors only; convergence is
  * reported per molecule in status[] (read it after synchronising).
+ * Defined by: Supplement section 2.3 (Eq. 6 position map, Eq. defA Newton
+ * matrix, Eqs. newton-constraint-equation update from lambda_0 = 0) and
+ * section 4 (stopping rule max_k |g_k| / d_k^2 <= Tol).
+ * Errors: ILVES_ERR_ARG (NULL plan or array, tol not positive, other
+ * device), ILVES_ERR_HIP (launch failure).
  */
 ilves_status_t ilves_solve(ilves_plan_t plan, const double* r, const double* r_u, const double* mass,
                            double tol, double* r_out, double* lambda, int32_t* iters, int32_t* status,
@@ -264,14 +302,20 @@ ilves_status_t ilves_solve(ilves_plan_t plan, const double* r, const double* r_u
  *   mu           device double [n_constraints] multipliers (input order)
  *   iters, status  as for ilves_solve
  * Asynchronous on hip_stream, allocates nothing, graph-capturable; one solve
- * or projection per plan in flight.  Errors as ilves_solve.
+ * or projection per plan in flight.  Defined by: Supplement section 2 (the
+ * velocity constraints G(r) v = 0 that follow from differentiating g along
+ * the motion, with the multiplier term of the equations of motion) and
+ * Eq. defA at r' = r.  Errors as ilves_solve.
  */
 ilves_status_t ilves_project_velocities(ilves_plan_t plan, const double* r, const double* v, const double* mass,
                                         double tol, int32_t precision, double* v_out, double* mu, int32_t* iters,
                                         int32_t* status, void* hip_stream);
 
 /* Same as ilves_solve with explicit precision / variant / warm start /
- * iteration cap, overriding the plan's options for this call. */
+ * iteration cap, overriding the plan's options for this call.  Defined by:
+ * as ilves_solve; the chord variant by Supplement section 3 (ILVES-F, the
+ * constant matrix A(r, r) factored once per solve).  Errors as ilves_solve,
+ * plus ILVES_ERR_ARG for an unknown precision, variant or warm start. */
 ilves_status_t ilves_solve_ex(ilves_plan_t plan, const double* r, const double* r_u, const double* mass,
                               double tol, int32_t precision, int32_t variant, int32_t warm_start,
                               int32_t max_iter, double* r_out, double* lambda, int32_t* iters,
@@ -294,22 +338,32 @@ ilves_status_t ilves_solve_ex(ilves_plan_t plan, const double* r, const double* 
 int32_t ilves_mlp_param_count(void);
 int32_t ilves_mlp_norm_count(void);
 
-/* Copies network parameters and normalisation (host float arrays) into the
- * plan and reserves the plan's feature buffers (4 * 17 bytes per
- * constraint).  Errors: ILVES_ERR_ARG, ILVES_ERR_HIP. */
-ilves_status_t ilves_mlp_load(ilves_plan_t plan, const float* params, const float* norm);
+/* Copies network parameters and normalisation (host float arrays of
+ * n_params = ilves_mlp_param_count() and n_norm = ilves_mlp_norm_count()
+ * values) into the plan and reserves the plan's feature buffers (4 * 17
+ * bytes per constraint).  Defined by: no passage (the learned start is not
+ * in the paper; it replaces the lambda_0 = 0 of Supplement section 2.3).
+ * Errors: ILVES_ERR_ARG (NULL pointer, a count that differs from the
+ * library's, a non-finite value, a feature scale not > 0), ILVES_ERR_HIP. */
+ilves_status_t ilves_mlp_load(ilves_plan_t plan, const float* params, int32_t n_params, const float* norm,
+                              int32_t n_norm);
 
 /* Features of every constraint, in plan row order (ilves_plan_row_constraints
  * maps rows to input constraints): feat device float [n_constraints][16],
- * w device float [n_constraints].  Asynchronous on hip_stream. */
+ * w device float [n_constraints].  Asynchronous on hip_stream.  Defined by:
+ * no passage (learned start); the coupling ratios are entries of Eq. defA.
+ * Errors: ILVES_ERR_ARG (NULL argument), ILVES_ERR_HIP. */
 ilves_status_t ilves_features(ilves_plan_t plan, const double* r, const double* r_u, const double* mass,
                               float* feat, float* w, void* hip_stream);
 
-/* Host int32 [n_constraints]: input constraint index of each plan row. */
+/* Host int32 [n_constraints]: input constraint index of each plan row
+ * (rows are ordered by elimination level, Supplement section 3).
+ * Errors: ILVES_ERR_ARG (NULL argument). */
 ilves_status_t ilves_plan_row_constraints(ilves_plan_t plan, int32_t* cid);
 
 /* The network's lambda_0 (device double [n_constraints], input order).
- * Errors: ILVES_ERR_UNSUPPORTED if no network was loaded. */
+ * Defined by: no passage (learned start).  Errors: ILVES_ERR_ARG (NULL
+ * argument), ILVES_ERR_UNSUPPORTED if no network was loaded, ILVES_ERR_HIP. */
 ilves_status_t ilves_mlp_predict(ilves_plan_t plan, const double* r, const double* r_u, const double* mass,
                                  double* lambda, void* hip_stream);
 
@@ -318,28 +372,35 @@ ilves_status_t ilves_mlp_predict(ilves_plan_t plan, const double* r, const doubl
  * that of lambda = 0 (or not finite), or when the violation rises in two
  * consecutive iterations.  fallback: device int32 [num_molecules] set to 1
  * where the fallback was taken (may be NULL).  Other arguments as
- * ilves_solve_ex.  Errors as ilves_solve_ex, plus ILVES_ERR_UNSUPPORTED
- * without a loaded network. */
+ * ilves_solve_ex.  Defined by: as ilves_solve, with lambda_0 from the
+ * network instead of 0.  Errors as ilves_solve_ex, plus
+ * ILVES_ERR_UNSUPPORTED without a loaded network. */
 ilves_status_t ilves_solve_learned(ilves_plan_t plan, const double* r, const double* r_u, const double* mass,
                                    double tol, int32_t precision, int32_t variant, int32_t max_iter,
                                    double* r_out, double* lambda, int32_t* iters, int32_t* status,
                                    int32_t* fallback, void* hip_stream);
 
-/* Training kernels (FP32, device arrays, asynchronous on hip_stream).
- * Forward pass of normalised inputs x [n][16] -> out [n]. */
+/* Training kernels (FP32, device arrays, asynchronous on hip_stream;
+ * defined by no passage of the paper: the network of the learned start).
+ * Forward pass of normalised inputs x [n][16] -> out [n].
+ * Errors: ILVES_ERR_ARG (NULL argument, n < 0), ILVES_ERR_HIP. */
 ilves_status_t ilves_mlp_forward_f32(const float* params, const float* x, int32_t n, float* out,
                                      void* hip_stream);
 
-/* Floats of workspace ilves_mlp_grad_f32 needs for n samples. */
+/* Floats of workspace ilves_mlp_grad_f32 needs for n samples (0 for n <= 0). */
 int64_t ilves_mlp_grad_workspace(int32_t n);
 
 /* Gradient of L = 1/(2n) sum_s (out_s - y_s)^2 with respect to the
  * parameters: grad [param_count], loss [1], work [ilves_mlp_grad_workspace(n)].
- * Partial sums are combined in a fixed order (deterministic). */
+ * Partial sums are combined in a fixed order (deterministic).
+ * Errors: ILVES_ERR_ARG (NULL argument, n <= 0, work_floats too small),
+ * ILVES_ERR_HIP. */
 ilves_status_t ilves_mlp_grad_f32(const float* params, const float* x, const float* y, int32_t n, float* grad,
                                   float* loss, float* work, int64_t work_floats, void* hip_stream);
 
-/* One Adam step (Kingma and Ba) on n parameters, step counting from 1. */
+
+/* One Adam step (Kingma and Ba) on n parameters, step counting from 1.
+ * Errors: ILVES_ERR_ARG (NULL argument, n <= 0, step < 1), ILVES_ERR_HIP. */
 ilves_status_t ilves_mlp_adam_f32(float* params, const float* grad, float* m, float* v, int32_t n, float lr,
                                   float beta1, float beta2, float eps, int32_t step, void* hip_stream);
 
@@ -356,6 +417,8 @@ ilves_status_t ilves_mlp_adam_f32(float* params, const float* grad, float* m, fl
  *   (at least the number of molecules); *n_molecules receives that number
  *   schedule_stats: host int64 [6] (molecules, factor entries, factor updates,
  *   largest level count, fill entries, split molecules) or NULL
+ * Defined by: as ilves_plan_create and ilves_solve.
+ * Errors: as ilves_plan_create (ILVES_ERR_ARG, ILVES_ERR_TOPOLOGY).
  */
 ilves_status_t ilves_plan_replay_host(int32_t n_atoms, int32_t n_constraints, const int32_t* pairs,
                                       const double* d, const ilves_options_t* opt, const double* mass,

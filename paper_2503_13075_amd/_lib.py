@@ -85,6 +85,8 @@ def lib() -> ctypes.CDLL:
     L.ilves_project_velocities.restype = ctypes.c_int
     L.ilves_plan_set_wait_limit.argtypes = [_P, ctypes.c_int32]
     L.ilves_plan_set_wait_limit.restype = ctypes.c_int
+    L.ilves_plan_reset_barriers.argtypes = [_P]
+    L.ilves_plan_reset_barriers.restype = ctypes.c_int
     L.ilves_plan_stats.argtypes = [_P, _I64P]
     L.ilves_plan_stats.restype = ctypes.c_int
     L.ilves_plan_molecules.argtypes = [_P, _I32P, _I32P, _I32P, _I32P]
@@ -100,7 +102,7 @@ def lib() -> ctypes.CDLL:
     L.ilves_plan_replay_host.restype = ctypes.c_int
     L.ilves_mlp_param_count.restype = ctypes.c_int32
     L.ilves_mlp_norm_count.restype = ctypes.c_int32
-    L.ilves_mlp_load.argtypes = [_P, _F32P, _F32P]
+    L.ilves_mlp_load.argtypes = [_P, _F32P, ctypes.c_int32, _F32P, ctypes.c_int32]
     L.ilves_mlp_load.restype = ctypes.c_int
     L.ilves_features.argtypes = [_P, _P, _P, _P, _P, _P, _P]
     L.ilves_features.restype = ctypes.c_int
@@ -246,6 +248,12 @@ class Plan:
         ilves_plan_set_wait_limit)."""
         check(self._L.ilves_plan_set_wait_limit(self._h, int(polls)))
 
+    def reset_barriers(self):
+        """Clears the barrier state of every split molecule (after
+        ILVES_ERR_TIMEOUT); synchronises the device (see
+        ilves_plan_reset_barriers)."""
+        check(self._L.ilves_plan_reset_barriers(self._h))
+
     def stats(self) -> dict:
         st = np.zeros(len(STAT_NAMES), np.int64)
         check(self._L.ilves_plan_stats(self._h, _ptr(st, ctypes.c_int64)))
@@ -337,7 +345,8 @@ def _plan_load_mlp(self, params, norm):
     norm = np.ascontiguousarray(norm, dtype=np.float32)
     if params.size != mlp_param_count() or norm.size != mlp_norm_count():
         raise ValueError("wrong parameter or normalisation size")
-    check(self._L.ilves_mlp_load(self._h, _ptr(params, ctypes.c_float), _ptr(norm, ctypes.c_float)))
+    check(self._L.ilves_mlp_load(self._h, _ptr(params, ctypes.c_float), params.size, _ptr(norm, ctypes.c_float),
+                                 norm.size))
 
 
 def _plan_row_constraints(self):

@@ -1423,6 +1423,7 @@ struct ilves_plan {
   std::vector<ilves::SplitPlan> splits;  // molecules split across workgroups
   std::vector<int32_t> split_mol;        // their molecule indices
   std::vector<int32_t> split_first;      // first part (device part index) of each
+  std::vector<int64_t> split_xch;        // workspace byte offset of each one's exchange area
   std::vector<int> split_lds[2];         // per part: dynamic LDS bytes
   std::vector<int> split_mode[2];        // per split molecule: ALL_LDS or VALUES_LDS
   std::vector<SplitLaunch> split_launch[2];
@@ -1622,6 +1623,7 @@ ilves_status_t build_device_plan(ilves_plan* P) {
   std::vector<int32_t> sadj, bsep, ext_ptr, ext_coef;
   std::vector<int64_t> ext_rec;
   P->split_first.clear();
+  P->split_xch.clear();
   for (int prec = 0; prec < 2; ++prec) {
     P->split_lds[prec].clear();
     P->split_mode[prec].clear();
@@ -1667,6 +1669,7 @@ ilves_status_t build_device_plan(ilves_plan* P) {
         seprows.push_back(R);
       }
       P->split_first.push_back(static_cast<int32_t>(sparts.size()));
+      P->split_xch.push_back(xch);
       // placement per precision: structure and values in LDS when every part
       // fits, else the values only
       for (int prec = 0; prec < 2; ++prec) {
@@ -2254,6 +2257,17 @@ ilves_status_t ilves_plan_set_wait_limit(ilves_plan_t P, int32_t polls) {
   return ILVES_OK;
 }
 
+ilves_status_t ilves_plan_reset_barriers(ilves_plan_t P) {
+  if (!P) return fail(ILVES_ERR_ARG, "plan must not be NULL");
+  int dev = -1;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev != P->device) return fail(ILVES_ERR_ARG, "plan was created on another device");
+  HIP_TRY(hipDeviceSynchronize());
+  for (int64_t xch : P->split_xch) HIP_TRY(hipMemset(P->d_ws + xch, 0, 64));
+  HIP_TRY(hipDeviceSynchronize());
+  return ILVES_OK;
+}
+
 ilves_status_t ilves_plan_stats(ilves_plan_t P, int64_t* stats) {
   if (!P || !stats) return fail(ILVES_ERR_ARG, "plan and stats must not be NULL");
   std::memcpy(stats, P->stats, sizeof(P->stats));
@@ -2469,8 +2483,16 @@ ilves_status_t ilves_plan_row_constraints(ilves_plan_t P, int32_t* cid) {
 int32_t ilves_mlp_param_count(void) { return ilves_ws::N_PARAMS; }
 int32_t ilves_mlp_norm_count(void) { return ilves_ws::N_NORM; }
 
-ilves_status_t ilves_mlp_load(ilves_plan_t P, const float* params, const float* norm) {
+ilves_status_t ilves_mlp_load(ilves_plan_t P, const float* params, int32_t n_params, const float* norm,
+                              int32_t n_norm) {
   if (!P || !params || !norm) return fail(ILVES_ERR_ARG, "null argument");
+  if (n_params != ilves_ws::N_PARAMS)
+    return fail(ILVES_ERR_ARG, "n_params must be ilves_mlp_param_count() = " + std::to_string(ilves_ws::N_PARAMS));
+  if (n_norm != ilves_ws::N_NORM)
+    return fail(ILVES_ERR_ARG, "n_norm must be ilves_mlp_norm_count() = " + std::to_string(ilves_ws::N_NORM));
+  for (int i = 0; i < ilves_ws::N_PARAMS + ilves_ws::N_NORM; ++i)
+    if (!std::isfinite(i < ilves_ws::N_PARAMS ? params[i] : norm[i - ilves_ws::N_PARAMS]))
+      return fail(ILVES_ERR_ARG, "network parameters and normalisation must be finite");
   for (int i = 0; i < ilves_ws::N_FEAT; ++i)
     if (!(norm[ilves_ws::N_FEAT + i] > 0.0f)) return fail(ILVES_ERR_ARG, "feature scales must be positive");
   if (!P->d_mlp) HIP_TRY(hipMalloc(&P->d_mlp, sizeof(float) * (ilves_ws::N_PARAMS + ilves_ws::N_NORM)));

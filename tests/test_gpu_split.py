@@ -218,12 +218,14 @@ def test_split_with_values_only_in_lds():
         _check(sm, out, ref, f"h-angle protein values-only/{prec}")
 
 
-def test_split_wait_limit_reports_timeout_and_poisons_the_plan():
+def test_split_wait_limit_reports_timeout_and_reset_recovers():
     """Failure handling of the split barriers, forced from the host: with a
     wait limit of zero polls a workgroup that has to wait gives up at once,
     marks the molecule poisoned and every part leaves; the split molecule
     reports ILVES_ERR_TIMEOUT (the whole molecules of the system still solve),
-    and so does every later solve of that plan, whatever the limit."""
+    and so does every later solve of that plan, whatever the limit, until
+    the host clears the barriers (ilves_plan_reset_barriers); the plan then
+    solves the split molecule again, against the oracle."""
     import torch
     print("== split wait limit", flush=True)
     sm = S.concat([S.protein(60, seed=3), S.random_tree(200, seed=4)], spacing=2.0)
@@ -242,6 +244,14 @@ def test_split_wait_limit_reports_timeout_and_poisons_the_plan():
         assert st[split_idx] == L.ERR_TIMEOUT, (rep, st)
         assert np.all(np.delete(st, split_idx) == L.OK), (rep, st)
         plan.set_wait_limit(1 << 22)
+    plan.reset_barriers()
+    plan.solve(ds.r, rud, ds.mass, TOL, ds.r_out, ds.lam, ds.iters, ds.status)
+    torch.cuda.synchronize()
+    st = ds.status.cpu().numpy()[:plan.n_molecules]
+    assert np.all(st == L.OK), st
+    out = {"r_out": ds.r_out.cpu().numpy().T.copy(), "lam": ds.lam.cpu().numpy().copy(), "status": st,
+           "iters": ds.iters.cpu().numpy()[:plan.n_molecules]}
+    _check(sm, out, _oracle(sm, ru), "split after reset")
     with pytest.raises(L.IlvesError):
         plan.set_wait_limit(-1)
 
