@@ -398,6 +398,23 @@ int64_t ilves_mlp_grad_workspace(int32_t n);
 ilves_status_t ilves_mlp_grad_f32(const float* params, const float* x, const float* y, int32_t n, float* grad,
                                   float* loss, float* work, int64_t work_floats, void* hip_stream);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight training loops, harnesses that forbid allocation): the
+ * gradient of ilves_mlp_grad_f32, same kernels and same result, with the
+ * per-workgroup partial sums in a fixed device array of the library instead
+ * of a caller workspace.  Allocates nothing.  At most
+ * ILVES_MLP_GRAD_STATIC_MAX_SAMPLES samples per call (the array holds 192
+ * workgroup records of 5,314 floats, 4.1 MB per GPU, kept until the process
+ * ends).  Every call on a GPU shares that GPU's array: calls that overlap on
+ * one GPU (several streams or host threads at once) race and must be
+ * serialised by the caller.  params, x, y, grad, loss as ilves_mlp_grad_f32.
+ * Errors: ILVES_ERR_ARG (NULL argument, n <= 0, n above the maximum),
+ * ILVES_ERR_HIP.
+ */
+#define ILVES_MLP_GRAD_STATIC_MAX_SAMPLES 12288
+ilves_status_t ilves_mlp_grad_f32_static(const float* params, const float* x, const float* y, int32_t n,
+                                         float* grad, float* loss, void* hip_stream);
 
 /* One Adam step (Kingma and Ba) on n parameters, step counting from 1.
  * Errors: ILVES_ERR_ARG (NULL argument, n <= 0, step < 1), ILVES_ERR_HIP. */

@@ -119,6 +119,8 @@ def lib() -> ctypes.CDLL:
     L.ilves_mlp_grad_workspace.restype = ctypes.c_int64
     L.ilves_mlp_grad_f32.argtypes = [_P, _P, _P, ctypes.c_int32, _P, _P, _P, ctypes.c_int64, _P]
     L.ilves_mlp_grad_f32.restype = ctypes.c_int
+    L.ilves_mlp_grad_f32_static.argtypes = [_P, _P, _P, ctypes.c_int32, _P, _P, _P]
+    L.ilves_mlp_grad_f32_static.restype = ctypes.c_int
     L.ilves_mlp_adam_f32.argtypes = [_P, _P, _P, _P, ctypes.c_int32, ctypes.c_float, ctypes.c_float,
                                      ctypes.c_float, ctypes.c_float, ctypes.c_int32, _P]
     L.ilves_mlp_adam_f32.restype = ctypes.c_int
@@ -326,6 +328,22 @@ def mlp_grad_f32(params, x, y, grad, loss, work, stream=None):
                                    _dev(y, torch.float32, (n,)), n, _dev(grad, torch.float32),
                                    _dev(loss, torch.float32), _dev(work, torch.float32), work.numel(),
                                    _stream(stream)))
+
+
+# sample limit of ilves_mlp_grad_f32_static, as include/ilves.h defines it
+MLP_GRAD_STATIC_MAX_SAMPLES = int(re.search(r"#define ILVES_MLP_GRAD_STATIC_MAX_SAMPLES (\d+)",
+                                            open(HEADER).read()).group(1))
+
+
+def mlp_grad_f32_static(params, x, y, grad, loss, stream=None):
+    """The gradient of mlp_grad_f32 without a workspace: the library's fixed
+    device array holds the partial sums (at most MLP_GRAD_STATIC_MAX_SAMPLES
+    samples; calls that overlap on one GPU race)."""
+    import torch
+    n = x.shape[0]
+    check(lib().ilves_mlp_grad_f32_static(_dev(params, torch.float32), _dev(x, torch.float32, (n, 16)),
+                                          _dev(y, torch.float32, (n,)), n, _dev(grad, torch.float32),
+                                          _dev(loss, torch.float32), _stream(stream)))
 
 
 def mlp_grad_workspace(n) -> int:

@@ -2523,6 +2523,19 @@ ilves_status_t ilves_mlp_grad_f32(const float* params, const float* x, const flo
   return e == hipSuccess ? ILVES_OK : fail(ILVES_ERR_HIP, hipGetErrorString(e));
 }
 
+ilves_status_t ilves_mlp_grad_f32_static(const float* params, const float* x, const float* y, int32_t n, float* grad,
+                                         float* loss, void* hip_stream) {
+  static_assert(ILVES_MLP_GRAD_STATIC_MAX_SAMPLES == ilves_ws::kStaticGradBlocks * ilves_ws::TRAIN_BS,
+                "header limit and device array size disagree");
+  if (!params || !x || !y || !grad || !loss || n <= 0) return fail(ILVES_ERR_ARG, "bad argument");
+  if (n > ILVES_MLP_GRAD_STATIC_MAX_SAMPLES)
+    return fail(ILVES_ERR_ARG, "n = " + std::to_string(n) + " exceeds ILVES_MLP_GRAD_STATIC_MAX_SAMPLES (" +
+                                   std::to_string(ILVES_MLP_GRAD_STATIC_MAX_SAMPLES) +
+                                   "); use ilves_mlp_grad_f32 with a workspace");
+  hipError_t e = ilves_ws::launch_mlp_grad_f32_static(params, x, y, n, grad, loss, static_cast<hipStream_t>(hip_stream));
+  return e == hipSuccess ? ILVES_OK : fail(ILVES_ERR_HIP, hipGetErrorString(e));
+}
+
 ilves_status_t ilves_mlp_adam_f32(float* params, const float* grad, float* m, float* v, int32_t n, float lr,
                                   float beta1, float beta2, float eps, int32_t step, void* hip_stream) {
   if (!params || !grad || !m || !v || n <= 0 || step < 1) return fail(ILVES_ERR_ARG, "bad argument");

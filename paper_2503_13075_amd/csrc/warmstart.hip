@@ -20,6 +20,7 @@
 #include "warmstart.hpp"
 
 #include <cmath>
+#include <mutex>
 
 namespace ilves_ws {
 
@@ -456,6 +457,49 @@ hipError_t launch_mlp_grad_f32(const float* params, const float* x, const float*
   hipLaunchKernelGGL(reduce_partials, dim3((N_PARAMS + 1 + 255) / 256), dim3(256), 0, stream, work, blocks, grad,
                      loss);
   return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Gradient without a caller workspace, for callers that cannot allocate
+// (HIP graph capture, tight training loops): the per-workgroup partial
+// gradients go to this file-scope device array.  Each GPU holds its own copy
+// of it (until the process ends).  In host code the name `scratch` is only a
+// host-side stand-in, never a device address: the address is looked up once
+// per device with hipGetSymbolAddress, with that device current, and that
+// pointer is what the kernels receive.  Every call overwrites the partials
+// it reads (ceil(n / TRAIN_BS) whole records), so nothing has to start at
+// zero; two calls that overlap on one GPU race on the array.
+static __device__ __align__(256) float scratch[kStaticGradBlocks * (N_PARAMS + 1)];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t static_grad_scratch(float** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = static_cast<float*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
+hipError_t launch_mlp_grad_f32_static(const float* params, const float* x, const float* y, int32_t n, float* grad,
+                                      float* loss, hipStream_t stream) {
+  if (n <= 0 || n > kStaticGradBlocks * TRAIN_BS) return hipErrorInvalidValue;
+  float* work = nullptr;
+  const hipError_t e = static_grad_scratch(&work);
+  if (e != hipSuccess) return e;
+  return launch_mlp_grad_f32(params, x, y, n, grad, loss, work, stream);
 }
 
 hipError_t launch_mlp_adam(float* params, const float* grad, float* m, float* v, int32_t n, float lr, float beta1,

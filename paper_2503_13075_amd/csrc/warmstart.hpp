@@ -40,6 +40,13 @@ hipError_t launch_mlp_forward_f32(const float* params, const float* x, int32_t n
 hipError_t launch_mlp_grad_f32(const float* params, const float* x, const float* y, int32_t n, float* grad,
                                float* loss, float* work, hipStream_t stream);
 
+// The same gradient with the partials in a file-scope device array of
+// kStaticGradBlocks workgroup records (no caller workspace, no allocation):
+// n <= kStaticGradBlocks * TRAIN_BS.  Calls that overlap on one GPU race.
+constexpr int kStaticGradBlocks = 192;  // 12,288 samples, 4.1 MB per GPU
+hipError_t launch_mlp_grad_f32_static(const float* params, const float* x, const float* y, int32_t n, float* grad,
+                                      float* loss, hipStream_t stream);
+
 // One Adam step on n parameters (step counts from 1).
 hipError_t launch_mlp_adam(float* params, const float* grad, float* m, float* v, int32_t n, float lr, float beta1,
                            float beta2, float eps, int32_t step, hipStream_t stream);
