@@ -200,7 +200,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--variants", default="fp64,mixed,decoupled,learned",
                     help="comma list of fp64, mixed, decoupled (mixed, each constraint's decoupled solution as "
-                         "lambda_0), learned (mixed, network lambda_0)")
+                         "lambda_0), learned (mixed, network lambda_0), and the chord method (A(r, r) factored "
+                         "once per solve): chord64, chord_mixed, chord_decoupled")
     ap.add_argument("--ordering", type=int, default=0,
                     help="fill-reducing ordering: 0 automatic, 1 minimum deficiency, 2 nested dissection")
     ap.add_argument("--eager", action="store_true", help="launch every step instead of replaying HIP graphs")
@@ -249,7 +250,7 @@ def main():
     ncon_mol = torch.from_numpy(mol["n_con"].astype(np.int64)).to(dev)
     stream = torch.cuda.current_stream()
 
-    def run(precision, steps, warmup, learned=False, warm=L.WARM_ZERO):
+    def run(precision, steps, warmup, learned=False, warm=L.WARM_ZERO, variant=L.VARIANT_NEWTON):
         iters = torch.zeros((steps, nm), dtype=torch.int32, device=dev)
         status = torch.full((steps, nm), -1, dtype=torch.int32, device=dev)
         fallback = torch.zeros((steps, nm), dtype=torch.int32, device=dev)
@@ -258,10 +259,11 @@ def main():
 
         def one(k, it, stt, fb):
             if learned:
-                plan.solve_learned(r, pool[k % len(pool)], mass, 1e-12, r_out, lam, it, stt, fb, precision=precision)
+                plan.solve_learned(r, pool[k % len(pool)], mass, 1e-12, r_out, lam, it, stt, fb, precision=precision,
+                                   variant=variant)
             else:
                 plan.solve(r, pool[k % len(pool)], mass, 1e-12, r_out, lam, it, stt, precision=precision,
-                           warm_start=warm)
+                           warm_start=warm, variant=variant)
 
         for w in range(warmup):
             one(w, wi, ws, None)
@@ -312,7 +314,7 @@ def main():
         viol = float(np.max(O.relative_violation(rp, sm.pairs, sm.d)))
         return viol
 
-    def rng_graph(steps, precision, learned, warm=L.WARM_ZERO):
+    def rng_graph(steps, precision, learned, warm=L.WARM_ZERO, variant=L.VARIANT_NEWTON):
         """Many solves without the host: one captured graph draws the step's
         r_u on the device (Philox4x32-10 + Box-Muller, step index in device
         memory), solves, folds status and iterations into device
@@ -331,9 +333,10 @@ def main():
         def one():
             gen()
             if learned:
-                plan.solve_learned(r, ru, mass, 1e-12, r_out, lam, it, stt, precision=precision)
+                plan.solve_learned(r, ru, mass, 1e-12, r_out, lam, it, stt, precision=precision, variant=variant)
             else:
-                plan.solve(r, ru, mass, 1e-12, r_out, lam, it, stt, precision=precision, warm_start=warm)
+                plan.solve(r, ru, mass, 1e-12, r_out, lam, it, stt, precision=precision, warm_start=warm,
+                           variant=variant)
             torch.maximum(worst, stt, out=worst)
             it_sum.add_(it)
             L.counter_add(step, 1)
@@ -374,7 +377,8 @@ def main():
                 "ms_per_step_solve": solve_ms,
                 "constraints_per_s_solve": (sm.n_constraints / (solve_ms / 1e3)) if ok else 0.0,
                 "all_ok": ok, "newton_iters_mean_per_molecule": iters, "max_rel_violation_last": viol,
-                "variant": "learned" if learned else ("decoupled" if warm == L.WARM_DECOUPLED else "mixed"),
+                "variant": ("chord_" if variant == L.VARIANT_CHORD else "") +
+                           ("learned" if learned else ("decoupled" if warm == L.WARM_DECOUPLED else "mixed")),
                 "seed": 1, "sigma_nm": sigma}
 
     if args.calibrate_copy > 0:
@@ -396,38 +400,44 @@ def main():
         plan.load_mlp(params, norm)
     tunings = {}
 
-    def tune(prec, warm=L.WARM_ZERO):
+    def tune(prec, warm=L.WARM_ZERO, variant=L.VARIANT_NEWTON):
         """Autotunes the launch of this precision and start once (untimed):
         the fastest launch depends on the iteration counts the start gives."""
         if args.tuning or args.no_autotune:
             t = json.loads(args.tuning) if args.tuning else {"band_block": [64, 128, 256, 512, 1024], "lds_limit": 0}
             plan.tune(band_block=t["band_block"], lds_limit=t["lds_limit"])
             return {"band_block": t["band_block"], "lds_limit": t["lds_limit"], "autotuned": False}
-        if (prec, warm) in tunings:
-            plan.tune(band_block=tunings[(prec, warm)]["band_block"], lds_limit=tunings[(prec, warm)]["lds_limit"])
-            return tunings[(prec, warm)]
+        if (prec, warm, variant) in tunings:
+            t = tunings[(prec, warm, variant)]
+            plan.tune(band_block=t["band_block"], lds_limit=t["lds_limit"])
+            return t
         from paper_2503_13075_amd import autotune as AT
         it = torch.zeros(nm, dtype=torch.int32, device=dev)
         stt = torch.zeros(nm, dtype=torch.int32, device=dev)
-        key = AT.plan_key(plan, prec, L.VARIANT_NEWTON, "decoupled" if warm == L.WARM_DECOUPLED else "zero")
+        key = AT.plan_key(plan, prec, variant, "decoupled" if warm == L.WARM_DECOUPLED else "zero")
         run_one = lambda: plan.solve(r, pool[0], mass, 1e-12, r_out, lam, it, stt, precision=prec,  # noqa: E731
-                                     warm_start=warm)
+                                     warm_start=warm, variant=variant)
         if args.retune:
             t = dict(AT.autotune(plan, run_one, reps=10), cached=False)
         else:
             t = AT.tuned(plan, run_one, key, path=args.tuning_file, reps=10,
                          store_path=args.tuning_store)
-        log(f"tuning precision {prec} start {warm} (key {key}): {t}")
-        tunings[(prec, warm)] = t
+        log(f"tuning precision {prec} start {warm} variant {variant} (key {key}): {t}")
+        tunings[(prec, warm, variant)] = t
         return t
 
-    for name, prec in (("fp64", L.PREC_FP64), ("mixed", L.PREC_MIXED), ("decoupled", L.PREC_MIXED),
-                       ("learned", L.PREC_MIXED)):
+    VARIANTS = (("fp64", L.PREC_FP64, L.WARM_ZERO, L.VARIANT_NEWTON),
+                ("mixed", L.PREC_MIXED, L.WARM_ZERO, L.VARIANT_NEWTON),
+                ("decoupled", L.PREC_MIXED, L.WARM_DECOUPLED, L.VARIANT_NEWTON),
+                ("learned", L.PREC_MIXED, L.WARM_ZERO, L.VARIANT_NEWTON),
+                ("chord64", L.PREC_FP64, L.WARM_ZERO, L.VARIANT_CHORD),
+                ("chord_mixed", L.PREC_MIXED, L.WARM_ZERO, L.VARIANT_CHORD),
+                ("chord_decoupled", L.PREC_MIXED, L.WARM_DECOUPLED, L.VARIANT_CHORD))
+    for name, prec, warm, variant in VARIANTS:
         if name not in wanted:
             continue
-        warm = L.WARM_DECOUPLED if name == "decoupled" else L.WARM_ZERO
-        tuning = tune(prec, warm)
-        res = run(prec, args.steps, args.warmup, learned=(name == "learned"), warm=warm)
+        tuning = tune(prec, warm, variant)
+        res = run(prec, args.steps, args.warmup, learned=(name == "learned"), warm=warm, variant=variant)
         res["tuning"] = tuning
         res["max_rel_violation_last"] = check_last(res)
         ms = res["gpu_ms"] / args.steps
@@ -437,7 +447,8 @@ def main():
         log(f"{name}: {ms:.3f} ms/step, {res['constraints_per_s']:.3e} constraints/s, all ok {res['all_ok']}, "
             f"iters mean {res['iters_mean']:.2f} max {res['iters_max']}, last violation {res['max_rel_violation_last']:.2e}")
 
-    heads = [k for k in ("mixed", "decoupled", "learned") if k in results and results[k]["all_ok"]]
+    heads = [k for k in ("mixed", "decoupled", "learned", "chord_mixed", "chord_decoupled")
+             if k in results and results[k]["all_ok"]]
     if "fp64" not in results or not heads:
         print(json.dumps(results), flush=True)
         return
@@ -469,7 +480,10 @@ def main():
         "config": dict(cfg, atoms=sm.n_atoms, constraints=sm.n_constraints,
                        variant={"learned": "mixed precision Newton, learned lambda_0",
                                 "decoupled": "mixed precision Newton, lambda_0 = each constraint's decoupled solution",
-                                "mixed": "mixed precision Newton, lambda_0 = 0"}[head_name],
+                                "mixed": "mixed precision Newton, lambda_0 = 0",
+                                "chord_mixed": "mixed precision chord (A(r, r) factored once), lambda_0 = 0",
+                                "chord_decoupled": "mixed precision chord (A(r, r) factored once), lambda_0 = each "
+                                                   "constraint's decoupled solution"}[head_name],
                        sigma_nm=sigma, tol=1e-12, split_molecules=st["split_molecules"],
                        split_parts=st["split_parts"]),
         "newton_iters": {k: v["iters_mean"] for k, v in results.items()},
@@ -488,9 +502,10 @@ def main():
         out["roofline"]["traffic_gbs"] = traffic / (head["ms_per_step"] / 1e3) / 1e9
     log(f"roofline: {achieved:.0f} GB/s algorithmic, copy {copy_gbs:.0f} GB/s, peak {HBM_PEAK_GBS:.0f} GB/s")
     if args.rng_steps > 0:
-        head_warm = L.WARM_DECOUPLED if head_name == "decoupled" else L.WARM_ZERO
-        tune(L.PREC_MIXED, head_warm)  # the head variant's launch tuning
-        out["rng_graph"] = rng_graph(args.rng_steps, L.PREC_MIXED, head_name == "learned", head_warm)
+        head_warm = L.WARM_DECOUPLED if head_name in ("decoupled", "chord_decoupled") else L.WARM_ZERO
+        head_variant = L.VARIANT_CHORD if head_name.startswith("chord") else L.VARIANT_NEWTON
+        tune(L.PREC_MIXED, head_warm, head_variant)  # the head variant's launch tuning
+        out["rng_graph"] = rng_graph(args.rng_steps, L.PREC_MIXED, head_name == "learned", head_warm, head_variant)
         log(f"rng graph: {out['rng_graph']}")
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")

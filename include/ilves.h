@@ -312,14 +312,26 @@ ilves_status_t ilves_project_velocities(ilves_plan_t plan, const double* r, cons
                                         int32_t* status, void* hip_stream);
 
 /* Same as ilves_solve with explicit precision / variant / warm start /
- * iteration cap, overriding the plan's options for this call.  Defined by:
- * as ilves_solve; the chord variant by Supplement section 3 (ILVES-F, the
- * constant matrix A(r, r) factored once per solve).  Errors as ilves_solve,
- * plus ILVES_ERR_ARG for an unknown precision, variant or warm start. */
+ * iteration cap, overriding the plan's options for this call, and an
+ * optional convergence history:
+ *   history      device double [num_molecules][history_len] or NULL; entry
+ *                (m, l) receives molecule m's maximum relative violation
+ *                max_k |g_k| / d_k^2 at iterate l (before its l-th linear
+ *                solve; l = iters[m] is the final one).  Entries past the
+ *                molecule's last iterate are left unchanged; after a learned
+ *                or decoupled start falls back to lambda_0 = 0 the restart
+ *                overwrites the start's entries.  history_len 0 = none.
+ * Defined by: as ilves_solve; the chord variant by Supplement section 3
+ * (ILVES-F, the constant matrix A(r, r) factored once per solve); the
+ * history is the quantity of Supplement section 4's stopping rule, whose
+ * decrease shows the convergence order (Supplement section 2.3).
+ * Errors as ilves_solve, plus ILVES_ERR_ARG for an unknown precision,
+ * variant or warm start, or history_len < 0 or > 0 with a NULL history;
+ * ILVES_ERR_UNSUPPORTED for ILVES_WARM_MLP without a loaded network. */
 ilves_status_t ilves_solve_ex(ilves_plan_t plan, const double* r, const double* r_u, const double* mass,
                               double tol, int32_t precision, int32_t variant, int32_t warm_start,
                               int32_t max_iter, double* r_out, double* lambda, int32_t* iters,
-                              int32_t* status, void* hip_stream);
+                              int32_t* status, double* history, int32_t history_len, void* hip_stream);
 
 /*
  * Learned warm start.  A small network predicts lambda_0 for the Newton

@@ -94,7 +94,7 @@ def lib() -> ctypes.CDLL:
     L.ilves_solve.argtypes = [_P, _P, _P, _P, ctypes.c_double, _P, _P, _P, _P, _P]
     L.ilves_solve.restype = ctypes.c_int
     L.ilves_solve_ex.argtypes = [_P, _P, _P, _P, ctypes.c_double, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
-                                 ctypes.c_int32, _P, _P, _P, _P, _P]
+                                 ctypes.c_int32, _P, _P, _P, _P, _P, ctypes.c_int32, _P]
     L.ilves_solve_ex.restype = ctypes.c_int
     L.ilves_plan_replay_host.argtypes = [ctypes.c_int32, ctypes.c_int32, _I32P, _F64P, ctypes.POINTER(Options),
                                          _F64P, _F64P, _F64P, ctypes.c_double, ctypes.c_int32, ctypes.c_int32,
@@ -268,10 +268,12 @@ class Plan:
         return {"n_con": a[0][:k], "n_atoms": a[1][:k], "n_levels": a[2][:k], "first_constraint": a[3][:k]}
 
     def solve(self, r, r_u, mass, tol, r_out, lam, iters, status, precision=PREC_FP64, variant=VARIANT_NEWTON,
-              warm_start=WARM_ZERO, max_iter=0, stream=None):
+              warm_start=WARM_ZERO, max_iter=0, stream=None, history=None):
         """Enqueues one solve.  All tensors are CUDA (HIP) tensors: r, r_u,
         r_out float64 [3, n_atoms] contiguous, mass float64 [n_atoms], lam
-        float64 [n_constraints], iters/status int32 [n_molecules]."""
+        float64 [n_constraints], iters/status int32 [n_molecules]; history
+        (optional) float64 [n_molecules, L] receives each molecule's maximum
+        relative violation at iterates 0 .. L-1."""
         import torch
         for t, dt in ((r, torch.float64), (r_u, torch.float64), (mass, torch.float64), (r_out, torch.float64),
                       (lam, torch.float64), (iters, torch.int32), (status, torch.int32)):
@@ -283,11 +285,18 @@ class Plan:
             raise ValueError("mass / lambda have the wrong length")
         if iters.numel() < self.n_molecules or status.numel() < self.n_molecules:
             raise ValueError("iters / status need one entry per molecule")
+        h_ptr, h_len = None, 0
+        if history is not None:
+            if not history.is_cuda or history.dtype != torch.float64 or not history.is_contiguous() or \
+                    history.dim() != 2 or history.shape[0] < self.n_molecules:
+                raise ValueError("history must be a contiguous float64 device tensor [n_molecules, L]")
+            h_ptr, h_len = history.data_ptr(), int(history.shape[1])
         if stream is None:
             stream = torch.cuda.current_stream()
         check(self._L.ilves_solve_ex(self._h, r.data_ptr(), r_u.data_ptr(), mass.data_ptr(), float(tol), precision,
                                      variant, warm_start, max_iter, r_out.data_ptr(), lam.data_ptr(),
-                                     iters.data_ptr(), status.data_ptr(), ctypes.c_void_p(stream.cuda_stream)))
+                                     iters.data_ptr(), status.data_ptr(), h_ptr, h_len,
+                                     ctypes.c_void_p(stream.cuda_stream)))
 
 
 def _stream(stream):

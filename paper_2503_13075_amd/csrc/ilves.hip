@@ -92,6 +92,8 @@ struct SolveArgs {
   int32_t chord;     // 0: Newton, 1: chord
   int32_t wait_limit;  // polls of a split molecule's barrier wait before it gives up
   int32_t project;   // 1: velocity projection (r_u holds velocities, residual e_k . p_k, chord)
+  double* hist;      // per molecule [hist_len]: max relative violation before each linear solve, may be null
+  int32_t hist_len;
 };
 
 // FP64 workspace of a molecule: per row {e, lambda} (4n) and {u, C_kk} (4n),
@@ -470,27 +472,55 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(const DevPlan P, const int
   const int32_t* __restrict__ rga = P.ga + md.row_off;
   const int32_t* __restrict__ rgb = P.gb + md.row_off;
   double v0 = 0.0;  // max relative violation at lambda = 0 (learned start fallback test)
-  for (int32_t k = tid; k < n; k += BLOCK) {
-    const int32_t ga = rga[k], gb = rgb[k];
-    const double a0 = ux[ga] - ux[gb], a1 = ux[S + ga] - ux[S + gb], a2 = ux[2 * S + ga] - ux[2 * S + gb];
-    const double e0 = rx[ga] - rx[gb], e1 = rx[S + ga] - rx[S + gb], e2 = rx[2 * S + ga] - rx[2 * S + gb];
-    const double cdk = 1.0 / A.mass[ga] + 1.0 / A.mass[gb];
-    const double lam0 = A.warm == 3 ? decoupled_lambda(a0, a1, a2, e0, e1, e2, cdk, d2[k])
-                                    : (A.warm ? A.lambda[cid[k]] : 0.0);
-    st_rec(er + 4 * k, e0, e1, e2, lam0);
-    if constexpr (SPLIT) {
-      if (k >= ni) {
-        const int32_t v = P.bsep[sp.bsep_off + (k - ni)];
-        if (v >> 30) {
-          SepX& X = sxa[v & 0x3fffffff];
-          X.e[0] = e0;
-          X.e[1] = e1;
-          X.e[2] = e2;
+  // rows RS per lane at a time (kernels of workgroups alone on their CU,
+  // whose registers cost no occupancy): the gathers of all of them in flight
+  // together
+  constexpr int RS = NB == kBatchNWide ? 2 : 1;
+  for (int32_t k0 = tid; k0 < n; k0 += RS * BLOCK) {
+    int32_t ga[RS], gb[RS];
+#pragma unroll
+    for (int i = 0; i < RS; ++i) {
+      const int32_t k = imin(k0 + i * BLOCK, n - 1);
+      ga[i] = rga[k];
+      gb[i] = rgb[k];
+    }
+    double ua[RS][3], ub[RS][3], ra_[RS][3], rb_[RS][3], ma[RS], mb[RS];
+#pragma unroll
+    for (int i = 0; i < RS; ++i) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        ua[i][c] = ux[c * S + ga[i]];
+        ub[i][c] = ux[c * S + gb[i]];
+        ra_[i][c] = rx[c * S + ga[i]];
+        rb_[i][c] = rx[c * S + gb[i]];
+      }
+      ma[i] = A.mass[ga[i]];
+      mb[i] = A.mass[gb[i]];
+    }
+#pragma unroll
+    for (int i = 0; i < RS; ++i) {
+      const int32_t k = k0 + i * BLOCK;
+      if (k >= n) break;
+      const double a0 = ua[i][0] - ub[i][0], a1 = ua[i][1] - ub[i][1], a2 = ua[i][2] - ub[i][2];
+      const double e0 = ra_[i][0] - rb_[i][0], e1 = ra_[i][1] - rb_[i][1], e2 = ra_[i][2] - rb_[i][2];
+      const double cdk = 1.0 / ma[i] + 1.0 / mb[i];
+      const double lam0 = A.warm == 3 ? decoupled_lambda(a0, a1, a2, e0, e1, e2, cdk, d2[k])
+                                      : (A.warm ? A.lambda[cid[k]] : 0.0);
+      st_rec(er + 4 * k, e0, e1, e2, lam0);
+      if constexpr (SPLIT) {
+        if (k >= ni) {
+          const int32_t v = P.bsep[sp.bsep_off + (k - ni)];
+          if (v >> 30) {
+            SepX& X = sxa[v & 0x3fffffff];
+            X.e[0] = e0;
+            X.e[1] = e1;
+            X.e[2] = e2;
+          }
         }
       }
+      st_rec(uc + 4 * k, a0, a1, a2, cdk);
+      v0 = fmax(v0, fabs(a0 * a0 + a1 * a1 + a2 * a2 - d2[k]) / (2.0 * d2[k]));
     }
-    st_rec(uc + 4 * k, a0, a1, a2, cdk);
-    v0 = fmax(v0, fabs(a0 * a0 + a1 * a1 + a2 * a2 - d2[k]) / (2.0 * d2[k]));
   }
   // slot couplings, four slots per lane at a time so that their two rounds
   // of gathers (coupling code, then the shared atom's mass) overlap
@@ -609,10 +639,15 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(const DevPlan P, const int
     r1 = uni(r1);
     p0 = uni(p0);
     p1 = uni(p1);
+    // the row items are padded to a whole number of waves, so that no wave
+    // holds both kinds of item: a wave with rows and pair tasks would run the
+    // two code paths one after the other
     const int32_t nr = r1 - r0;
-    const int32_t items = nr + (FACTOR ? p1 - p0 : 0);
+    const int32_t nrp = FACTOR ? (nr + 63) & ~63 : nr;
+    const int32_t items = nrp + (FACTOR ? p1 - p0 : 0);
     for (int32_t idx = tid; idx < items; idx += BLOCK) {
-      if (idx < nr) {
+      if (idx < nrp) {
+        if (idx >= nr) continue;
         const int32_t j = r0 + idx;
         T acc = D[j], yj = y[j];
         const T a0 = acc;
@@ -645,7 +680,7 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(const DevPlan P, const int
         if (FORWARD) y[j] = yj;
       } else if (FACTOR) {
         int32_t q, tr, u0, nu;
-        ld4(prec + 4 * (p0 + idx - nr), q, tr, u0, nu);
+        ld4(prec + 4 * (p0 + idx - nrp), q, tr, u0, nu);
         T au = F[q], aw = F[tr];
         for (int32_t b = 0; b < nu; b += KU) {
           int32_t pa[KU], pb[KU], s1[KU], s2[KU], ui[KU];
@@ -1046,6 +1081,10 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(const DevPlan P, const int
       gmax = uni(gm);
       sing_all = uni(sing_all);
     }
+    // convergence history: the maximum violation at iterate it (a restart
+    // from 0 after a fallback overwrites the start's entries)
+    if (A.hist && tid == 0 && (!SPLIT || sp.part == 0) && it < A.hist_len)
+      A.hist[static_cast<int64_t>(report) * A.hist_len + it] = gmax;
     if (A.warm >= 2 && !fell_back) {
       // learned or decoupled start: keep it only while it beats lambda = 0 and the
       // residual does not rise twice in a row; otherwise restart from 0
@@ -1228,6 +1267,7 @@ __global__ void __launch_bounds__(256) small_kernel(const SmallMol* __restrict__
       if (!(rel <= DBL_MAX)) rel = INFINITY;
       if (k < nc) gmax = fmax(gmax, rel);
     }
+    if (A.hist && it < A.hist_len) A.hist[static_cast<int64_t>(M.mol) * A.hist_len + it] = gmax;
     if (A.warm >= 2 && !fell_back) {
       rises = (it > 0 && gmax > prev) ? rises + 1 : 0;
       if ((it == 0 && !(gmax < v0)) || rises >= 2) {
@@ -2181,6 +2221,7 @@ ilves_status_t ilves_plan_destroy(ilves_plan_t P) {
   if (P->d_mlp) (void)hipFree(P->d_mlp);
   if (P->d_feat) (void)hipFree(P->d_feat);
   if (P->d_w) (void)hipFree(P->d_w);
+  (void)hipGetLastError();  // the codes above are ignored: leave no error state behind
   delete P;
   return ILVES_OK;
 }
@@ -2321,8 +2362,13 @@ ilves_status_t run_features(ilves_plan_t P, const double* r, const double* r_u, 
 ilves_status_t solve_impl(ilves_plan_t P, const double* r, const double* r_u, const double* mass, double tol,
                           int32_t precision, int32_t variant, int32_t warm, int32_t max_iter, double* r_out,
                           double* lambda, int32_t* iters, int32_t* status, int32_t* fallback, hipStream_t stream,
-                          int32_t project = 0) {
+                          int32_t project = 0, double* hist = nullptr, int32_t hist_len = 0) {
+  // an error left by an earlier, unrelated runtime call (already returned to
+  // its caller, or ignored) must not be reported as this solve's launch error
+  (void)hipGetLastError();
   SolveArgs A;
+  A.hist = hist_len > 0 ? hist : nullptr;
+  A.hist_len = hist_len > 0 ? hist_len : 0;
   A.r = r;
   A.r_u = r_u;
   A.mass = mass;
@@ -2419,18 +2465,24 @@ extern "C" {
 
 ilves_status_t ilves_solve_ex(ilves_plan_t P, const double* r, const double* r_u, const double* mass, double tol,
                               int32_t precision, int32_t variant, int32_t warm_start, int32_t max_iter,
-                              double* r_out, double* lambda, int32_t* iters, int32_t* status, void* hip_stream) {
+                              double* r_out, double* lambda, int32_t* iters, int32_t* status, double* history,
+                              int32_t history_len, void* hip_stream) {
   ilves_status_t st = check_solve_args(P, r, r_u, mass, tol, precision, variant, r_out, lambda, iters, status);
   if (st != ILVES_OK) return st;
+  if (history_len < 0 || (history_len > 0 && !history)) return fail(ILVES_ERR_ARG, "bad history buffer");
   hipStream_t stream = static_cast<hipStream_t>(hip_stream);
-  if (warm_start == ILVES_WARM_MLP)
-    return ilves_solve_learned(P, r, r_u, mass, tol, precision, variant, max_iter, r_out, lambda, iters, status,
-                               nullptr, hip_stream);
-  if (warm_start != ILVES_WARM_ZERO && warm_start != ILVES_WARM_CALLER && warm_start != ILVES_WARM_DECOUPLED)
+  if (warm_start != ILVES_WARM_ZERO && warm_start != ILVES_WARM_CALLER && warm_start != ILVES_WARM_DECOUPLED &&
+      warm_start != ILVES_WARM_MLP)
     return fail(ILVES_ERR_ARG, "bad warm_start");
-  return solve_impl(P, r, r_u, mass, tol, precision, variant,
-                    warm_start == ILVES_WARM_CALLER ? 1 : warm_start == ILVES_WARM_DECOUPLED ? 3 : 0, max_iter,
-                    r_out, lambda, iters, status, nullptr, stream);
+  if (warm_start == ILVES_WARM_MLP && P->n_con > 0) {
+    st = predict_impl(P, r, r_u, mass, lambda, stream);
+    if (st != ILVES_OK) return st;
+  }
+  const int32_t warm = warm_start == ILVES_WARM_CALLER ? 1
+                       : warm_start == ILVES_WARM_DECOUPLED ? 3
+                       : (warm_start == ILVES_WARM_MLP && P->n_con > 0) ? 2 : 0;
+  return solve_impl(P, r, r_u, mass, tol, precision, variant, warm, max_iter, r_out, lambda, iters, status, nullptr,
+                    stream, 0, history, history_len);
 }
 
 ilves_status_t ilves_solve_learned(ilves_plan_t P, const double* r, const double* r_u, const double* mass, double tol,
@@ -2548,7 +2600,7 @@ ilves_status_t ilves_solve(ilves_plan_t P, const double* r, const double* r_u, c
                            double* r_out, double* lambda, int32_t* iters, int32_t* status, void* hip_stream) {
   if (!P) return fail(ILVES_ERR_ARG, "plan must not be NULL");
   return ilves_solve_ex(P, r, r_u, mass, tol, P->opt.precision, P->opt.variant, P->opt.warm_start,
-                        P->opt.max_iter, r_out, lambda, iters, status, hip_stream);
+                        P->opt.max_iter, r_out, lambda, iters, status, nullptr, 0, hip_stream);
 }
 
 }  // extern "C"

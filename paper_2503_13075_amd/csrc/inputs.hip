@@ -69,12 +69,14 @@ namespace ilves_in {
 hipError_t launch_perturb(const double* r, int32_t n_atoms, double sigma, uint64_t seed, const uint64_t* step,
                           double* r_u, hipStream_t stream) {
   const uint2 key = make_uint2(static_cast<uint32_t>(seed), static_cast<uint32_t>(seed >> 32));
+  (void)hipGetLastError();  // no stale error from an earlier call
   hipLaunchKernelGGL(perturb_kernel, dim3((n_atoms + 255) / 256), dim3(256), 0, stream, r, n_atoms, sigma, key,
                      step, r_u);
   return hipGetLastError();
 }
 
 hipError_t launch_counter_add(uint64_t* counter, uint64_t delta, hipStream_t stream) {
+  (void)hipGetLastError();  // no stale error from an earlier call
   hipLaunchKernelGGL(counter_add_kernel, dim3(1), dim3(64), 0, stream, counter, delta);
   return hipGetLastError();
 }

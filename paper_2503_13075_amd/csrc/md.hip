@@ -47,11 +47,13 @@ namespace ilves_md {
 
 hipError_t launch_kick_drift(const double* r, double* v, const double* f, const double* mass, double h, int32_t n,
                              double* r_u, hipStream_t stream) {
+  (void)hipGetLastError();  // no stale error from an earlier call
   hipLaunchKernelGGL(kick_drift_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, r, v, f, mass, h, n, r_u);
   return hipGetLastError();
 }
 
 hipError_t launch_finish(double* r, const double* r_new, double h, int32_t n, double* v, hipStream_t stream) {
+  (void)hipGetLastError();  // no stale error from an earlier call
   hipLaunchKernelGGL(finish_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, r, r_new, 1.0 / h, n, v);
   return hipGetLastError();
 }

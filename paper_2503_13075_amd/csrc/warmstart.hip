@@ -413,6 +413,7 @@ __global__ void adam_kernel(float* __restrict__ p, const float* __restrict__ g, 
 hipError_t launch_features(const DevPlan& P, const int2* chunks, int32_t n_chunks, bool wide, const double* r,
                            const double* r_u, const double* mass, int32_t n_atoms, unsigned char* ws, float* feat,
                            float* w, hipStream_t stream) {
+  (void)hipGetLastError();  // no stale error from an earlier call
   if (n_chunks <= 0) return hipSuccess;
   if (wide) {
     hipLaunchKernelGGL(features_own_kernel<int32_t>, dim3(n_chunks), dim3(kChunk), 0, stream, P, chunks, r, r_u,
@@ -430,6 +431,7 @@ hipError_t launch_features(const DevPlan& P, const int2* chunks, int32_t n_chunk
 
 hipError_t launch_mlp_infer(const float* params, const float* norm, const float* feat, const float* w,
                             const int32_t* cid, int32_t n_rows, double* lambda, hipStream_t stream) {
+  (void)hipGetLastError();  // no stale error from an earlier call
   if (n_rows <= 0) return hipSuccess;
   const int tiles = (n_rows + 15) / 16;
   const int blocks = (tiles + 3) / 4 < 2048 ? (tiles + 3) / 4 : 2048;
@@ -439,6 +441,7 @@ hipError_t launch_mlp_infer(const float* params, const float* norm, const float*
 }
 
 hipError_t launch_mlp_forward_f32(const float* params, const float* x, int32_t n, float* out, hipStream_t stream) {
+  (void)hipGetLastError();  // no stale error from an earlier call
   if (n <= 0) return hipSuccess;
   const int blocks = (n + TRAIN_BS - 1) / TRAIN_BS;
   hipLaunchKernelGGL(mlp_block_kernel, dim3(blocks), dim3(256), 0, stream, params, x, nullptr, n, 0.0f, nullptr,
@@ -448,6 +451,7 @@ hipError_t launch_mlp_forward_f32(const float* params, const float* x, int32_t n
 
 hipError_t launch_mlp_grad_f32(const float* params, const float* x, const float* y, int32_t n, float* grad,
                                float* loss, float* work, hipStream_t stream) {
+  (void)hipGetLastError();  // no stale error from an earlier call
   if (n <= 0) return hipErrorInvalidValue;
   const int blocks = (n + TRAIN_BS - 1) / TRAIN_BS;
   hipLaunchKernelGGL(mlp_block_kernel, dim3(blocks), dim3(256), 0, stream, params, x, y, n, 1.0f / n, work,
@@ -504,6 +508,7 @@ hipError_t launch_mlp_grad_f32_static(const float* params, const float* x, const
 
 hipError_t launch_mlp_adam(float* params, const float* grad, float* m, float* v, int32_t n, float lr, float beta1,
                            float beta2, float eps, int32_t step, hipStream_t stream) {
+  (void)hipGetLastError();  // no stale error from an earlier call
   if (n <= 0 || step < 1) return hipErrorInvalidValue;
   const float bc1 = 1.0f - powf(beta1, static_cast<float>(step));
   const float bc2 = 1.0f - powf(beta2, static_cast<float>(step));
