@@ -191,10 +191,18 @@ def load(path=DEFAULT_WEIGHTS):
 
 
 def evaluate(seeds, params, norm, precision=L.PREC_MIXED, dev="cuda", tol=1e-12, kind="angles"):
-    """Newton iterations with lambda_0 = 0 vs the learned start on the
-    given seeds (per molecule), fallback rate and convergence."""
+    """Per molecule of the given seeds: Newton iterations from lambda_0 = 0,
+    from the decoupled start (the untrained network's output) and from the
+    network, the fallback rates, convergence, and the error of both starts
+    against the converged multipliers lambda* (FP64 solve to 1e-14):
+    |lambda_0 - lambda*| / |lambda*| over each molecule's constraints (RMS
+    over molecules) and the maximum relative violation at lambda_0."""
     import torch
-    it0, it1, fb, ok0, ok1 = [], [], [], [], []
+    it = {"zero": [], "decoupled": [], "learned": []}
+    ok = {"zero": [], "decoupled": [], "learned": []}
+    fb = {"decoupled": [], "learned": []}
+    err = {"decoupled": [], "learned": []}
+    v0 = {"zero": [], "decoupled": [], "learned": []}
     for seed in seeds:
         sm = make_system(kind, seed)
         ru = perturbed(sm, seed, kind)
@@ -207,26 +215,127 @@ def evaluate(seeds, params, norm, precision=L.PREC_MIXED, dev="cuda", tol=1e-12,
         iters = torch.zeros(nm, dtype=torch.int32, device=dev)
         status = torch.zeros(nm, dtype=torch.int32, device=dev)
         fallback = torch.zeros(nm, dtype=torch.int32, device=dev)
-        plan.solve(r, rut, mass, tol, r_out, lam, iters, status, precision=precision)
+        hist = torch.zeros((nm, 2), dtype=torch.float64, device=dev)
+        # converged multipliers
+        plan.solve(r, rut, mass, 1e-14, r_out, lam, iters, status, precision=L.PREC_FP64, max_iter=30)
         torch.cuda.synchronize()
-        it0.append(iters.cpu().numpy().copy())
-        ok0.append(status.cpu().numpy() == L.OK)
-        plan.solve_learned(r, rut, mass, tol, r_out, lam, iters, status, fallback, precision=precision)
+        lam_star = lam.cpu().numpy().copy()
+        # the two starts themselves
+        lam0 = torch.zeros_like(lam)
+        plan.predict(r, rut, mass, lam0)
         torch.cuda.synchronize()
-        it1.append(iters.cpu().numpy().copy())
-        ok1.append(status.cpu().numpy() == L.OK)
-        fb.append(fallback.cpu().numpy().copy())
+        starts = {"learned": lam0.cpu().numpy().copy()}
+        feat = torch.empty((n, N_FEAT), dtype=torch.float32, device=dev)
+        wf = torch.empty(n, dtype=torch.float32, device=dev)
+        plan.features(r, rut, mass, feat, wf)
+        torch.cuda.synchronize()
+        cid = plan.row_constraints()
+        w64 = 1.0 / sm.mass[sm.pairs[:, 0]] + 1.0 / sm.mass[sm.pairs[:, 1]]
+        dec = np.zeros(n)
+        dec[cid] = feat.cpu().numpy()[:, 0].astype(np.float64)
+        starts["decoupled"] = dec / w64
+        mol = plan.molecules()
+        row = 0
+        for m in range(nm):
+            k = int(mol["n_con"][m])
+            cons = cid[row:row + k]
+            row += k
+            den = np.linalg.norm(lam_star[cons])
+            for name in ("decoupled", "learned"):
+                err[name].append(np.linalg.norm(starts[name][cons] - lam_star[cons]) / max(den, 1e-300))
+        # the solves from each start (with the per-molecule fallback rule)
+        for name, warm in (("zero", L.WARM_ZERO), ("decoupled", L.WARM_DECOUPLED), ("learned", L.WARM_MLP)):
+            fallback.zero_()
+            if name == "learned":
+                plan.solve_learned(r, rut, mass, tol, r_out, lam, iters, status, fallback, precision=precision)
+                plan.solve(r, rut, mass, tol, r_out, lam, iters, status, precision=precision, warm_start=warm,
+                           history=hist)
+            else:
+                plan.solve(r, rut, mass, tol, r_out, lam, iters, status, precision=precision, warm_start=warm,
+                           history=hist)
+            torch.cuda.synchronize()
+            it[name].append(iters.cpu().numpy().copy())
+            ok[name].append(status.cpu().numpy() == L.OK)
+            v0[name].append(hist.cpu().numpy()[:, 0].copy())
+            if name == "learned":
+                fb[name].append(fallback.cpu().numpy().copy())
+            elif name == "decoupled":
+                # the decoupled start falls back where its violation is not below that at 0
+                fb[name].append((v0[name][-1] >= v0["zero"][-1]).astype(np.int32))
         plan.close()
-    it0, it1, fb = np.concatenate(it0), np.concatenate(it1), np.concatenate(fb)
-    return {"molecules": int(it0.size), "iters_zero_mean": float(it0.mean()), "iters_learned_mean": float(it1.mean()),
-            "iters_zero_max": int(it0.max()), "iters_learned_max": int(it1.max()),
-            "fallback_rate": float(fb.mean()), "converged_zero": float(np.concatenate(ok0).mean()),
-            "converged_learned": float(np.concatenate(ok1).mean())}
+    cat = {k: np.concatenate(v) for k, v in it.items()}
+    res = {"molecules": int(cat["zero"].size)}
+    for k in ("zero", "decoupled", "learned"):
+        res[f"iters_{k}_mean"] = float(cat[k].mean())
+        res[f"iters_{k}_max"] = int(cat[k].max())
+        res[f"converged_{k}"] = float(np.concatenate(ok[k]).mean())
+        res[f"violation0_{k}_median"] = float(np.median(np.concatenate(v0[k])))
+    for k in ("decoupled", "learned"):
+        res[f"fallback_rate_{k}"] = float(np.concatenate(fb[k]).mean())
+        e = np.asarray(err[k])
+        res[f"start_error_{k}_rms"] = float(np.sqrt(np.mean(e * e)))
+        res[f"start_error_{k}_median"] = float(np.median(e))
+    res["fallback_rate"] = res["fallback_rate_learned"]
+    return res
+
+
+def heldout_benchmark(seeds, params, norm, kind="angles", steps=20, dev="cuda", log=print):
+    """Constraints solved per second at 1e-12 on the held-out systems
+    concatenated into one system (one solve of all of them), for lambda_0 =
+    0, the decoupled start and the learned start, mixed precision, each
+    step replayed from a captured HIP graph; iterations and fallback too."""
+    import torch
+    systems = [make_system(kind, s) for s in seeds]
+    sm = S.concat(systems, spacing=3.0, name=f"heldout-{kind}")
+    ru = np.concatenate([perturbed(x, s, kind) + (sm.r[o:o + x.n_atoms] - x.r)
+                         for x, s, o in zip(systems, seeds, np.cumsum([0] + [x.n_atoms for x in systems[:-1]]))])
+    plan = L.Plan(sm.n_atoms, sm.pairs, sm.d)
+    plan.load_mlp(params, norm)
+    r, rut, mass = _device_inputs(sm, ru, dev)
+    nm = plan.n_molecules
+    ncon = torch.from_numpy(plan.molecules()["n_con"].astype(np.int64)).to(dev)
+    out = {"systems": len(seeds), "constraints": int(sm.n_constraints), "molecules": int(nm)}
+    for name in ("zero", "decoupled", "learned"):
+        r_out = torch.empty_like(r)
+        lam = torch.zeros(sm.n_constraints, dtype=torch.float64, device=dev)
+        iters = torch.zeros(nm, dtype=torch.int32, device=dev)
+        status = torch.zeros(nm, dtype=torch.int32, device=dev)
+        fallback = torch.zeros(nm, dtype=torch.int32, device=dev)
+
+        def one():
+            if name == "learned":
+                plan.solve_learned(r, rut, mass, 1e-12, r_out, lam, iters, status, fallback, precision=L.PREC_MIXED)
+            else:
+                plan.solve(r, rut, mass, 1e-12, r_out, lam, iters, status, precision=L.PREC_MIXED,
+                           warm_start=L.WARM_DECOUPLED if name == "decoupled" else L.WARM_ZERO)
+        for _ in range(3):
+            one()
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            one()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            g.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        okm = status == L.OK
+        solved = int((okm.to(torch.int64) * ncon).sum().item())
+        out[name] = {"ms_per_solve": ms, "constraints_per_s": solved / (ms / 1e3),
+                     "all_ok": bool(okm.all().item()), "iters_mean": float(iters.double().mean().item()),
+                     "iters_max": int(iters.max().item()),
+                     "fallback_rate": float(fallback.double().mean().item()) if name == "learned" else None}
+        log(f"held-out benchmark {name}: {out[name]}")
+    plan.close()
+    return out
 
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("cmd", choices=["train", "evaluate"])
+    ap.add_argument("cmd", choices=["train", "evaluate", "benchmark"])
     ap.add_argument("--kind", choices=["angles", "trees"], default="angles")
     ap.add_argument("--out", default=None)
     ap.add_argument("--seeds", type=int, default=1000)
@@ -253,14 +362,13 @@ def main(argv=None):
                 "history": hist[-3:], "heldout": res, "sigma_nm": SIGMA[args.kind]}
         save(out, params, norm, meta)
         log(f"saved {out}")
-    else:
+    elif args.cmd == "evaluate":
         params, norm, meta = load(out)
         res = evaluate(range(1000, 1000 + args.eval_seeds), params, norm, kind=args.kind)
-        # ablation: the untrained network (zero output layer) returns the
-        # decoupled solution t0 alone
-        res0 = evaluate(range(1000, 1000 + args.eval_seeds), init_params(0), norm, kind=args.kind)
-        res["iters_decoupled_start_mean"] = res0["iters_learned_mean"]
-        res["fallback_rate_decoupled_start"] = res0["fallback_rate"]
+        log(json.dumps(res))
+    else:
+        params, norm, meta = load(out)
+        res = heldout_benchmark(list(range(1000, 1000 + args.eval_seeds)), params, norm, kind=args.kind, log=log)
         log(json.dumps(res))
 
 
