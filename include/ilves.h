@@ -165,11 +165,14 @@ ilves_status_t ilves_plan_reset_barriers(ilves_plan_t plan);
  *   [11] plan bytes on the device, [12] molecules split across workgroups,
  *   [13] workgroups (parts) of the split molecules, [14] largest separator
  *   (constraints joining the parts of one molecule), [15] split molecules
- *   whose parts keep only their factor values in LDS (FP64).
+ *   whose parts keep only their factor values in LDS (FP64), [16] split
+ *   molecules whose parts keep their factor values and per-row structure in
+ *   LDS and read pair tasks and update lists from global memory (mixed
+ *   precision).
  * Defined by: Supplement section 3 (L(G), ordering, fill of the factors).
  * Errors: ILVES_ERR_ARG (NULL plan or stats).
  */
-#define ILVES_STAT_COUNT 16
+#define ILVES_STAT_COUNT 17
 ilves_status_t ilves_plan_stats(ilves_plan_t plan, int64_t* stats);
 
 /*

@@ -13,7 +13,10 @@ namespace ilves_dev {
 //   STRUCT_LDS: slot structure in LDS, factor values in the workspace
 //   VALUES_LDS: factor values in LDS, slot structure read from global memory
 //   GLOBAL:     both read from global memory (molecules too large for LDS)
-enum { ALL_LDS = 0, STRUCT_LDS = 1, GLOBAL = 2, VALUES_LDS = 3 };
+//   PAIRS_GLOBAL: factor values and the per-row structure (row starts,
+//               upper columns, level headers, lower-slot records) in LDS; the
+//               pair tasks and their update lists read from global memory
+enum { ALL_LDS = 0, STRUCT_LDS = 1, GLOBAL = 2, VALUES_LDS = 3, PAIRS_GLOBAL = 4 };
 
 struct MolDesc {
   int32_t n, s, n_up, n_l, n_upd, n_levels, n_pl;

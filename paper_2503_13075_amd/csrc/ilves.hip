@@ -336,7 +336,7 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(const DevPlan P, const int
   // from global memory, so that several of its records are in flight
   constexpr bool kStructGlobal = MODE == VALUES_LDS || MODE == GLOBAL;
   constexpr int KB = kStructGlobal ? 4 : kBatch;
-  constexpr int KU = kStructGlobal ? 8 : kBatchU;
+  constexpr int KU = (kStructGlobal || MODE == PAIRS_GLOBAL) ? 8 : kBatchU;
   __shared__ double red[BLOCK / 64];
   __shared__ double red0[BLOCK / 64];
   __shared__ int32_t singular;
@@ -368,10 +368,13 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(const DevPlan P, const int
   const Layout Lo = struct_layout(n, H, n_up, n_l, n_pl, n_upd, static_cast<int>(sizeof(Idx)));
   const unsigned char* gst = P.ix + md.ix_off;
   const unsigned char* st;
+  // bytes of the structure block held in LDS (PAIRS_GLOBAL: up to the pair
+  // tasks, rounded up to whole 16-byte copies)
+  const int64_t st_lds = MODE == PAIRS_GLOBAL ? align_to(Lo.prec, 16) : Lo.total;
   if (MODE == GLOBAL || MODE == VALUES_LDS) {
     st = gst;
   } else {
-    const int64_t nvec = Lo.total / 16;  // blocks are 16-byte aligned and padded
+    const int64_t nvec = st_lds / 16;  // blocks are 16-byte aligned and padded
     const int4* gv = reinterpret_cast<const int4*>(gst);
     int4* lv = reinterpret_cast<int4*>(smem);
     // four 16-byte loads in flight per lane before their stores
@@ -392,9 +395,10 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(const DevPlan P, const int
   const Idx* __restrict__ lvh = reinterpret_cast<const Idx*>(st + Lo.lvh);
   // lower-slot records are indexed by the F index t in [n_up, n_up + n_l)
   const Idx* __restrict__ lpair = reinterpret_cast<const Idx*>(st + Lo.lpair) - 2 * static_cast<int64_t>(n_up);
-  const Idx* __restrict__ prec = reinterpret_cast<const Idx*>(st + Lo.prec);
-  const Idx* __restrict__ upd = reinterpret_cast<const Idx*>(st + Lo.upd);
-  const Idx* __restrict__ updi = reinterpret_cast<const Idx*>(st + Lo.updi);
+  const unsigned char* stp = MODE == PAIRS_GLOBAL ? gst : st;  // pair tasks and updates
+  const Idx* __restrict__ prec = reinterpret_cast<const Idx*>(stp + Lo.prec);
+  const Idx* __restrict__ upd = reinterpret_cast<const Idx*>(stp + Lo.upd);
+  const Idx* __restrict__ updi = reinterpret_cast<const Idx*>(stp + Lo.updi);
 
   // ---- workspace and values
   unsigned char* wsb = A.ws + md.ws_off;
@@ -404,6 +408,7 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(const DevPlan P, const int
   double* __restrict__ invm = cf + n_up + n_l;
   T* __restrict__ F;
   if (MODE == ALL_LDS) F = reinterpret_cast<T*>(smem + Lo.total);
+  else if (MODE == PAIRS_GLOBAL) F = reinterpret_cast<T*>(smem + st_lds);
   else if (MODE == VALUES_LDS) F = reinterpret_cast<T*>(smem);
   else F = reinterpret_cast<T*>(wsb + ws_vec_bytes(n, s, n_up, n_l));
   T* __restrict__ D = F + n_up + n_l;
@@ -1401,12 +1406,15 @@ KernelFn pick_kernel(bool fp32, int mode, bool wide, int block, bool heavy = fal
 }
 
 // parts of split molecules (16-bit indices): structure and values in LDS,
-// or the values only
+// the values and the per-row structure, or the values only
 constexpr int kSplitBlock = 512;
 KernelFn pick_split(bool fp32, int mode) {
   if (mode == ALL_LDS)
     return fp32 ? solve_kernel<float, uint16_t, ALL_LDS, kSplitBlock, true>
                 : solve_kernel<double, uint16_t, ALL_LDS, kSplitBlock, true>;
+  if (mode == PAIRS_GLOBAL)
+    return fp32 ? solve_kernel<float, uint16_t, PAIRS_GLOBAL, kSplitBlock, true, kBatchNWide>
+                : solve_kernel<double, uint16_t, PAIRS_GLOBAL, kSplitBlock, true, kBatchNWide>;
   return fp32 ? solve_kernel<float, uint16_t, VALUES_LDS, kSplitBlock, true, kBatchNWide>
               : solve_kernel<double, uint16_t, VALUES_LDS, kSplitBlock, true, kBatchNWide>;
 }
@@ -1465,7 +1473,7 @@ struct ilves_plan {
   std::vector<int32_t> split_first;      // first part (device part index) of each
   std::vector<int64_t> split_xch;        // workspace byte offset of each one's exchange area
   std::vector<int> split_lds[2];         // per part: dynamic LDS bytes
-  std::vector<int> split_mode[2];        // per split molecule: ALL_LDS or VALUES_LDS
+  std::vector<int> split_mode[2];        // per split molecule: ALL_LDS, PAIRS_GLOBAL or VALUES_LDS
   std::vector<SplitLaunch> split_launch[2];
   int32_t chunk_first[2] = {0, 0};     // row chunks of the feature passes, by index width
   int32_t chunk_count[2] = {0, 0};
@@ -1711,18 +1719,20 @@ ilves_status_t build_device_plan(ilves_plan* P) {
       P->split_first.push_back(static_cast<int32_t>(sparts.size()));
       P->split_xch.push_back(xch);
       // placement per precision: structure and values in LDS when every part
-      // fits, else the values only
+      // fits, else the values with the per-row structure (pair tasks and
+      // updates read from global memory), else the values only
       for (int prec = 0; prec < 2; ++prec) {
-        bool all = true;
+        bool all = true, rows = true;
         for (int32_t g = 0; g < G; ++g) {
           const ilves::MolPlan& M = SPL.parts[g];
-          const int64_t sb = struct_layout(M.n, M.n_levels, M.n_up, M.n_l, static_cast<int32_t>(M.plist.size()),
-                                           M.n_upd, 2).total;
+          const Layout Lo = struct_layout(M.n, M.n_levels, M.n_up, M.n_l, static_cast<int32_t>(M.plist.size()),
+                                          M.n_upd, 2);
           const int64_t vb = prec == 0 ? value_bytes<double>(M.n, M.n_up, M.n_l) : value_bytes<float>(M.n, M.n_up, M.n_l);
-          if (static_cast<int64_t>(align16(sb + vb)) + split_lds_bytes(m, M.n - M.n_int, ew_total, n_sadj) > kLdsMax)
-            all = false;
+          const int64_t scr = split_lds_bytes(m, M.n - M.n_int, ew_total, n_sadj);
+          if (static_cast<int64_t>(align16(Lo.total + vb)) + scr > kLdsMax) all = false;
+          if (static_cast<int64_t>(align16(align_to(Lo.prec, 16) + vb)) + scr > kLdsMax) rows = false;
         }
-        P->split_mode[prec].push_back(all ? ALL_LDS : VALUES_LDS);
+        P->split_mode[prec].push_back(all ? ALL_LDS : rows ? PAIRS_GLOBAL : VALUES_LDS);
       }
       for (int32_t g = 0; g < G; ++g) {
         const ilves::MolPlan& M = SPL.parts[g];
@@ -1757,13 +1767,16 @@ ilves_status_t build_device_plan(ilves_plan* P) {
         X.ew_total = ew_total;
         X.n_sadj = n_sadj;
         X.bw = SPL.bw;
-        // LDS: structure and values (ALL_LDS) then the split scratch
-        const int64_t sb = struct_layout(M.n, M.n_levels, M.n_up, M.n_l, static_cast<int32_t>(M.plist.size()),
-                                         M.n_upd, 2).total;
+        // LDS: the structure block (ALL_LDS) or its per-row part
+        // (PAIRS_GLOBAL), then the values, then the split scratch
+        const Layout Lo = struct_layout(M.n, M.n_levels, M.n_up, M.n_l, static_cast<int32_t>(M.plist.size()),
+                                        M.n_upd, 2);
         for (int prec = 0; prec < 2; ++prec) {
           const int64_t vb = prec == 0 ? value_bytes<double>(M.n, M.n_up, M.n_l) : value_bytes<float>(M.n, M.n_up, M.n_l);
-          const int64_t base = P->split_mode[prec].back() == ALL_LDS ? static_cast<int64_t>(align16(sb + vb))
-                                                                     : static_cast<int64_t>(align16(vb));
+          const int mode = P->split_mode[prec].back();
+          const int64_t base = mode == ALL_LDS        ? static_cast<int64_t>(align16(Lo.total + vb))
+                               : mode == PAIRS_GLOBAL ? static_cast<int64_t>(align16(align_to(Lo.prec, 16) + vb))
+                                                      : static_cast<int64_t>(align16(vb));
           X.lds_extra[prec] = static_cast<int32_t>(base);
           P->split_lds[prec].push_back(static_cast<int>(base + split_lds_bytes(m, nbg, ew_total, n_sadj)));
         }
@@ -2011,6 +2024,7 @@ ilves_status_t build_device_plan(ilves_plan* P) {
   P->stats[13] = n_parts;
   P->stats[14] = max_sep;
   P->stats[15] = std::count(P->split_mode[0].begin(), P->split_mode[0].end(), static_cast<int>(VALUES_LDS));
+  P->stats[16] = std::count(P->split_mode[1].begin(), P->split_mode[1].end(), static_cast<int>(PAIRS_GLOBAL));
   return ILVES_OK;
 }
 
@@ -2042,7 +2056,7 @@ ilves_status_t finalize_groups(ilves_plan* P) {
   for (int prec = 0; prec < 2; ++prec) {
     P->split_launch[prec].clear();
     if (P->splits.empty()) continue;
-    for (int mode : {ALL_LDS, VALUES_LDS}) {
+    for (int mode : {ALL_LDS, PAIRS_GLOBAL, VALUES_LDS}) {
     const void* k = reinterpret_cast<const void*>(pick_split(prec == 1, mode));
     HIP_TRY(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsMax));
     auto capacity = [&](int lds, int64_t& cap) -> ilves_status_t {

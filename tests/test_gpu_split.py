@@ -202,19 +202,20 @@ def test_mixed_system_with_split_molecules():
 
 def test_split_with_values_only_in_lds():
     """Angle-constrained protein whose parts' update lists do not fit in
-    LDS next to their factor values: the parts keep only the values in LDS
-    and read their structure through L2; FP64 and mixed against the
-    oracle."""
+    LDS next to their factor values: in FP64 the parts keep only the values
+    in LDS and read their structure through L2; with the FP32 factor they
+    keep the values and the per-row structure in LDS and read only the pair
+    tasks and update lists from global memory; both against the oracle."""
     print("== split values-only placement", flush=True)
     sm = S.add_h_angles(S.protein(80, seed=9))
     ru = S.perturb(sm.r, 0.004, 5)
     ref = _oracle(sm, ru)
     for prec in (L.PREC_FP64, L.PREC_MIXED):
-        out = solve_once(sm, ru, TOL, prec, L.VARIANT_NEWTON, split_rows=1000, split_part_rows=512)
+        out = solve_once(sm, ru, TOL, prec, L.VARIANT_NEWTON, split_rows=1000, split_part_rows=1000)
         st = out["plan"].stats()
         print(f"   {sm.n_constraints} constraints, parts {st['split_parts']}, separator {st['max_separator']}, "
-              f"values-only {st['split_values_lds']}", flush=True)
-        assert st["split_molecules"] == 1 and st["split_values_lds"] == 1, st
+              f"values-only {st['split_values_lds']}, pairs-global {st['split_pairs_global']}", flush=True)
+        assert st["split_molecules"] == 1 and st["split_values_lds"] == 1 and st["split_pairs_global"] == 1, st
         _check(sm, out, ref, f"h-angle protein values-only/{prec}")
 
 
