@@ -33,8 +33,15 @@ def plan_key(plan: L.Plan, precision: int, variant: int, warm: str = "zero") -> 
 
 
 def _timer(run, reps):
+    """Best of two rounds of ``reps`` replays of a HIP graph capturing one
+    ``run()`` (the way a tuned solve is then used: eager launches add host
+    overhead that shifts the optimum), in ms per run."""
     import torch
     run()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        run()
     torch.cuda.synchronize()
     a = torch.cuda.Event(enable_timing=True)
     b = torch.cuda.Event(enable_timing=True)
@@ -42,17 +49,18 @@ def _timer(run, reps):
     for _ in range(2):
         a.record()
         for _ in range(reps):
-            run()
+            g.replay()
         b.record()
         b.synchronize()
         best = min(best, a.elapsed_time(b) / reps)
+    del g
     return best
 
 
 def autotune(plan: L.Plan, run, reps: int = 10, log=None, passes: int = 3) -> dict:
     """Coordinate descent over the plan's tuning.  ``run()`` enqueues one
-    solve on torch's current stream with the plan; it is timed ``reps`` times
-    per candidate (best of two rounds).  A pass tries every LDS limit, then
+    solve on torch's current stream with the plan; it is captured in a HIP
+    graph per candidate and replayed ``reps`` times (best of two rounds).  A pass tries every LDS limit, then
     every block size band by band, keeping a change when it saves more than
     1%; passes repeat (the best block sizes depend on which molecules the
     LDS limit keeps in LDS, and back) until one brings no gain.  Leaves the
