@@ -213,7 +213,9 @@ def main():
                          "in --tuning-store")
     ap.add_argument("--tuning-store", default=AT_DEFAULT_STORE,
                     help="file that receives tunings found by autotuning (the recorded file is left unchanged)")
-    ap.add_argument("--retune", action="store_true", help="autotune even when the tuning file has an entry")
+    ap.add_argument("--retune", action="store_true",
+                    help="autotune even when the tuning file has an entry (the entry seeds the search); the result "
+                         "goes to --tuning-store")
     ap.add_argument("--rng-steps", type=int, default=1000,
                     help="also replay a graph of [device Philox inputs, solve, step += 1] this many times (0: skip)")
     ap.add_argument("--calibrate-copy", type=int, default=0,
@@ -418,7 +420,10 @@ def main():
         run_one = lambda: plan.solve(r, pool[0], mass, 1e-12, r_out, lam, it, stt, precision=prec,  # noqa: E731
                                      warm_start=warm, variant=variant)
         if args.retune:
-            t = dict(AT.autotune(plan, run_one, reps=10), cached=False)
+            hit = AT.load_cached(key, args.tuning_file)
+            t = AT.autotune(plan, run_one, reps=10, seeds=[hit] if hit else [])
+            AT.store(key, t, args.tuning_store)
+            t = dict(t, cached=False)
         else:
             t = AT.tuned(plan, run_one, key, path=args.tuning_file, reps=10,
                          store_path=args.tuning_store)

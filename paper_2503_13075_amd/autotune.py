@@ -17,6 +17,7 @@ import os
 
 from . import _lib as L
 
+DEFAULT_TUNING = {"band_block": [64, 128, 256, 512, 1024], "lds_limit": 0}   # a new plan's launch
 BAND_CANDIDATES = [[64, 128, 256, 512, 1024]] * 3 + [[256, 512, 1024]] * 2
 LDS_CANDIDATES = [0, 120 * 1024, 112 * 1024, 96 * 1024, 80 * 1024, 64 * 1024, 48 * 1024, 32 * 1024]
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "ilves_tuning.json")
@@ -57,21 +58,32 @@ def _timer(run, reps):
     return best
 
 
-def autotune(plan: L.Plan, run, reps: int = 10, log=None, passes: int = 3) -> dict:
+def autotune(plan: L.Plan, run, reps: int = 10, log=None, passes: int = 3, seeds=()) -> dict:
     """Coordinate descent over the plan's tuning.  ``run()`` enqueues one
     solve on torch's current stream with the plan; it is captured in a HIP
-    graph per candidate and replayed ``reps`` times (best of two rounds).  A pass tries every LDS limit, then
+    graph per candidate and replayed ``reps`` times (best of two rounds).
+    The descent starts from the fastest of the default tuning and
+    ``seeds`` (tunings found before, e.g. a recorded entry: coordinate
+    descent stops in local optima, so a retune seeded with the known point
+    can only keep or improve it).  A pass tries every LDS limit, then
     every block size band by band, keeping a change when it saves more than
     1%; passes repeat (the best block sizes depend on which molecules the
     LDS limit keeps in LDS, and back) until one brings no gain.  Leaves the
     plan on the fastest tuning and returns it with the default and tuned
     times (ms)."""
-    cur = plan.get_tuning()
-    cur = {"band_block": list(cur["band_block"]), "lds_limit": 0}
+    cur = {"band_block": list(DEFAULT_TUNING["band_block"]), "lds_limit": DEFAULT_TUNING["lds_limit"]}
     plan.tune(**cur)
     base = best = _timer(run, reps)
     if log:
         log(f"autotune: default {cur} {base:.4f} ms")
+    for sd in seeds:
+        trial = {"band_block": list(sd["band_block"]), "lds_limit": int(sd["lds_limit"])}
+        plan.tune(**trial)
+        t = _timer(run, reps)
+        if log:
+            log(f"autotune: seed {trial} {t:.4f} ms")
+        if t < best:
+            best, cur = t, trial
 
     def consider(trial, what):
         nonlocal best, cur

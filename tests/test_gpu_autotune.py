@@ -43,6 +43,10 @@ def test_autotune_keeps_parity(tmp_path):
     assert plan.get_tuning()["band_block"] == res["band_block"]
     again = AT.tuned(plan, run, key, path=path)
     assert again["cached"] and again["band_block"] == res["band_block"]
+    seeded = AT.autotune(plan, run, reps=3, passes=1,
+                         seeds=[{"band_block": [1024, 1024, 1024, 512, 1024], "lds_limit": 32 * 1024}])
+    print("seeded autotune:", seeded, flush=True)
+    assert plan.get_tuning()["band_block"] == seeded["band_block"]
     out = solve_once(sm, ru, 1e-12, L.PREC_MIXED, plan=plan)
     ref = O.solve(sm.pairs, sm.d, sm.mass, sm.r, ru, tol=1e-15, until_stagnation=True, max_iter=40)
     assert np.all(out["status"] == L.OK)
