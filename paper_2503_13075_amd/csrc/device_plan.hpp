@@ -35,12 +35,20 @@ struct MolDesc {
 //   up_start[n+1], l_start[n+1], ucol[n_up]          per row / upper slot
 //   lvh[H]      level header {first row, end row, first pair task, end}
 //   lpair[n_l]  lower slot t: {column i, slot of the transpose (i, k)}
+//   ccode[n_up + n_l]  one byte per slot (F index): coupling code, see
+//               kFillCode
 //   prec[n_pl]  pair task: {upper slot q, slot of (m, j), first update, count}
 //   upd[n_upd]  update: {slot (j,i), slot (m,i), slot (i,m), slot (i,j)}
 //   updi[n_upd] row i of the update
 struct Layout {
-  int64_t up_start, l_start, ucol, lvh, lpair, prec, upd, updi, total;
+  int64_t up_start, l_start, ucol, lvh, lpair, ccode, prec, upd, updi, total;
 };
+
+// Coupling code of the slot (k, j): C_kj = sign / m_x, x the atom that
+// constraints k and j share, which is one of k's two atoms.  Bit 1: x is
+// b_k (else a_k); bit 0: negative sign; kFillCode: a fill entry of the
+// factor (k and j share no atom, C_kj = 0).
+constexpr uint8_t kFillCode = 4;
 
 __host__ __device__ inline int64_t align_to(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
 
@@ -52,7 +60,8 @@ __host__ __device__ inline Layout struct_layout(int32_t n, int32_t H, int32_t n_
   L.ucol = L.l_start + static_cast<int64_t>(isz) * (n + 1);
   L.lvh = align_to(L.ucol + static_cast<int64_t>(isz) * n_up, 4 * isz);
   L.lpair = L.lvh + static_cast<int64_t>(4 * isz) * H;
-  L.prec = align_to(L.lpair + static_cast<int64_t>(2 * isz) * n_l, 4 * isz);
+  L.ccode = L.lpair + static_cast<int64_t>(2 * isz) * n_l;
+  L.prec = align_to(L.ccode + static_cast<int64_t>(n_up) + n_l, 4 * isz);
   L.upd = L.prec + static_cast<int64_t>(4 * isz) * n_pl;
   L.updi = L.upd + static_cast<int64_t>(4 * isz) * n_upd;
   L.total = align_to(L.updi + static_cast<int64_t>(isz) * n_upd, 16);
@@ -72,7 +81,7 @@ struct DevPlan {
   const int32_t* inc;
   const int32_t* ga;     // per row: input index of atom a_k (same offsets as ra)
   const int32_t* gb;     // per row: input index of atom b_k
-  const int32_t* gcoef;  // per slot: (input index of the shared atom << 1) | (sign < 0), -1 for fill
+  const int32_t* gcoef;  // per slot: (input index of the shared atom << 1) | (sign < 0), -1 for fill (feature passes)
   // molecules split across workgroups (one workgroup per part)
   const struct SplitPart* split;  // per part, in launch order
   const struct SepRow* sep;       // separator rows of every split molecule

@@ -96,10 +96,10 @@ struct SolveArgs {
   int32_t hist_len;
 };
 
-// FP64 workspace of a molecule: per row {e, lambda} (4n) and {u, C_kk} (4n),
-// the couplings of every off-diagonal slot, 1/m (s + 1)
-__host__ __device__ inline size_t ws_vec_bytes(int32_t n, int32_t s, int32_t n_up, int32_t n_l) {
-  return align16(8 * (8 * static_cast<size_t>(n) + n_up + n_l + s + 1));
+// FP64 workspace of a molecule: per row {e, lambda} (4n), {u, C_kk} (4n) and
+// {1/m_a, 1/m_b} (2n), 1/m per atom (s + 1)
+__host__ __device__ inline size_t ws_vec_bytes(int32_t n, int32_t s, int32_t, int32_t) {
+  return align16(8 * (10 * static_cast<size_t>(n) + s + 1));
 }
 // factor values: F (off-diagonal slots), D (diagonal, then 1/U_jj), y
 template <typename T>
@@ -300,6 +300,13 @@ __device__ inline double decoupled_lambda(double u0, double u1, double u2, doubl
   return b != 0.0 ? -c / b : 0.0;
 }
 
+// C_kj of a slot of row k from its coupling code (see kFillCode) and the
+// inverse masses of k's atoms
+__device__ __forceinline__ double coupling(uint32_t code, double ima, double imb) {
+  const double v = (code & 2u) ? imb : ima;
+  return (code & kFillCode) ? 0.0 : ((code & 1u) ? -v : v);
+}
+
 // integer min by value (no reference to a temporary, which would keep
 // small arrays out of registers)
 __device__ __forceinline__ int32_t imin(int32_t a, int32_t b) { return a < b ? a : b; }
@@ -395,6 +402,7 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(const DevPlan P, const int
   const Idx* __restrict__ lvh = reinterpret_cast<const Idx*>(st + Lo.lvh);
   // lower-slot records are indexed by the F index t in [n_up, n_up + n_l)
   const Idx* __restrict__ lpair = reinterpret_cast<const Idx*>(st + Lo.lpair) - 2 * static_cast<int64_t>(n_up);
+  const uint8_t* __restrict__ ccode = reinterpret_cast<const uint8_t*>(st + Lo.ccode);  // per slot (F index)
   const unsigned char* stp = MODE == PAIRS_GLOBAL ? gst : st;  // pair tasks and updates
   const Idx* __restrict__ prec = reinterpret_cast<const Idx*>(stp + Lo.prec);
   const Idx* __restrict__ upd = reinterpret_cast<const Idx*>(stp + Lo.upd);
@@ -404,8 +412,8 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(const DevPlan P, const int
   unsigned char* wsb = A.ws + md.ws_off;
   double* __restrict__ er = reinterpret_cast<double*>(wsb);  // per row {e_x, e_y, e_z, lambda}
   double* __restrict__ uc = er + 4 * static_cast<int64_t>(n);  // per row {u_x, u_y, u_z, C_kk}
-  double* __restrict__ cf = uc + 4 * static_cast<int64_t>(n);
-  double* __restrict__ invm = cf + n_up + n_l;
+  double* __restrict__ im2 = uc + 4 * static_cast<int64_t>(n);  // per row {1/m_a, 1/m_b}
+  double* __restrict__ invm = im2 + 2 * static_cast<int64_t>(n);
   T* __restrict__ F;
   if (MODE == ALL_LDS) F = reinterpret_cast<T*>(smem + Lo.total);
   else if (MODE == PAIRS_GLOBAL) F = reinterpret_cast<T*>(smem + st_lds);
@@ -443,8 +451,9 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(const DevPlan P, const int
   const double* __restrict__ rx = A.r;
   const double* __restrict__ ux = A.r_u;
 
-  // ---- set-up: 1/m, old and unconstrained bond vectors, lambda_0,
-  //      couplings, coordinate magnitude
+  // ---- set-up: 1/m, old and unconstrained bond vectors, lambda_0, the
+  //      inverse masses of each row's atoms (the slot couplings C_kj are
+  //      taken from them and the slot's code), coordinate magnitude
   // (the loops read input atom indices prepared with the plan, so each
   // entry takes one round of gathers)
   double rmax = 0.0;
@@ -508,7 +517,8 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(const DevPlan P, const int
       if (k >= n) break;
       const double a0 = ua[i][0] - ub[i][0], a1 = ua[i][1] - ub[i][1], a2 = ua[i][2] - ub[i][2];
       const double e0 = ra_[i][0] - rb_[i][0], e1 = ra_[i][1] - rb_[i][1], e2 = ra_[i][2] - rb_[i][2];
-      const double cdk = 1.0 / ma[i] + 1.0 / mb[i];
+      const double ima = 1.0 / ma[i], imb = 1.0 / mb[i];
+      const double cdk = ima + imb;
       const double lam0 = A.warm == 3 ? decoupled_lambda(a0, a1, a2, e0, e1, e2, cdk, d2[k])
                                       : (A.warm ? A.lambda[cid[k]] : 0.0);
       st_rec(er + 4 * k, e0, e1, e2, lam0);
@@ -524,26 +534,8 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(const DevPlan P, const int
         }
       }
       st_rec(uc + 4 * k, a0, a1, a2, cdk);
+      *reinterpret_cast<double2*>(im2 + 2 * k) = make_double2(ima, imb);
       v0 = fmax(v0, fabs(a0 * a0 + a1 * a1 + a2 * a2 - d2[k]) / (2.0 * d2[k]));
-    }
-  }
-  // slot couplings, four slots per lane at a time so that their two rounds
-  // of gathers (coupling code, then the shared atom's mass) overlap
-  const int32_t* __restrict__ gcoef = P.gcoef + md.coef_off;
-  const int32_t n_slots = n_up + n_l;
-  for (int32_t q0 = tid; q0 < n_slots; q0 += 4 * BLOCK) {
-    int32_t c[4];
-    double m[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) c[i] = gcoef[imin(q0 + i * BLOCK, n_slots - 1)];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) m[i] = A.mass[c[i] < 0 ? 0 : c[i] >> 1];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      if (q0 + i * BLOCK < n_slots) {
-        const double v = c[i] < 0 ? 0.0 : 1.0 / m[i];
-        cf[q0 + i * BLOCK] = (c[i] & 1) ? -v : v;
-      }
     }
   }
   int32_t adj0 = 0;  // first separator coupling of the molecule
@@ -610,6 +602,7 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(const DevPlan P, const int
   // batch discarded) so that their loads are issued together.
   auto build_row = [&](int32_t k, double px, double py, double pz) {
     const Rec ek = ld_rec(er + 4 * k);
+    const double2 mk = *reinterpret_cast<const double2*>(im2 + 2 * k);
     set_diag(k, static_cast<T>(uc[4 * k + 3] * (px * ek.x + py * ek.y + pz * ek.z)));
     const int32_t q0 = up_start[k], nq = up_start[k + 1] - q0;
     const int32_t t0 = l_start[k], tot = nq + (l_start[k + 1] - t0);
@@ -622,7 +615,7 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(const DevPlan P, const int
         int32_t j;
         slot_of(imin(b + i, tot - 1), q0, nq, t0, sb[i], j);
         nb[i] = ld_rec(er + 4 * j);
-        cb[i] = cf[sb[i]];
+        cb[i] = coupling(ccode[sb[i]], mk.x, mk.y);
       }
 #pragma unroll
       for (int i = 0; i < NB; ++i)
@@ -978,6 +971,7 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(const DevPlan P, const int
     for (int32_t k = tid; k < n; k += BLOCK) {
       const Rec ek = ld_rec(er + 4 * k);
       const Rec uk = ld_rec(uc + 4 * k);
+      const double2 mk = *reinterpret_cast<const double2*>(im2 + 2 * k);
       const double lk = ek.l * uk.l;
       double px = uk.x - lk * ek.x;
       double py = uk.y - lk * ek.y;
@@ -993,7 +987,7 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(const DevPlan P, const int
           int32_t j;
           slot_of(imin(b + i, tot - 1), q0, nq, t0, sb[i], j);
           nb[i] = ld_rec(er + 4 * j);
-          cb[i] = cf[sb[i]];
+          cb[i] = coupling(ccode[sb[i]], mk.x, mk.y);
         }
 #pragma unroll
         for (int i = 0; i < NB; ++i) {
@@ -1508,7 +1502,8 @@ void append(std::vector<V>& dst, const std::vector<int32_t>& src) {
 }
 
 // Appends a molecule's structure block (see struct_layout) to the pool and
-// returns its byte offset.
+// returns its byte offset (-1 if a slot's shared atom is not one of its
+// row's atoms, which a consistent plan never has).
 template <typename Idx>
 int64_t pack_struct(const ilves::MolPlan& M, std::vector<unsigned char>& pool) {
   const int32_t n_pl = static_cast<int32_t>(M.plist.size());
@@ -1534,6 +1529,20 @@ int64_t pack_struct(const ilves::MolPlan& M, std::vector<unsigned char>& pool) {
     put(Lo.lpair, 2 * t + 0, M.lcol[t]);
     put(Lo.lpair, 2 * t + 1, M.ltr[t]);
   }
+  // coupling codes: the shared atom of every slot is one of its row's atoms
+  unsigned char* cc = pool.data() + off + Lo.ccode;
+  bool bad = false;
+  auto code = [&](int32_t k, int32_t c) -> unsigned char {
+    const int32_t x = c >> 1;
+    if (x >= M.s) return kFillCode;
+    if (x != M.ra[k] && x != M.rb[k]) bad = true;
+    return static_cast<unsigned char>((x == M.rb[k] ? 2 : 0) | (c & 1));
+  };
+  for (int32_t k = 0; k < M.n; ++k) {
+    for (int32_t q = M.up_start[k]; q < M.up_start[k + 1]; ++q) cc[q] = code(k, M.ucoef[q]);
+    for (int32_t t = M.l_start[k]; t < M.l_start[k + 1]; ++t) cc[t] = code(k, M.lcoef[t - M.n_up]);
+  }
+  if (bad) return -1;
   for (int32_t pi = 0; pi < n_pl; ++pi) {
     const int32_t q = M.plist[pi];
     put(Lo.prec, 4 * pi + 0, q);
@@ -1598,6 +1607,7 @@ ilves_status_t build_device_plan(ilves_plan* P) {
     wide[i] = (total >= 65535 || M.n >= 65535 || M.n_upd >= 65535) ? 1 : 0;
     D.wide = wide[i];
     D.ix_off = wide[i] ? pack_struct<int32_t>(M, pool) : pack_struct<uint16_t>(M, pool);
+    if (D.ix_off < 0) return fail(ILVES_ERR_TOPOLOGY, "plan: a coupling's shared atom is not an atom of its row");
     D.coef_off = static_cast<int32_t>(coef.size());
     coef.insert(coef.end(), M.ucoef.begin(), M.ucoef.end());
     coef.insert(coef.end(), M.lcoef.begin(), M.lcoef.end());
