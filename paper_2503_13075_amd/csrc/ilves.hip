@@ -355,7 +355,7 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(const DevPlan P, const int
   for (;;) {
   int32_t slot;
   if constexpr (SPLIT) {
-    slot = blockIdx.x;
+    slot = uni(mols[blockIdx.x]);  // the launch's parts
   } else {
     if (tid == 0) next_slot = atomicAdd(counter, 1);
     __syncthreads();
@@ -1434,7 +1434,7 @@ constexpr int kMaxGroups = 64;
 // One launch of split-molecule parts: whole molecules, at most as many
 // parts as can be resident on the device at once (their barriers need it).
 struct SplitLaunch {
-  int32_t first = 0, count = 0;  // parts, in the device part array
+  int32_t first = 0, count = 0;  // parts: a range of the precision's part order (d_split_order)
   int lds_bytes = 0;
   int stream = 0;
   int mode = ALL_LDS;            // placement of every part of the launch
@@ -1469,6 +1469,7 @@ struct ilves_plan {
   std::vector<int> split_lds[2];         // per part: dynamic LDS bytes
   std::vector<int> split_mode[2];        // per split molecule: ALL_LDS, PAIRS_GLOBAL or VALUES_LDS
   std::vector<SplitLaunch> split_launch[2];
+  const int32_t* d_split_order[2] = {nullptr, nullptr};  // per precision: parts grouped by placement
   int32_t chunk_first[2] = {0, 0};     // row chunks of the feature passes, by index width
   int32_t chunk_count[2] = {0, 0};
   const int2* d_chunks = nullptr;      // {molecule, first row} pairs in d_buf
@@ -1983,6 +1984,18 @@ ilves_status_t build_device_plan(ilves_plan* P) {
   const size_t o_extp = push_array(blob, ext_ptr);
   const size_t o_extr = push_array(blob, ext_rec);
   const size_t o_extc = push_array(blob, ext_coef);
+  // per precision: the parts of the split molecules grouped by placement (the
+  // order the split launches take them in, one range per launch, so that
+  // molecules of different placements do not cut a launch into pieces)
+  std::vector<int32_t> split_order[2];
+  for (int prec = 0; prec < 2; ++prec)
+    for (int mode : {ALL_LDS, PAIRS_GLOBAL, VALUES_LDS})
+      for (size_t si = 0; si < P->splits.size(); ++si)
+        if (P->split_mode[prec][si] == mode)
+          for (size_t g = 0; g < P->splits[si].parts.size(); ++g)
+            split_order[prec].push_back(P->split_first[si] + static_cast<int32_t>(g));
+  const size_t o_sord0 = push_array(blob, split_order[0]);
+  const size_t o_sord1 = push_array(blob, split_order[1]);
   blob.resize(blob.size() + 256);
 
   HIP_TRY(hipMalloc(&P->d_buf, blob.size()));
@@ -2006,6 +2019,8 @@ ilves_status_t build_device_plan(ilves_plan* P) {
   P->d_chunks = reinterpret_cast<const int2*>(b + o_chunks);
   P->d_small = reinterpret_cast<const SmallMol*>(b + o_small);
   P->dp.split = reinterpret_cast<const SplitPart*>(b + o_sparts);
+  P->d_split_order[0] = reinterpret_cast<const int32_t*>(b + o_sord0);
+  P->d_split_order[1] = reinterpret_cast<const int32_t*>(b + o_sord1);
   P->dp.sep = reinterpret_cast<const SepRow*>(b + o_seprows);
   P->dp.sadj = reinterpret_cast<const int32_t*>(b + o_sadj);
   P->dp.bsep = reinterpret_cast<const int32_t*>(b + o_bsep);
@@ -2066,6 +2081,7 @@ ilves_status_t finalize_groups(ilves_plan* P) {
   for (int prec = 0; prec < 2; ++prec) {
     P->split_launch[prec].clear();
     if (P->splits.empty()) continue;
+    int32_t pos = 0;  // position in the precision's part order (d_split_order)
     for (int mode : {ALL_LDS, PAIRS_GLOBAL, VALUES_LDS}) {
     const void* k = reinterpret_cast<const void*>(pick_split(prec == 1, mode));
     HIP_TRY(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsMax));
@@ -2080,10 +2096,11 @@ ilves_status_t finalize_groups(ilves_plan* P) {
     cur.mode = mode;
     for (size_t si = 0; si < P->splits.size(); ++si) {
       if (P->split_mode[prec][si] != mode) continue;
-      const int32_t first = P->split_first[si];
+      const int32_t first = pos;
       const int32_t G = static_cast<int32_t>(P->splits[si].parts.size());
+      pos += G;
       int lds = 0;
-      for (int32_t g = 0; g < G; ++g) lds = std::max(lds, P->split_lds[prec][first + g]);
+      for (int32_t g = 0; g < G; ++g) lds = std::max(lds, P->split_lds[prec][P->split_first[si] + g]);
       int64_t cap_alone = 0, cap_joined = 0;
       ilves_status_t st = capacity(lds, cap_alone);
       if (st != ILVES_OK) return st;
@@ -2093,11 +2110,6 @@ ilves_status_t finalize_groups(ilves_plan* P) {
       if (cur.count > 0 && cur.count + G > cap_joined) {
         P->split_launch[prec].push_back(cur);
         cur.first = first;
-        cur.count = 0;
-        cur.lds_bytes = 0;
-      }
-      if (cur.count > 0 && first != cur.first + cur.count) {  // launches cover consecutive parts
-        P->split_launch[prec].push_back(cur);
         cur.count = 0;
         cur.lds_bytes = 0;
       }
@@ -2434,8 +2446,7 @@ ilves_status_t solve_impl(ilves_plan_t P, const double* r, const double* r_u, co
   for (const SplitLaunch& l : P->split_launch[pr]) {
     KernelFn k = pick_split(pr == 1, l.mode);
     DevPlan dp = P->dp;
-    dp.split = P->dp.split + l.first;
-    const int32_t* list = nullptr;
+    const int32_t* list = P->d_split_order[pr] + l.first;
     int32_t count = l.count;
     int32_t* counter = nullptr;
     SolveArgs a = A;

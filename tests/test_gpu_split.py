@@ -219,6 +219,26 @@ def test_split_with_values_only_in_lds():
         _check(sm, out, ref, f"h-angle protein values-only/{prec}")
 
 
+def test_split_molecules_of_different_placements_interleaved():
+    """Three split molecules whose parts take different placements, the one
+    that does not fit in LDS between the two that do: the split launches
+    take the parts grouped by placement (one launch per placement, not one
+    per run of consecutive molecules), and every molecule matches the
+    oracle."""
+    print("== split placements interleaved", flush=True)
+    sm = S.concat([S.protein(120, seed=21), S.add_h_angles(S.protein(80, seed=9)), S.protein(110, seed=22)],
+                  spacing=2.0)
+    ru = S.perturb(sm.r, 0.003, 7)
+    ref = _oracle(sm, ru)
+    for prec in (L.PREC_FP64, L.PREC_MIXED):
+        out = solve_once(sm, ru, TOL, prec, L.VARIANT_NEWTON, split_rows=1000, split_part_rows=1000)
+        st = out["plan"].stats()
+        print(f"   {sm.n_constraints} constraints, split {st['split_molecules']}, parts {st['split_parts']}, "
+              f"values-only {st['split_values_lds']}, pairs-global {st['split_pairs_global']}", flush=True)
+        assert st["split_molecules"] == 3 and st["split_values_lds"] == 1 and st["split_pairs_global"] == 1, st
+        _check(sm, out, ref, f"interleaved placements/{prec}")
+
+
 def test_split_wait_limit_reports_timeout_and_reset_recovers():
     """Failure handling of the split barriers, forced from the host: with a
     wait limit of zero polls a workgroup that has to wait gives up at once,
