@@ -34,6 +34,8 @@ struct MolDesc {
 // byte offsets from the block start (16-byte aligned):
 //   up_start[n+1], l_start[n+1], ucol[n_up]          per row / upper slot
 //   lvh[H]      level header {first row, end row, first pair task, end}
+//   lvc[H]      per level {lg of the factorisation, lg of the backward
+//               substitution}: 2^lg lanes per item (see item_lanes_log2)
 //   lpair[n_l]  lower slot t: {column i, slot of the transpose (i, k)}
 //   ccode[n_up + n_l]  one byte per slot (F index): coupling code, see
 //               kFillCode
@@ -41,8 +43,33 @@ struct MolDesc {
 //   upd[n_upd]  update: {slot (j,i), slot (m,i), slot (i,m), slot (i,j)}
 //   updi[n_upd] row i of the update
 struct Layout {
-  int64_t up_start, l_start, ucol, lvh, lpair, ccode, prec, upd, updi, total;
+  int64_t up_start, l_start, ucol, lvh, lvc, lpair, ccode, prec, upd, updi, total;
 };
+
+// Lanes per item of an elimination level.  Where a level's longest chain
+// (the most lower entries of a row or updates of a pair task in the
+// factorisation, the most upper entries of a row in the backward
+// substitution) is long, G = 2^lg lanes share each item's entries and add
+// their partial sums with lane shuffles: the largest G <= kMaxItemLanes that
+// leaves each lane at least kLaneEntries entries of that chain while the
+// level's items (rows padded to whole waves when pair tasks follow, then
+// pair tasks) fit kItemLaneBudget lanes.  It depends on the plan only, not
+// on the launch tuning, so a tuning never changes the arithmetic.  Only the
+// kernel of the parts of split molecules has the shared-lane path (the long
+// chains are theirs: angle constraints fill the factor); whole molecules
+// always take one lane per item, which keeps that kernel's code lean.
+constexpr int kMaxItemLanes = 16;
+constexpr int kLaneEntries = 4;
+constexpr int kItemLaneBudget = 512;
+__host__ __device__ inline int32_t item_lanes_log2(int32_t chain, int32_t nr, int32_t np, bool pad) {
+  int32_t lg = 0;
+  while ((1 << (lg + 1)) <= kMaxItemLanes && (chain >> (lg + 1)) >= kLaneEntries) {
+    const int32_t nrl = nr << (lg + 1);
+    if ((pad ? (nrl + 63) & ~63 : nrl) + (np << (lg + 1)) > kItemLaneBudget) break;
+    ++lg;
+  }
+  return lg;
+}
 
 // Coupling code of the slot (k, j): C_kj = sign / m_x, x the atom that
 // constraints k and j share, which is one of k's two atoms.  Bit 1: x is
@@ -59,7 +86,8 @@ __host__ __device__ inline Layout struct_layout(int32_t n, int32_t H, int32_t n_
   L.l_start = L.up_start + static_cast<int64_t>(isz) * (n + 1);
   L.ucol = L.l_start + static_cast<int64_t>(isz) * (n + 1);
   L.lvh = align_to(L.ucol + static_cast<int64_t>(isz) * n_up, 4 * isz);
-  L.lpair = L.lvh + static_cast<int64_t>(4 * isz) * H;
+  L.lvc = L.lvh + static_cast<int64_t>(4 * isz) * H;
+  L.lpair = align_to(L.lvc + static_cast<int64_t>(2 * isz) * H, 4 * isz);
   L.ccode = L.lpair + static_cast<int64_t>(2 * isz) * n_l;
   L.prec = align_to(L.ccode + static_cast<int64_t>(n_up) + n_l, 4 * isz);
   L.upd = L.prec + static_cast<int64_t>(4 * isz) * n_pl;

@@ -270,6 +270,7 @@ constexpr int kBatchN = 2;
 constexpr int kBatchNWide = 4;
 constexpr int kBatch = 2;
 constexpr int kBatchU = 1;
+
 // 1/a from the hardware reciprocal refined by Newton steps (one in FP32,
 // two in FP64): a few dependent operations instead of a full division; the
 // result is within an ulp or two, which the factorisation does not notice
@@ -400,6 +401,7 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(const DevPlan P, const int
   const Idx* __restrict__ l_start = reinterpret_cast<const Idx*>(st + Lo.l_start);
   const Idx* __restrict__ ucol = reinterpret_cast<const Idx*>(st + Lo.ucol);
   const Idx* __restrict__ lvh = reinterpret_cast<const Idx*>(st + Lo.lvh);
+  const Idx* __restrict__ lvc = reinterpret_cast<const Idx*>(st + Lo.lvc);
   // lower-slot records are indexed by the F index t in [n_up, n_up + n_l)
   const Idx* __restrict__ lpair = reinterpret_cast<const Idx*>(st + Lo.lpair) - 2 * static_cast<int64_t>(n_up);
   const uint8_t* __restrict__ ccode = reinterpret_cast<const uint8_t*>(st + Lo.ccode);  // per slot (F index)
@@ -624,10 +626,11 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(const DevPlan P, const int
   };
 
   // one elimination level: diagonal entries (forward substitution fused
-  // when FORWARD) and, when FACTOR, the upper entries with updates.  The
-  // entries of an item are taken KB (updates KU) at a time, indices
+  // when FORWARD) and, when FACTOR, the upper entries with updates.  A lane
+  // takes every G-th entry of its item, KB (updates KU) at a time, indices
   // clamped to the last entry and the extra lanes of a batch discarded, so
-  // that the loads of a batch are issued together.
+  // that the loads of a batch are issued together; the G lanes of an item
+  // then add their partial sums.
   auto factor_level = [&](int32_t h, auto factor_tag, auto forward_tag) {
     constexpr bool FACTOR = decltype(factor_tag)::value;
     constexpr bool FORWARD = decltype(forward_tag)::value;
@@ -637,54 +640,144 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(const DevPlan P, const int
     r1 = uni(r1);
     p0 = uni(p0);
     p1 = uni(p1);
+    const int32_t nr = r1 - r0;
+    const int32_t np = FACTOR ? p1 - p0 : 0;
+    const int32_t lg = uni(static_cast<int32_t>(lvc[2 * h]));
     // the row items are padded to a whole number of waves, so that no wave
     // holds both kinds of item: a wave with rows and pair tasks would run the
     // two code paths one after the other
-    const int32_t nr = r1 - r0;
-    const int32_t nrp = FACTOR ? (nr + 63) & ~63 : nr;
-    const int32_t items = nrp + (FACTOR ? p1 - p0 : 0);
-    for (int32_t idx = tid; idx < items; idx += BLOCK) {
-      if (idx < nrp) {
-        if (idx >= nr) continue;
-        const int32_t j = r0 + idx;
-        T acc = D[j], yj = y[j];
-        const T a0 = acc;
-        const int32_t t0 = l_start[j], nt = l_start[j + 1] - t0;
-        for (int32_t b = 0; b < nt; b += KB) {
+    if (!SPLIT || lg == 0) {  // one lane per item (whole molecules: always)
+      const int32_t nrp = FACTOR ? (nr + 63) & ~63 : nr;
+      const int32_t items = nrp + np;
+      for (int32_t idx = tid; idx < items; idx += BLOCK) {
+        if (idx < nrp) {
+          if (idx >= nr) continue;
+          const int32_t j = r0 + idx;
+          T acc = D[j], yj = y[j];
+          const T a0 = acc;
+          const int32_t t0 = l_start[j], nt = l_start[j + 1] - t0;
+          for (int32_t b = 0; b < nt; b += KB) {
+            int32_t ii[KB], ss[KB];
+            T f[KB], di[KB], fs[KB], yi[KB];
+#pragma unroll
+            for (int i = 0; i < KB; ++i) ld2(lpair + 2 * (t0 + imin(b + i, nt - 1)), ii[i], ss[i]);
+#pragma unroll
+            for (int i = 0; i < KB; ++i) {
+              f[i] = F[t0 + imin(b + i, nt - 1)];
+              di[i] = D[ii[i]];
+              if (FACTOR) fs[i] = F[ss[i]];
+              if (FORWARD) yi[i] = y[ii[i]];
+            }
+#pragma unroll
+            for (int i = 0; i < KB; ++i) {
+              if (b + i < nt) {
+                const T l = f[i] * di[i];
+                if (FACTOR) acc -= l * fs[i];
+                if (FORWARD) yj -= l * yi[i];
+              }
+            }
+          }
+          if (FACTOR) {
+            if (!(fabs(acc) > pivot_eps<T>() * fabs(a0))) singular = 1;
+            D[j] = recip(acc);
+          }
+          if (FORWARD) y[j] = yj;
+        } else if (FACTOR) {
+          int32_t q, tr, u0, nu;
+          ld4(prec + 4 * (p0 + idx - nrp), q, tr, u0, nu);
+          T au = F[q], aw = F[tr];
+          for (int32_t b = 0; b < nu; b += KU) {
+            int32_t pa[KU], pb[KU], s1[KU], s2[KU], ui[KU];
+#pragma unroll
+            for (int i = 0; i < KU; ++i) {
+              const int32_t u = u0 + imin(b + i, nu - 1);
+              ld4(upd + 4 * u, pa[i], pb[i], s1[i], s2[i]);
+              ui[i] = updi[u];
+            }
+            T fa[KU], fb[KU], f1[KU], f2[KU], di[KU];
+#pragma unroll
+            for (int i = 0; i < KU; ++i) {
+              fa[i] = F[pa[i]];
+              fb[i] = F[pb[i]];
+              f1[i] = F[s1[i]];
+              f2[i] = F[s2[i]];
+              di[i] = D[ui[i]];
+            }
+#pragma unroll
+            for (int i = 0; i < KU; ++i) {
+              if (b + i < nu) {
+                au -= fa[i] * di[i] * f1[i];
+                aw -= fb[i] * di[i] * f2[i];
+              }
+            }
+          }
+          F[q] = au;
+          F[tr] = aw;
+        }
+      }
+      return;
+    }
+    const int32_t G = 1 << lg;
+    const int32_t nrl = nr << lg;
+    const int32_t nrp = FACTOR ? (nrl + 63) & ~63 : nrl;
+    const int32_t lanes = nrp + (np << lg);
+    // whole waves per pass, so that every lane of a wave takes part in the
+    // shuffles of its items
+    for (int32_t base = tid & ~63; base < lanes; base += BLOCK) {
+      const int32_t idx = base + (tid & 63);
+      const int32_t sub = idx & (G - 1);
+      if (base < nrp) {
+        const bool valid = idx < nrl;
+        const int32_t j = r0 + (valid ? idx >> lg : 0);
+        const T a0 = D[j], y0 = y[j];  // loaded with the item's first records
+        const int32_t t0 = l_start[j], nt = valid ? l_start[j + 1] - t0 : 0;
+        T sf = T(0), sy = T(0);
+        for (int32_t b = sub; b < nt; b += KB * G) {
           int32_t ii[KB], ss[KB];
           T f[KB], di[KB], fs[KB], yi[KB];
 #pragma unroll
-          for (int i = 0; i < KB; ++i) ld2(lpair + 2 * (t0 + imin(b + i, nt - 1)), ii[i], ss[i]);
+          for (int i = 0; i < KB; ++i) ld2(lpair + 2 * (t0 + imin(b + i * G, nt - 1)), ii[i], ss[i]);
 #pragma unroll
           for (int i = 0; i < KB; ++i) {
-            f[i] = F[t0 + imin(b + i, nt - 1)];
+            f[i] = F[t0 + imin(b + i * G, nt - 1)];
             di[i] = D[ii[i]];
             if (FACTOR) fs[i] = F[ss[i]];
             if (FORWARD) yi[i] = y[ii[i]];
           }
 #pragma unroll
           for (int i = 0; i < KB; ++i) {
-            if (b + i < nt) {
+            if (b + i * G < nt) {
               const T l = f[i] * di[i];
-              if (FACTOR) acc -= l * fs[i];
-              if (FORWARD) yj -= l * yi[i];
+              if (FACTOR) sf += l * fs[i];
+              if (FORWARD) sy += l * yi[i];
             }
           }
         }
-        if (FACTOR) {
-          if (!(fabs(acc) > pivot_eps<T>() * fabs(a0))) singular = 1;
-          D[j] = recip(acc);
+        for (int32_t o = G >> 1; o > 0; o >>= 1) {
+          if (FACTOR) sf += __shfl_xor(sf, o, 64);
+          if (FORWARD) sy += __shfl_xor(sy, o, 64);
         }
-        if (FORWARD) y[j] = yj;
+        if (valid && sub == 0) {
+          if (FACTOR) {
+            const T acc = a0 - sf;
+            if (!(fabs(acc) > pivot_eps<T>() * fabs(a0))) singular = 1;
+            D[j] = recip(acc);
+          }
+          if (FORWARD) y[j] = y0 - sy;
+        }
       } else if (FACTOR) {
+        const int32_t pl = idx - nrp;
+        const bool valid = pl < (np << lg);
         int32_t q, tr, u0, nu;
-        ld4(prec + 4 * (p0 + idx - nrp), q, tr, u0, nu);
-        T au = F[q], aw = F[tr];
-        for (int32_t b = 0; b < nu; b += KU) {
+        ld4(prec + 4 * (p0 + (valid ? pl >> lg : 0)), q, tr, u0, nu);
+        if (!valid) nu = 0;
+        const T au = F[q], aw = F[tr];
+        T sa = T(0), sw = T(0);
+        for (int32_t b = sub; b < nu; b += KU * G) {
           int32_t pa[KU], pb[KU], s1[KU], s2[KU], ui[KU];
 #pragma unroll
           for (int i = 0; i < KU; ++i) {
-            const int32_t u = u0 + imin(b + i, nu - 1);
+            const int32_t u = u0 + imin(b + i * G, nu - 1);
             ld4(upd + 4 * u, pa[i], pb[i], s1[i], s2[i]);
             ui[i] = updi[u];
           }
@@ -699,14 +792,20 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(const DevPlan P, const int
           }
 #pragma unroll
           for (int i = 0; i < KU; ++i) {
-            if (b + i < nu) {
-              au -= fa[i] * di[i] * f1[i];
-              aw -= fb[i] * di[i] * f2[i];
+            if (b + i * G < nu) {
+              sa += fa[i] * di[i] * f1[i];
+              sw += fb[i] * di[i] * f2[i];
             }
           }
         }
-        F[q] = au;
-        F[tr] = aw;
+        for (int32_t o = G >> 1; o > 0; o >>= 1) {
+          sa += __shfl_xor(sa, o, 64);
+          sw += __shfl_xor(sw, o, 64);
+        }
+        if (valid && sub == 0) {
+          F[q] = au - sa;
+          F[tr] = aw - sw;
+        }
       }
     }
   };
@@ -716,29 +815,63 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(const DevPlan P, const int
       __syncthreads();
     }
   };
-  // backward substitution, levels h_top-1 .. 0
+  // backward substitution, levels h_top-1 .. 0 (G lanes per row as in the
+  // factorisation, from the level's longest row of upper entries)
   auto back_sweep = [&](int32_t h_top) {
     for (int32_t h = h_top - 1; h >= 0; --h) {
       const int32_t k0 = uni(static_cast<int32_t>(lvh[4 * h])), k1 = uni(static_cast<int32_t>(lvh[4 * h + 1]));
-      for (int32_t k = k0 + tid; k < k1; k += BLOCK) {
-        T acc = y[k];
-        const T dk = D[k];
-        const int32_t q0 = up_start[k], nq = up_start[k + 1] - q0;
-        for (int32_t b = 0; b < nq; b += KB) {
+      const int32_t nr = k1 - k0;
+      const int32_t lg = uni(static_cast<int32_t>(lvc[2 * h + 1]));
+      if (!SPLIT || lg == 0) {  // one lane per row (whole molecules: always)
+        for (int32_t k = k0 + tid; k < k1; k += BLOCK) {
+          T acc = y[k];
+          const T dk = D[k];
+          const int32_t q0 = up_start[k], nq = up_start[k + 1] - q0;
+          for (int32_t b = 0; b < nq; b += KB) {
+            int32_t c[KB];
+            T f[KB], yc[KB];
+#pragma unroll
+            for (int i = 0; i < KB; ++i) c[i] = ucol[q0 + imin(b + i, nq - 1)];
+#pragma unroll
+            for (int i = 0; i < KB; ++i) {
+              f[i] = F[q0 + imin(b + i, nq - 1)];
+              yc[i] = y[c[i]];
+            }
+#pragma unroll
+            for (int i = 0; i < KB; ++i)
+              if (b + i < nq) acc -= f[i] * yc[i];
+          }
+          y[k] = acc * dk;
+        }
+        __syncthreads();
+        continue;
+      }
+      const int32_t G = 1 << lg;
+      const int32_t nrl = nr << lg;
+      for (int32_t base = tid & ~63; base < nrl; base += BLOCK) {
+        const int32_t idx = base + (tid & 63);
+        const int32_t sub = idx & (G - 1);
+        const bool valid = idx < nrl;
+        const int32_t k = k0 + (valid ? idx >> lg : 0);
+        const T yk = y[k], dk = D[k];
+        const int32_t q0 = up_start[k], nq = valid ? up_start[k + 1] - q0 : 0;
+        T sacc = T(0);
+        for (int32_t b = sub; b < nq; b += KB * G) {
           int32_t c[KB];
           T f[KB], yc[KB];
 #pragma unroll
-          for (int i = 0; i < KB; ++i) c[i] = ucol[q0 + imin(b + i, nq - 1)];
+          for (int i = 0; i < KB; ++i) c[i] = ucol[q0 + imin(b + i * G, nq - 1)];
 #pragma unroll
           for (int i = 0; i < KB; ++i) {
-            f[i] = F[q0 + imin(b + i, nq - 1)];
+            f[i] = F[q0 + imin(b + i * G, nq - 1)];
             yc[i] = y[c[i]];
           }
 #pragma unroll
           for (int i = 0; i < KB; ++i)
-            if (b + i < nq) acc -= f[i] * yc[i];
+            if (b + i * G < nq) sacc += f[i] * yc[i];
         }
-        y[k] = acc * dk;
+        for (int32_t o = G >> 1; o > 0; o >>= 1) sacc += __shfl_xor(sacc, o, 64);
+        if (valid && sub == 0) y[k] = (yk - sacc) * dk;
       }
       __syncthreads();
     }
@@ -1525,6 +1658,18 @@ int64_t pack_struct(const ilves::MolPlan& M, std::vector<unsigned char>& pool) {
     put(Lo.lvh, 4 * h + 1, M.lvl_row[h + 1]);
     put(Lo.lvh, 4 * h + 2, M.pl_start[h]);
     put(Lo.lvh, 4 * h + 3, M.pl_start[h + 1]);
+  }
+  for (int32_t h = 0; h < M.n_levels; ++h) {
+    int32_t cf = 0, cb = 0;
+    for (int32_t j = M.lvl_row[h]; j < M.lvl_row[h + 1]; ++j) {
+      cf = std::max(cf, M.l_start[j + 1] - M.l_start[j]);
+      cb = std::max(cb, M.up_start[j + 1] - M.up_start[j]);
+    }
+    for (int32_t pi = M.pl_start[h]; pi < M.pl_start[h + 1]; ++pi)
+      cf = std::max(cf, M.ustart[M.plist[pi] + 1] - M.ustart[M.plist[pi]]);
+    const int32_t nr = M.lvl_row[h + 1] - M.lvl_row[h], np = M.pl_start[h + 1] - M.pl_start[h];
+    put(Lo.lvc, 2 * h + 0, item_lanes_log2(cf, nr, np, true));
+    put(Lo.lvc, 2 * h + 1, item_lanes_log2(cb, nr, 0, false));
   }
   for (int32_t t = 0; t < M.n_l; ++t) {
     put(Lo.lpair, 2 * t + 0, M.lcol[t]);
