@@ -10,7 +10,10 @@
 // the small dense separator system is solved, and every part finishes its
 // backward substitution from the separator solution.  It exists so that the
 // planner (ordering, symbolic factorisation, slot links, splits) can be
-// tested without a GPU; the solve entry points never call it.
+// tested without a GPU; the solve entry points never call it.  The sums of
+// an item run in entry order here; in the levels where the device shares an
+// item over several lanes (parts of split molecules with long chains) it
+// adds per-lane partial sums instead, so the two agree to rounding there.
 #include <algorithm>
 #include <cfloat>
 #include <cmath>
