@@ -440,7 +440,7 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(const DevPlan P, const int
   double* Ab = gB + nb;
   double* Lb = Ab + nb * nb;
   double* Ub = Lb + nb * nb;
-  double* amax = Ub + nb * nb;  // row maxima of the separator matrix
+  double* amax = Ub + nb * nb;  // row maxima of the separator matrix, then 1/pivot per row
   double* xs = amax + ms;       // copy of SepX[ms] (8 doubles each) then the E/w blocks
   const int32_t ew_total = SPLIT ? sp.ew_total : 0;
   SepRow* srow = reinterpret_cast<SepRow*>(xs + 8 * ms + ew_total);
@@ -987,6 +987,11 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(const DevPlan P, const int
     }
     __syncthreads();
     if (tid < 64) {
+      // a step's entries (row r, column cc) sit at lane r * W + cc, W the
+      // power of two >= bw + 1 (at most bw columns and the right-hand side)
+      int32_t lw = 0;
+      while ((1 << lw) < bw + 1) ++lw;
+      const int32_t W = 1 << lw;
       int32_t bad = 0;
       for (int32_t p = 0; p < ms; ++p) {
         const double piv = Sm[p * (ms + 1) + p];
@@ -994,16 +999,19 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(const DevPlan P, const int
           bad = 1;
           break;
         }
-        const double inv = 1.0 / piv;
+        const double inv = recip(piv);
+        if (tid == 0) amax[p] = inv;  // the row maximum is used up: keep 1/pivot for the triangular solves
         // rows p + 1 .. p + nr, columns p + 1 .. c1 (and the right-hand side
         // column): one (row, column) entry per lane; column p and row p are
         // only read in this step, so every entry has one writer
         const int32_t c1 = p + bw < ms - 1 ? p + bw : ms - 1;
         const int32_t nr = c1 - p, w = nr + (cols > ms ? 1 : 0);
-        for (int32_t l = tid; l < nr * w; l += 64) {
-          const int32_t r = l / w, cc = l - r * w;
-          const int32_t q = p + 1 + r, c = cc < nr ? p + 1 + cc : ms;
-          Sm[q * (ms + 1) + c] -= Sm[q * (ms + 1) + p] * inv * Sm[p * (ms + 1) + c];
+        for (int32_t l = tid; l < nr * W; l += 64) {
+          const int32_t r = l >> lw, cc = l & (W - 1);
+          if (cc < w) {
+            const int32_t q = p + 1 + r, c = cc < nr ? p + 1 + cc : ms;
+            Sm[q * (ms + 1) + c] -= Sm[q * (ms + 1) + p] * inv * Sm[p * (ms + 1) + c];
+          }
         }
         __builtin_amdgcn_wave_barrier();
       }
@@ -1036,7 +1044,7 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(const DevPlan P, const int
       if (forward)
         for (int32_t p = 0; p < ms; ++p) {
           const int32_t q = p + 1 + tid;
-          if (tid < bw && q < ms) zs[q] -= Sm[q * (ms + 1) + p] / Sm[p * (ms + 1) + p] * zs[p];
+          if (tid < bw && q < ms) zs[q] -= Sm[q * (ms + 1) + p] * amax[p] * zs[p];
           __builtin_amdgcn_wave_barrier();
         }
       if (tid == 0)
@@ -1044,10 +1052,30 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(const DevPlan P, const int
           double acc = zs[q];
           const int32_t c1 = q + bw < ms - 1 ? q + bw : ms - 1;
           for (int32_t c = q + 1; c <= c1; ++c) acc -= Sm[q * (ms + 1) + c] * zs[c];
-          zs[q] = acc / Sm[q * (ms + 1) + q];
+          zs[q] = acc * amax[q];
         }
     }
     __syncthreads();
+  };
+
+  // maximum over the molecule's parts of their violation (at lambda = 0 with
+  // rel0) and OR of their singular flags: the lanes of every wave read the
+  // parts' records together (one round of device-coherent loads, not one per
+  // part), then reduce within the wave; every wave obtains the same values
+  [[maybe_unused]] auto parts_reduce = [&](bool rel0, double& vmax, int32_t& sing) {
+    double v = 0.0;
+    int32_t sg = 0;
+    for (int32_t q = tid & 63; q < sp.n_parts; q += 64) {
+      v = fmax(v, ld_coh(rel0 ? &pxa[q].rel0 : &pxa[q].viol));
+      sg |= ld_coh(&pxa[q].singular);
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      v = fmax(v, __shfl_xor(v, off, 64));
+      sg |= __shfl_xor(sg, off, 64);
+    }
+    vmax = v;
+    sing = sg;
   };
 
   // ---- chord: factor A(r, r) once
@@ -1079,10 +1107,7 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(const DevPlan P, const int
       st_code = ILVES_ERR_TIMEOUT;
     } else {
       int32_t sing = 0;
-      for (int32_t q = 0; q < sp.n_parts; ++q) {
-        rel_zero = fmax(rel_zero, ld_coh(&pxa[q].rel0));
-        sing |= ld_coh(&pxa[q].singular);
-      }
+      parts_reduce(true, rel_zero, sing);
       rel_zero = uni(rel_zero);
       chord_singular = A.chord && uni(sing) != 0;
       if (A.chord && !chord_singular) {
@@ -1206,10 +1231,7 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(const DevPlan P, const int
       }
       if (!grid_barrier(bar, sp.n_parts, A.wait_limit, &next_slot)) { st_code = ILVES_ERR_TIMEOUT; break; }
       double gm = 0.0;
-      for (int32_t q = 0; q < sp.n_parts; ++q) {
-        gm = fmax(gm, ld_coh(&pxa[q].viol));
-        sing_all |= ld_coh(&pxa[q].singular);
-      }
+      parts_reduce(false, gm, sing_all);
       gmax = uni(gm);
       sing_all = uni(sing_all);
     }
