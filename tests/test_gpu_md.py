@@ -1,6 +1,7 @@
 """Constrained leapfrog around the device solve: the supplement's simple
 pendulum (energy error bounded and second order in h at Tol = 1e-12, drift
-at loose tolerance with the simplified Newton method), a multi-link pendulum
+at loose tolerance with the simplified Newton method, the sign of the energy
+error at Tol = 1e-4 opposite for Newton and chord), a multi-link pendulum
 on the general path, and a few steps of a mixed system against the same
 integration done on the CPU with the oracle."""
 import numpy as np
@@ -87,6 +88,66 @@ def test_pendulum_loose_tolerance_drifts():
     print(f"drift of the 5-period mean energy error: Tol 1e-3 {drift_l:.3e}, Tol 1e-6 {drift_t:.3e}", flush=True)
     assert drift_l > 0.05 * np.abs(Rl).max()
     assert abs(drift_t) < 0.01 * np.abs(Rt).max()
+
+
+def _pendulum_sign_run(periods, variant, tol=1e-4, steps_per_period=100, every=10):
+    """Relative energy error of the pendulum every ``every`` steps over
+    ``periods`` periods; ten steps and the energy sample are captured in one
+    HIP graph and replayed, so that a million steps take seconds."""
+    import torch
+    T = _period()
+    h = T / steps_per_period
+    sm, v = MD.pendulum(LEN, 1.0, 1e20, V0)
+    v = v.copy()
+    v[1] = [V0, -0.5 * h * V0 ** 2 / LEN, 0.0]
+    ig = MD.ConstrainedLeapfrog(sm, v, h, tol=tol, variant=variant)
+    f = torch.from_numpy(S.soa(MD.gravity(sm, G, fixed=(0,)))).cuda()
+    e0 = 0.5 * V0 ** 2
+    n_rec = periods * steps_per_period // every
+    R = torch.zeros(n_rec + 1, dtype=torch.float64, device="cuda")
+    idx = torch.zeros(1, dtype=torch.int64, device="cuda")
+    one = torch.ones(1, dtype=torch.int64, device="cuda")
+    vp = torch.empty(3, dtype=torch.float64, device="cuda")
+    yp = torch.empty(1, dtype=torch.float64, device="cuda")
+
+    def block():
+        for _ in range(every - 1):
+            ig.step(f)
+        vp.copy_(ig.v[:, 1])
+        yp.copy_(ig.r[1, 1:2])
+        ig.step(f)
+        vk = 0.5 * (vp + ig.v[:, 1])
+        R.index_put_((idx,), (0.5 * (vk * vk).sum() + G * yp - e0) / e0)
+        idx.add_(one)
+
+    block()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        block()
+    torch.cuda.synchronize()
+    idx.zero_()
+    for _ in range(n_rec):
+        g.replay()
+    torch.cuda.synchronize()
+    assert np.all(ig.worst.cpu().numpy() == L.OK)
+    return R[:n_rec].cpu().numpy()
+
+
+def test_pendulum_energy_error_sign_depends_on_the_solver():
+    """The supplement's third set of pendulum runs: 10,000 periods at 100
+    steps per period with Tol = 1e-4.  With Newton's method the relative
+    energy error settles below zero (the pendulum appears to lose energy);
+    with the simplified Newton (chord) method it stays above zero (it appears
+    to gain energy): the sign of the computed drift depends on the solver."""
+    rn = _pendulum_sign_run(10_000, L.VARIANT_NEWTON)
+    rc = _pendulum_sign_run(10_000, L.VARIANT_CHORD)
+    half = len(rn) // 2
+    print(f"Newton: negative in {100 * (rn < 0).mean():.1f}% of the samples ({100 * (rn[half:] < 0).mean():.1f}% "
+          f"of the second half), mean {rn.mean():.2e}; chord: positive in {100 * (rc > 0).mean():.1f}%, "
+          f"mean {rc.mean():.2e}", flush=True)
+    assert (rn[half:] < 0).mean() >= 0.9 and rn[half:].mean() < 0
+    assert (rc > 0).mean() >= 0.99 and rc[half:].mean() > 0
 
 
 def test_chain_pendulum_on_general_path():
