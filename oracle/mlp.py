@@ -52,8 +52,14 @@ def features(pairs, d, mass, r, r_u):
     ee = np.einsum("ij,ij->i", e, e)
     bb = np.einsum("ij,ij->i", u, e)
     c = np.einsum("ij,ij->i", u, u) - d2
-    disc = np.maximum(bb * bb - ee * c, 0.0)
-    t0 = c / (bb + np.sqrt(disc))
+    # t0 = w * (the decoupled start of constraint k): the root nearest 0 of
+    # |u - t e|^2 = d^2 when u.e > 0 and a real root exists, else the Newton
+    # step from t = 0, c / (2 u.e) (0 when u.e = 0)
+    disc = bb * bb - ee * c
+    root = (bb > 0) & (disc >= 0)
+    safe_bb = np.where(bb != 0, bb, 1.0)
+    t0 = np.where(root, c / np.where(root, bb + np.sqrt(np.maximum(disc, 0.0)), 1.0),
+                  np.where(bb != 0, c / (2 * safe_bb), 0.0))
     f = np.zeros((n, N_FEAT))
     f[:, 0] = t0
     f[:, 1] = c / (2 * d2)

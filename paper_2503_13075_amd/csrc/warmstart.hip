@@ -100,11 +100,14 @@ __global__ void __launch_bounds__(kChunk) features_own_kernel(const DevPlan P, c
   const double ee = e0 * e0 + e1 * e1 + e2 * e2;
   const double bb = u0 * e0 + u1 * e1 + u2 * e2;
   const double cc = u0 * u0 + u1 * u1 + u2 * u2 - d2;
-  const double disc = fmax(bb * bb - ee * cc, 0.0);
+  const double disc = bb * bb - ee * cc;
+  // t0 = w * (the decoupled start): the root nearest 0 of |u - t e|^2 = d^2
+  // when u.e > 0 and a real root exists, else the Newton step from 0
+  const double t0 = (bb > 0.0 && disc >= 0.0) ? cc / (bb + sqrt(disc)) : (bb != 0.0 ? cc / (2.0 * bb) : 0.0);
   const double cx = u1 * e2 - u2 * e1, cy = u2 * e0 - u0 * e2, cz = u0 * e1 - u1 * e0;
   const int32_t dega = inc_ptr[la + 1] - inc_ptr[la], degb = inc_ptr[lb + 1] - inc_ptr[lb];
   float4* f = reinterpret_cast<float4*>(feat + (R0 + k) * N_FEAT);
-  f[0] = make_float4(static_cast<float>(cc / (bb + sqrt(disc))), static_cast<float>(cc / (2.0 * d2)),
+  f[0] = make_float4(static_cast<float>(t0), static_cast<float>(cc / (2.0 * d2)),
                      static_cast<float>(bb / d2 - 1.0), static_cast<float>(sqrt(cx * cx + cy * cy + cz * cz) / d2));
   f[1] = make_float4(static_cast<float>(fabs(ia - ib) / w), static_cast<float>((dega + degb - 2) * 0.25),
                      static_cast<float>(abs(dega - degb) * 0.25), 0.0f);

@@ -60,6 +60,23 @@ def test_untrained_network_returns_decoupled_solution():
     assert abs(out["lam"][0] - lam[0]) <= 1e-12 * abs(ref)
 
 
+def test_untrained_network_without_a_root_takes_one_newton_step():
+    """Where the decoupled quadratic has no usable root (u.e <= 0: the
+    unconstrained bond turned away from the old one), the untrained network
+    returns the decoupled start's fallback, the first Newton step from
+    lambda = 0 of the constraint alone: the oracle's Newton solve of the
+    diatomic stopped after one iteration."""
+    pts = np.array([[0.0, 0, 0], [0.11, 0, 0]])
+    m = np.array([1.008, 12.011])
+    for ru in (np.array([[0.0, 0, 0], [-0.02, 0.105, 0.0]]),     # u.e < 0, real root
+               np.array([[0.0, 0, 0], [-0.05, 0.01, 0.0]])):     # u.e < 0, no real root
+        f, w = M.features([[0, 1]], [0.11], m, pts, ru)
+        lam = M.predict_lambda(M.init_params(0), np.zeros(16), np.ones(16), 0.1, f, w)
+        one = O.solve([[0, 1]], [0.11], m, pts, ru, tol=1e-300, max_iter=1)
+        assert one["iters"][0] == 1
+        assert abs(lam[0] - one["lam"][0]) <= 1e-12 * abs(one["lam"][0])
+
+
 def test_features_invariances():
     rng = np.random.default_rng(4)
     sm = S.add_h_angles(S.protein(6, seed=3))
