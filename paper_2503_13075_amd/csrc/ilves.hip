@@ -1043,8 +1043,11 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(const DevPlan P, const int
       __builtin_amdgcn_wave_barrier();
       if (forward)
         for (int32_t p = 0; p < ms; ++p) {
-          const int32_t q = p + 1 + tid;
-          if (tid < bw && q < ms) zs[q] -= Sm[q * (ms + 1) + p] * amax[p] * zs[p];
+          // rows p + 1 .. p + bw, the wave's lanes striding over them
+          for (int32_t i = tid; i < bw; i += 64) {
+            const int32_t q = p + 1 + i;
+            if (q < ms) zs[q] -= Sm[q * (ms + 1) + p] * amax[p] * zs[p];
+          }
           __builtin_amdgcn_wave_barrier();
         }
       if (tid == 0)
