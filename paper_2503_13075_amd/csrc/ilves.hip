@@ -1457,13 +1457,16 @@ __global__ void __launch_bounds__(256) small_kernel(const SmallMol* __restrict__
     for (int p = 0; p < kSmallCons; ++p) {
       if (!(fabs(m[p][p]) > 1e-13 * fabs(cdiag[p] * (e[p][0] * e[p][0] + e[p][1] * e[p][1] + e[p][2] * e[p][2]))))
         sing = sing || p < nc;
-      const double inv = 1.0 / m[p][p];
+      // 1 / pivot from the hardware reciprocal refined by Newton steps,
+      // kept in the pivot's slot for the back substitution
+      const double inv = recip(m[p][p]);
 #pragma unroll
       for (int q = p + 1; q < kSmallCons; ++q) {
         const double f = m[q][p] * inv;
 #pragma unroll
         for (int j = p; j <= kSmallCons; ++j) m[q][j] -= f * m[p][j];
       }
+      m[p][p] = inv;
     }
     if (sing) { st_code = ILVES_ERR_SINGULAR; break; }
     double z[kSmallCons];
@@ -1472,7 +1475,7 @@ __global__ void __launch_bounds__(256) small_kernel(const SmallMol* __restrict__
       double acc = m[p][kSmallCons];
 #pragma unroll
       for (int j = p + 1; j < kSmallCons; ++j) acc -= m[p][j] * z[j];
-      z[p] = acc / m[p][p];
+      z[p] = acc * m[p][p];
     }
 #pragma unroll
     for (int k = 0; k < kSmallCons; ++k)
