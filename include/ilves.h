@@ -168,11 +168,13 @@ ilves_status_t ilves_plan_reset_barriers(ilves_plan_t plan);
  *   whose parts keep only their factor values in LDS (FP64), [16] split
  *   molecules whose parts keep their factor values and per-row structure in
  *   LDS and read pair tasks and update lists from global memory (mixed
- *   precision).
+ *   precision), [17] elimination levels of the split molecules' parts whose
+ *   items are shared over several lanes (in the factorisation or the
+ *   backward substitution: levels with long chains of entries).
  * Defined by: Supplement section 3 (L(G), ordering, fill of the factors).
  * Errors: ILVES_ERR_ARG (NULL plan or stats).
  */
-#define ILVES_STAT_COUNT 17
+#define ILVES_STAT_COUNT 18
 ilves_status_t ilves_plan_stats(ilves_plan_t plan, int64_t* stats);
 
 /*

@@ -23,7 +23,8 @@ VARIANT_NEWTON, VARIANT_CHORD = 0, 1
 WARM_ZERO, WARM_MLP, WARM_CALLER, WARM_DECOUPLED = 0, 1, 2, 3
 STAT_NAMES = ["molecules", "constraints", "atoms", "factor_entries", "fill", "updates", "max_levels",
               "sum_levels", "mol_lds", "mol_workspace", "workspace_bytes", "plan_bytes", "split_molecules",
-              "split_parts", "max_separator", "split_values_lds", "split_pairs_global"]
+              "split_parts", "max_separator", "split_values_lds", "split_pairs_global",
+              "split_shared_lane_levels"]
 
 
 class IlvesError(RuntimeError):

@@ -2223,6 +2223,21 @@ ilves_status_t build_device_plan(ilves_plan* P) {
   P->stats[14] = max_sep;
   P->stats[15] = std::count(P->split_mode[0].begin(), P->split_mode[0].end(), static_cast<int>(VALUES_LDS));
   P->stats[16] = std::count(P->split_mode[1].begin(), P->split_mode[1].end(), static_cast<int>(PAIRS_GLOBAL));
+  int64_t shared = 0;  // levels of the parts that share items over several lanes
+  for (const auto& sp : P->splits)
+    for (const auto& M : sp.parts)
+      for (int32_t h = 0; h < M.n_levels; ++h) {
+        int32_t cf = 0, cb = 0;
+        for (int32_t j = M.lvl_row[h]; j < M.lvl_row[h + 1]; ++j) {
+          cf = std::max(cf, M.l_start[j + 1] - M.l_start[j]);
+          cb = std::max(cb, M.up_start[j + 1] - M.up_start[j]);
+        }
+        for (int32_t pi = M.pl_start[h]; pi < M.pl_start[h + 1]; ++pi)
+          cf = std::max(cf, M.ustart[M.plist[pi] + 1] - M.ustart[M.plist[pi]]);
+        const int32_t nr = M.lvl_row[h + 1] - M.lvl_row[h], np = M.pl_start[h + 1] - M.pl_start[h];
+        if (item_lanes_log2(cf, nr, np, true) > 0 || item_lanes_log2(cb, nr, 0, false) > 0) ++shared;
+      }
+  P->stats[17] = shared;
   return ILVES_OK;
 }
 

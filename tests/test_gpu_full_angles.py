@@ -49,7 +49,7 @@ def test_angles_full_size(system, name, prec, warm):
     print(f"== angles full size, {name}", flush=True)
     out = solve_once(sm, ru, 1e-12, prec, L.VARIANT_NEWTON, warm=warm)
     st = out["plan"].stats()
-    assert st["split_molecules"] == 20, st
+    assert st["split_molecules"] == 20 and st["split_shared_lane_levels"] > 0, st
     assert np.all(out["status"] == L.OK)
     viol = np.max(O.relative_violation(out["r_out"], sm.pairs, sm.d))
     corr = sm.mass[:, None] * (out["r_out"] - ru)

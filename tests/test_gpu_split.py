@@ -216,6 +216,7 @@ def test_split_with_values_only_in_lds():
         print(f"   {sm.n_constraints} constraints, parts {st['split_parts']}, separator {st['max_separator']}, "
               f"values-only {st['split_values_lds']}, pairs-global {st['split_pairs_global']}", flush=True)
         assert st["split_molecules"] == 1 and st["split_values_lds"] == 1 and st["split_pairs_global"] == 1, st
+        assert st["split_shared_lane_levels"] > 0, st  # the angle fill gives levels whose items share lanes
         _check(sm, out, ref, f"h-angle protein values-only/{prec}")
 
 

@@ -121,3 +121,13 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
         L.lib()
     with pytest.raises(ImportError):
         L.Plan(2, np.array([[0, 1]], np.int32), np.array([0.1]))
+
+
+def test_stat_names_cover_the_header_count():
+    """ilves_plan_stats writes ILVES_STAT_COUNT int64 values into the buffer
+    the binding sizes from its list of names: the two must agree."""
+    import os
+    import re
+    hdr = open(os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "ilves.h")).read()
+    count = int(re.search(r"#define ILVES_STAT_COUNT (\d+)", hdr).group(1))
+    assert len(L.STAT_NAMES) == count
