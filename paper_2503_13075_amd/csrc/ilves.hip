@@ -1663,6 +1663,22 @@ void append(std::vector<V>& dst, const std::vector<int32_t>& src) {
   for (int32_t x : src) dst.push_back(static_cast<V>(x));
 }
 
+// lanes per item (log2) of level h: in the factorisation from its longest
+// chain (lower entries of a row, updates of a pair task), in the backward
+// substitution from its longest row of upper entries
+void level_lanes(const ilves::MolPlan& M, int32_t h, int32_t& lg_factor, int32_t& lg_backward) {
+  int32_t cf = 0, cb = 0;
+  for (int32_t j = M.lvl_row[h]; j < M.lvl_row[h + 1]; ++j) {
+    cf = std::max(cf, M.l_start[j + 1] - M.l_start[j]);
+    cb = std::max(cb, M.up_start[j + 1] - M.up_start[j]);
+  }
+  for (int32_t pi = M.pl_start[h]; pi < M.pl_start[h + 1]; ++pi)
+    cf = std::max(cf, M.ustart[M.plist[pi] + 1] - M.ustart[M.plist[pi]]);
+  const int32_t nr = M.lvl_row[h + 1] - M.lvl_row[h], np = M.pl_start[h + 1] - M.pl_start[h];
+  lg_factor = item_lanes_log2(cf, nr, np, true);
+  lg_backward = item_lanes_log2(cb, nr, 0, false);
+}
+
 // Appends a molecule's structure block (see struct_layout) to the pool and
 // returns its byte offset (-1 if a slot's shared atom is not one of its
 // row's atoms, which a consistent plan never has).
@@ -1688,16 +1704,10 @@ int64_t pack_struct(const ilves::MolPlan& M, std::vector<unsigned char>& pool) {
     put(Lo.lvh, 4 * h + 3, M.pl_start[h + 1]);
   }
   for (int32_t h = 0; h < M.n_levels; ++h) {
-    int32_t cf = 0, cb = 0;
-    for (int32_t j = M.lvl_row[h]; j < M.lvl_row[h + 1]; ++j) {
-      cf = std::max(cf, M.l_start[j + 1] - M.l_start[j]);
-      cb = std::max(cb, M.up_start[j + 1] - M.up_start[j]);
-    }
-    for (int32_t pi = M.pl_start[h]; pi < M.pl_start[h + 1]; ++pi)
-      cf = std::max(cf, M.ustart[M.plist[pi] + 1] - M.ustart[M.plist[pi]]);
-    const int32_t nr = M.lvl_row[h + 1] - M.lvl_row[h], np = M.pl_start[h + 1] - M.pl_start[h];
-    put(Lo.lvc, 2 * h + 0, item_lanes_log2(cf, nr, np, true));
-    put(Lo.lvc, 2 * h + 1, item_lanes_log2(cb, nr, 0, false));
+    int32_t lf, lb;
+    level_lanes(M, h, lf, lb);
+    put(Lo.lvc, 2 * h + 0, lf);
+    put(Lo.lvc, 2 * h + 1, lb);
   }
   for (int32_t t = 0; t < M.n_l; ++t) {
     put(Lo.lpair, 2 * t + 0, M.lcol[t]);
@@ -2227,15 +2237,9 @@ ilves_status_t build_device_plan(ilves_plan* P) {
   for (const auto& sp : P->splits)
     for (const auto& M : sp.parts)
       for (int32_t h = 0; h < M.n_levels; ++h) {
-        int32_t cf = 0, cb = 0;
-        for (int32_t j = M.lvl_row[h]; j < M.lvl_row[h + 1]; ++j) {
-          cf = std::max(cf, M.l_start[j + 1] - M.l_start[j]);
-          cb = std::max(cb, M.up_start[j + 1] - M.up_start[j]);
-        }
-        for (int32_t pi = M.pl_start[h]; pi < M.pl_start[h + 1]; ++pi)
-          cf = std::max(cf, M.ustart[M.plist[pi] + 1] - M.ustart[M.plist[pi]]);
-        const int32_t nr = M.lvl_row[h + 1] - M.lvl_row[h], np = M.pl_start[h + 1] - M.pl_start[h];
-        if (item_lanes_log2(cf, nr, np, true) > 0 || item_lanes_log2(cb, nr, 0, false) > 0) ++shared;
+        int32_t lf, lb;
+        level_lanes(M, h, lf, lb);
+        if (lf > 0 || lb > 0) ++shared;
       }
   P->stats[17] = shared;
   return ILVES_OK;
