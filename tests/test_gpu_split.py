@@ -70,6 +70,8 @@ def test_split_matches_oracle_and_replay(cases, case, name, prec, variant):
     out = solve_once(sm, ru, TOL, prec, variant, split_rows=rows, split_part_rows=part)
     st = out["plan"].stats()
     assert st["split_molecules"] == 1 and st["split_parts"] >= 2, st
+    if case == "h_angles":  # its parts' long chains take the shared-lane levels (every variant, chord included)
+        assert st["split_shared_lane_levels"] > 0, st
     print(f"   parts {st['split_parts']}, separator rows {st['max_separator']}", flush=True)
     _check(sm, out, ref, f"{case}/{name}")
     rep = L.replay_host(sm.n_atoms, sm.pairs, sm.d, sm.mass, S.soa(sm.r), S.soa(ru), TOL, precision=prec,
