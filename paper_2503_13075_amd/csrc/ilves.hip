@@ -2109,6 +2109,27 @@ ilves_status_t build_device_plan(ilves_plan* P) {
       g.stream = best;
       load[best] += g.work;
     }
+    // the group of the smallest molecules runs last on the stream of the
+    // group of the largest: started beside the large trees it takes CUs
+    // that lengthen their critical path, chained behind them its many
+    // short molecules fill the CUs the trees release as they finish (the
+    // same shortest-last rule as the order inside each group)
+    if (gs.size() >= 3) {
+      size_t big = 0, small = 0;
+      for (size_t i = 1; i < gs.size(); ++i) {
+        if (gs[i].lds_bytes > gs[big].lds_bytes) big = i;
+        if (gs[i].lds_bytes < gs[small].lds_bytes) small = i;
+      }
+      if (big != small) {
+        Group sg = gs[small];
+        load[sg.stream] -= sg.work;
+        sg.stream = gs[big].stream;
+        load[sg.stream] += sg.work;
+        gs.erase(gs.begin() + static_cast<std::ptrdiff_t>(small));
+        if (small < big) --big;
+        gs.insert(gs.begin() + static_cast<std::ptrdiff_t>(big + 1), sg);
+      }
+    }
     auto least_loaded = [&]() {
       int least = 0;
       for (int i = 1; i < kStreams; ++i)
