@@ -1588,7 +1588,7 @@ struct Group {
   int32_t counter = 0;  // index of the group's queue counter
   int stream = 0;       // index into the plan's streams
   int64_t work = 0;     // sum over its molecules of rows + off-diagonal slots
-  bool heavy = false;   // one workgroup per CU by LDS: the wide-batch kernel
+  bool heavy = false;   // largest trees, one workgroup per CU: the wide-batch kernel
 };
 constexpr int kMaxGroups = 64;
 
@@ -2268,7 +2268,9 @@ ilves_status_t build_device_plan(ilves_plan* P) {
 
 // Kernel attributes and persistent grid sizes of the launch groups.
 ilves_status_t finalize_groups(ilves_plan* P) {
-  for (int prec = 0; prec < 2; ++prec)
+  for (int prec = 0; prec < 2; ++prec) {
+    int lds_top = 0;
+    for (const Group& g : P->groups[prec]) lds_top = std::max(lds_top, g.lds_bytes);
     for (Group& g : P->groups[prec]) {
       g.heavy = false;
       const void* k = reinterpret_cast<const void*>(pick_kernel(prec == 1, g.mode, g.wide, g.block));
@@ -2278,9 +2280,12 @@ ilves_status_t finalize_groups(ilves_plan* P) {
       int per_cu = 0;
       HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, g.block, static_cast<size_t>(g.lds_bytes)));
       if (per_cu < 1) return fail(ILVES_ERR_HIP, "a solve kernel cannot be resident on a compute unit");
-      // one workgroup per CU by LDS: the wide-batch kernel costs no occupancy
-      // (512 threads: at 1024 the launch bounds leave 128 registers, too few)
-      if (per_cu == 1 && g.mode == ALL_LDS && !g.wide && g.block == 512) {
+      // one workgroup per CU by LDS: the wide-batch kernel costs the group no
+      // occupancy (512 threads: at 1024 the launch bounds leave 128 registers,
+      // too few).  Only the group of the largest trees takes it: a CU that
+      // holds a workgroup of another one-per-CU group has LDS left for
+      // smaller molecules, and the extra registers would keep them out.
+      if (per_cu == 1 && g.lds_bytes == lds_top && g.mode == ALL_LDS && !g.wide && g.block == 512) {
         const void* kh = reinterpret_cast<const void*>(pick_kernel(prec == 1, g.mode, g.wide, g.block, true));
         HIP_TRY(hipFuncSetAttribute(kh, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsMax));
         int per_cu_h = 0;
@@ -2289,6 +2294,7 @@ ilves_status_t finalize_groups(ilves_plan* P) {
       }
       g.grid = static_cast<int32_t>(std::min<int64_t>(g.count, static_cast<int64_t>(per_cu) * P->n_cu));
     }
+  }
   // split molecules: launches of whole molecules whose parts can all be
   // resident at once (the barriers of a molecule wait for all its parts)
   for (int prec = 0; prec < 2; ++prec) {
