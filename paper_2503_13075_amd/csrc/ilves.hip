@@ -2673,10 +2673,24 @@ ilves_status_t solve_impl(ilves_plan_t P, const double* r, const double* r_u, co
     HIP_TRY(hipLaunchKernel(reinterpret_cast<const void*>(k), dim3(l.count), dim3(kSplitBlock), args,
                             static_cast<size_t>(l.lds_bytes), P->streams[l.stream]));
   }
+  // the group of the largest trees (and the group chained behind it) runs on
+  // the caller's stream: its launch follows the counter reset in the same
+  // queue, while the forked streams first wait for the fork event, so its
+  // workgroups take whole CUs before the other groups spread over them
+  // (with every group forked, eager launches left that to the order in
+  // which the hardware serves the queues).  Not with split molecules: their
+  // parts are dispatched first.
+  int origin = -1;
+  if (!groups.empty() && P->split_launch[pr].empty()) {
+    size_t big = 0;
+    for (size_t gi = 1; gi < groups.size(); ++gi)
+      if (groups[gi].lds_bytes > groups[big].lds_bytes) big = gi;
+    origin = groups[big].stream;
+  }
   for (size_t gi = 0; gi < groups.size(); ++gi) {
     const Group& g = groups[gi];
     KernelFn k = pick_kernel(precision == ILVES_PREC_MIXED, g.mode, g.wide, g.block, g.heavy);
-    hipStream_t s = P->streams[g.stream];
+    hipStream_t s = g.stream == origin ? stream : P->streams[g.stream];
     DevPlan dp = P->dp;
     const int32_t* list = P->d_lists + g.first;
     int32_t count = g.count;
