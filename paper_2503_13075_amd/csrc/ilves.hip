@@ -1340,76 +1340,94 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(const DevPlan P, const int
 // ---------------------------------------------------------------------------
 // small molecules (at most 3 constraints on at most 4 atoms): one thread per
 // molecule, the same constraint-space Newton iteration in FP64 registers,
-// the dense 3x3 system solved by elimination without pivoting.
+// the dense system solved by elimination without pivoting.  A connected
+// molecule of that size has one of five shapes; the plan numbers its atoms
+// and constraints in the shape's canonical order (SmallTopo) and groups the
+// molecules by shape, so each shape runs code with the atom of every
+// constraint end and every coupling known at compile time.  G(r) does not
+// depend on which end of a constraint comes first (e_k and the signs of its
+// row flip together), so the canonical orientation changes nothing.
+
+// Canonical constraints (A[k], B[k]) of each shape: 0 one bond; 1 two bonds
+// at atom 0; 2 triangle; 3 three bonds at atom 0; 4 chain 0-1-2-3.
+template <int CLS> struct SmallTopo;
+template <> struct SmallTopo<0> { static constexpr int NC = 1, NA = 2; static constexpr int A[3] = {0, 0, 0}, B[3] = {1, 1, 1}; };
+template <> struct SmallTopo<1> { static constexpr int NC = 2, NA = 3; static constexpr int A[3] = {0, 0, 0}, B[3] = {1, 2, 2}; };
+template <> struct SmallTopo<2> { static constexpr int NC = 3, NA = 3; static constexpr int A[3] = {0, 0, 1}, B[3] = {1, 2, 2}; };
+template <> struct SmallTopo<3> { static constexpr int NC = 3, NA = 4; static constexpr int A[3] = {0, 0, 0}, B[3] = {1, 2, 3}; };
+template <> struct SmallTopo<4> { static constexpr int NC = 3, NA = 4; static constexpr int A[3] = {0, 1, 2}, B[3] = {1, 2, 3}; };
+
+// sigma_{k,x}: +1 if atom x is A[k], -1 if it is B[k], else 0
+template <int CLS>
+__device__ constexpr int small_sigma(int k, int x) {
+  return SmallTopo<CLS>::A[k] == x ? 1 : (SmallTopo<CLS>::B[k] == x ? -1 : 0);
+}
+// the atom constraints k != j share, or -1
+template <int CLS>
+__device__ constexpr int small_shared(int k, int j) {
+  using T = SmallTopo<CLS>;
+  return k == j ? -1
+         : (T::A[k] == T::A[j] || T::A[k] == T::B[j]) ? T::A[k]
+         : (T::B[k] == T::A[j] || T::B[k] == T::B[j]) ? T::B[k]
+                                                      : -1;
+}
 
 // PROJECT: velocity projection (residual e_k . p_k; compiled apart so that
 // the solve keeps its registers)
-template <bool PROJECT>
-__global__ void __launch_bounds__(256) small_kernel(const SmallMol* __restrict__ sm, int32_t count,
-                                                   const SolveArgs A) {
-  const int32_t t = blockIdx.x * 256 + threadIdx.x;
-  if (t >= count) return;
-  const SmallMol M = sm[t];
+template <int CLS, bool PROJECT>
+__device__ __forceinline__ void small_solve(const SmallMol& M, const SolveArgs& A) {
+  using Tp = SmallTopo<CLS>;
+  constexpr int NC = Tp::NC, NA = Tp::NA;
   const int32_t S = A.n_atoms;
-  const int nc = M.nc, na = M.na;
-  double invm[kSmallAtoms], ru[kSmallAtoms][3];
+  double invm[NA], ru[NA][3];
   double rmax = 0.0;
 #pragma unroll
-  for (int i = 0; i < kSmallAtoms; ++i) {
+  for (int i = 0; i < NA; ++i) {
     const int32_t g = M.atom[i];
-    invm[i] = i < na ? 1.0 / A.mass[g] : 0.0;
+    invm[i] = 1.0 / A.mass[g];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       ru[i][c] = A.r_u[c * S + g];
-      if (i < na) rmax = fmax(rmax, fabs(ru[i][c]));
+      rmax = fmax(rmax, fabs(ru[i][c]));
     }
   }
-  double e[kSmallCons][3], u[kSmallCons][3], lam[kSmallCons], cdiag[kSmallCons], coup[kSmallCons][kSmallCons];
+  // u_k is formed from r_u where it is needed rather than kept
+  auto ucomp = [&](int k, int c) { return ru[Tp::A[k]][c] - ru[Tp::B[k]][c]; };
+  double e[NC][3], lam[NC], cdiag[NC], id2[NC];
   double v0 = 0.0;
 #pragma unroll
-  for (int k = 0; k < kSmallCons; ++k) {
-    const int a = M.a[k], b = M.b[k];
-    const int32_t ga = M.atom[a], gb = M.atom[b];
+  for (int k = 0; k < NC; ++k) {
+    const int32_t ga = M.atom[Tp::A[k]], gb = M.atom[Tp::B[k]];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      e[k][c] = A.r[c * S + ga] - A.r[c * S + gb];
-      u[k][c] = ru[a][c] - ru[b][c];
-    }
-    cdiag[k] = invm[a] + invm[b];
-    lam[k] = k >= nc ? 0.0
-             : A.warm == 3 ? decoupled_lambda(u[k][0], u[k][1], u[k][2], e[k][0], e[k][1], e[k][2], cdiag[k], M.d2[k])
+    for (int c = 0; c < 3; ++c) e[k][c] = A.r[c * S + ga] - A.r[c * S + gb];
+    cdiag[k] = invm[Tp::A[k]] + invm[Tp::B[k]];
+    id2[k] = 1.0 / M.d2[k];
+    const double u0 = ucomp(k, 0), u1 = ucomp(k, 1), u2 = ucomp(k, 2);
+    lam[k] = A.warm == 3 ? decoupled_lambda(u0, u1, u2, e[k][0], e[k][1], e[k][2], cdiag[k], M.d2[k])
              : A.warm ? A.lambda[M.cid[k]] : 0.0;
-    if (k < nc)
-      v0 = fmax(v0, fabs(u[k][0] * u[k][0] + u[k][1] * u[k][1] + u[k][2] * u[k][2] - M.d2[k]) / (2.0 * M.d2[k]));
+    v0 = fmax(v0, fabs(u0 * u0 + u1 * u1 + u2 * u2 - M.d2[k]) * (0.5 * id2[k]));
   }
-  // C_kj for k != j: sign(k, x) sign(j, x) / m_x for the shared atom x
-#pragma unroll
-  for (int k = 0; k < kSmallCons; ++k)
-#pragma unroll
-    for (int j = 0; j < kSmallCons; ++j) {
-      double c = 0.0;
-      if (k != j && k < nc && j < nc) {
-        if (M.a[k] == M.a[j]) c = invm[M.a[k]];
-        else if (M.b[k] == M.b[j]) c = invm[M.b[k]];
-        else if (M.a[k] == M.b[j]) c = -invm[M.a[k]];
-        else if (M.b[k] == M.a[j]) c = -invm[M.b[k]];
-      }
-      coup[k][j] = c;
-    }
+  // C_kj for k != j: sigma(k, x) sigma(j, x) / m_x for the shared atom x
+  auto coup = [&](int k, int j) {
+    const int x = small_shared<CLS>(k, j);
+    const double w = invm[x < 0 ? 0 : x];
+    return small_sigma<CLS>(k, x < 0 ? 0 : x) * small_sigma<CLS>(j, x < 0 ? 0 : x) > 0 ? w : -w;
+  };
   const double delta = 1.7320508075688772 * rmax * 0x1.0p-52;
   const double delta2 = 0.5 * delta * delta;
   int32_t it = 0, st_code = ILVES_ERR_NOT_CONVERGED, fell_back = 0, rises = 0;
   double prev = INFINITY;
   for (;;) {
-    double ep[kSmallCons][3], g[kSmallCons];
+    double ep[NC][3], g[NC];
     double gmax = 0.0;
 #pragma unroll
-    for (int k = 0; k < kSmallCons; ++k) {
+    for (int k = 0; k < NC; ++k) {
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        double x = u[k][c] - cdiag[k] * lam[k] * e[k][c];
+        double x = ucomp(k, c) - cdiag[k] * lam[k] * e[k][c];
 #pragma unroll
-        for (int j = 0; j < kSmallCons; ++j) x -= coup[k][j] * lam[j] * e[j][c];
+        for (int j = 0; j < NC; ++j)
+          if (small_shared<CLS>(k, j) >= 0) x -= coup(k, j) * lam[j] * e[j][c];
         ep[k][c] = x;
       }
       const double pp = ep[k][0] * ep[k][0] + ep[k][1] * ep[k][1] + ep[k][2] * ep[k][2];
@@ -1419,10 +1437,10 @@ __global__ void __launch_bounds__(256) small_kernel(const SmallMol* __restrict__
         rel = fabs(g[k]) / fmax(sqrt(pp * (e[k][0] * e[k][0] + e[k][1] * e[k][1] + e[k][2] * e[k][2])), DBL_MIN);
       } else {
         g[k] = 0.5 * (pp - M.d2[k]);
-        rel = (fabs(g[k]) + sqrt(pp) * delta + delta2) / M.d2[k];
+        rel = (fabs(g[k]) + sqrt(pp) * delta + delta2) * id2[k];
       }
       if (!(rel <= DBL_MAX)) rel = INFINITY;
-      if (k < nc) gmax = fmax(gmax, rel);
+      gmax = fmax(gmax, rel);
     }
     if (A.hist && it < A.hist_len) A.hist[static_cast<int64_t>(M.mol) * A.hist_len + it] = gmax;
     if (A.warm >= 2 && !fell_back) {
@@ -1431,7 +1449,7 @@ __global__ void __launch_bounds__(256) small_kernel(const SmallMol* __restrict__
         fell_back = 1;
         prev = INFINITY;
 #pragma unroll
-        for (int k = 0; k < kSmallCons; ++k) lam[k] = 0.0;
+        for (int k = 0; k < NC; ++k) lam[k] = 0.0;
         continue;
       }
       prev = gmax;
@@ -1439,62 +1457,58 @@ __global__ void __launch_bounds__(256) small_kernel(const SmallMol* __restrict__
     if (gmax == INFINITY) { st_code = ILVES_ERR_NONFINITE; break; }
     if (gmax <= A.tol) { st_code = ILVES_OK; break; }
     if (it >= A.max_iter) { st_code = ILVES_ERR_NOT_CONVERGED; break; }
-    // A_kj = C_kj (e'_k . e_j); unused rows are the identity
-    double m[kSmallCons][kSmallCons + 1];
+    // A_kj = C_kj (e'_k . e_j), zero where k and j share no atom
+    double m[NC][NC + 1];
 #pragma unroll
-    for (int k = 0; k < kSmallCons; ++k) {
+    for (int k = 0; k < NC; ++k) {
 #pragma unroll
-      for (int j = 0; j < kSmallCons; ++j) {
-        const double c = k == j ? cdiag[k] : coup[k][j];
+      for (int j = 0; j < NC; ++j) {
         const double* xk = A.chord ? e[k] : ep[k];  // chord: the constant A(r, r)
         const double dot = xk[0] * e[j][0] + xk[1] * e[j][1] + xk[2] * e[j][2];
-        m[k][j] = k < nc ? c * dot : (k == j ? 1.0 : 0.0);
+        m[k][j] = k == j ? cdiag[k] * dot : (small_shared<CLS>(k, j) >= 0 ? coup(k, j) * dot : 0.0);
       }
-      m[k][kSmallCons] = k < nc ? g[k] : 0.0;
+      m[k][NC] = g[k];
     }
     bool sing = false;
 #pragma unroll
-    for (int p = 0; p < kSmallCons; ++p) {
+    for (int p = 0; p < NC; ++p) {
       if (!(fabs(m[p][p]) > 1e-13 * fabs(cdiag[p] * (e[p][0] * e[p][0] + e[p][1] * e[p][1] + e[p][2] * e[p][2]))))
-        sing = sing || p < nc;
+        sing = true;
       // 1 / pivot from the hardware reciprocal refined by Newton steps,
       // kept in the pivot's slot for the back substitution
       const double inv = recip(m[p][p]);
 #pragma unroll
-      for (int q = p + 1; q < kSmallCons; ++q) {
+      for (int q = p + 1; q < NC; ++q) {
         const double f = m[q][p] * inv;
 #pragma unroll
-        for (int j = p; j <= kSmallCons; ++j) m[q][j] -= f * m[p][j];
+        for (int j = p; j <= NC; ++j) m[q][j] -= f * m[p][j];
       }
       m[p][p] = inv;
     }
     if (sing) { st_code = ILVES_ERR_SINGULAR; break; }
-    double z[kSmallCons];
+    double z[NC];
 #pragma unroll
-    for (int p = kSmallCons - 1; p >= 0; --p) {
-      double acc = m[p][kSmallCons];
+    for (int p = NC - 1; p >= 0; --p) {
+      double acc = m[p][NC];
 #pragma unroll
-      for (int j = p + 1; j < kSmallCons; ++j) acc -= m[p][j] * z[j];
+      for (int j = p + 1; j < NC; ++j) acc -= m[p][j] * z[j];
       z[p] = acc * m[p][p];
     }
 #pragma unroll
-    for (int k = 0; k < kSmallCons; ++k)
-      if (k < nc) lam[k] += z[k];
+    for (int k = 0; k < NC; ++k) lam[k] += z[k];
     ++it;
   }
 #pragma unroll
-  for (int k = 0; k < kSmallCons; ++k)
-    if (k < nc) A.lambda[M.cid[k]] = lam[k];
+  for (int k = 0; k < NC; ++k) A.lambda[M.cid[k]] = lam[k];
 #pragma unroll
-  for (int i = 0; i < kSmallAtoms; ++i) {
-    if (i >= na) continue;
+  for (int i = 0; i < NA; ++i) {
     double d[3] = {0.0, 0.0, 0.0};
 #pragma unroll
-    for (int k = 0; k < kSmallCons; ++k) {
-      if (k >= nc) continue;
-      const double l = M.a[k] == i ? lam[k] : (M.b[k] == i ? -lam[k] : 0.0);
+    for (int k = 0; k < NC; ++k) {
+      const int sg = small_sigma<CLS>(k, i);
+      if (sg == 0) continue;
 #pragma unroll
-      for (int c = 0; c < 3; ++c) d[c] += l * e[k][c];
+      for (int c = 0; c < 3; ++c) d[c] += (sg > 0 ? lam[k] : -lam[k]) * e[k][c];
     }
     const int32_t gi = M.atom[i];
 #pragma unroll
@@ -1503,6 +1517,28 @@ __global__ void __launch_bounds__(256) small_kernel(const SmallMol* __restrict__
   A.iters[M.mol] = it;
   A.status[M.mol] = st_code;
   if (A.fallback) A.fallback[M.mol] = fell_back;
+}
+
+// the shape of a record, from its canonical numbering (small_shape on the
+// host): a star and a chain both have three constraints on four atoms and
+// differ in the first atom of constraint 1
+__device__ __forceinline__ int small_class(const SmallMol& M) {
+  return M.nc == 1 ? 0 : M.nc == 2 ? 1 : M.na == 3 ? 2 : (M.a[1] == 0 ? 3 : 4);
+}
+
+template <bool PROJECT>
+__global__ void __launch_bounds__(256) small_kernel(const SmallMol* __restrict__ sm, int32_t count,
+                                                   const SolveArgs A) {
+  const int32_t t = blockIdx.x * 256 + threadIdx.x;
+  if (t >= count) return;
+  const SmallMol M = sm[t];
+  switch (small_class(M)) {
+    case 0: small_solve<0, PROJECT>(M, A); break;
+    case 1: small_solve<1, PROJECT>(M, A); break;
+    case 2: small_solve<2, PROJECT>(M, A); break;
+    case 3: small_solve<3, PROJECT>(M, A); break;
+    default: small_solve<4, PROJECT>(M, A); break;
+  }
 }
 
 __global__ void reset_counters(int32_t* __restrict__ c, int32_t n) {
@@ -1656,6 +1692,95 @@ size_t push_array(std::vector<unsigned char>& blob, const std::vector<V>& v) {
   blob.resize(off + v.size() * sizeof(V));
   if (!v.empty()) std::memcpy(blob.data() + off, v.data(), v.size() * sizeof(V));
   return off;
+}
+
+// Ends of constraint k of a small-molecule shape (the canonical order of
+// SmallTopo): end 0 is A[k], end 1 is B[k].
+int small_topo_end(int shape, int k, int end) {
+  switch (shape) {
+    case 0: return end == 0 ? SmallTopo<0>::A[k] : SmallTopo<0>::B[k];
+    case 1: return end == 0 ? SmallTopo<1>::A[k] : SmallTopo<1>::B[k];
+    case 2: return end == 0 ? SmallTopo<2>::A[k] : SmallTopo<2>::B[k];
+    case 3: return end == 0 ? SmallTopo<3>::A[k] : SmallTopo<3>::B[k];
+    default: return end == 0 ? SmallTopo<4>::A[k] : SmallTopo<4>::B[k];
+  }
+}
+
+// Shape of a molecule of at most kSmallCons constraints on kSmallAtoms
+// atoms and its canonical numbering: atom[a] is the molecule's local atom
+// that takes canonical number a, con[k] the local constraint that takes
+// canonical number k.  Returns -1 when the molecule has none of the shapes
+// (a connected molecule of that size always has one).
+int small_shape(const ilves::MolPlan& M, int32_t atom[kSmallAtoms], int32_t con[kSmallCons]) {
+  const int nc = M.n, na = M.s;
+  int deg[kSmallAtoms] = {0, 0, 0, 0};
+  for (int k = 0; k < nc; ++k) {
+    if (M.ra[k] < 0 || M.ra[k] >= na || M.rb[k] < 0 || M.rb[k] >= na) return -1;
+    ++deg[M.ra[k]];
+    ++deg[M.rb[k]];
+  }
+  auto other = [&](int k, int x) { return M.ra[k] == x ? M.rb[k] : M.ra[k]; };
+  auto find = [&](int x, int y) {
+    for (int k = 0; k < nc; ++k)
+      if ((M.ra[k] == x && M.rb[k] == y) || (M.ra[k] == y && M.rb[k] == x)) return k;
+    return -1;
+  };
+  auto center = [&](int d) {
+    for (int x = 0; x < na; ++x)
+      if (deg[x] == d) return x;
+    return -1;
+  };
+  int shape = -1;
+  for (int a = 0; a < kSmallAtoms; ++a) atom[a] = 0;
+  for (int k = 0; k < kSmallCons; ++k) con[k] = 0;
+  if (nc == 1 && na == 2) {
+    shape = 0;
+    atom[0] = M.ra[0];
+    atom[1] = M.rb[0];
+  } else if (nc == 2 && na == 3) {
+    const int c = center(2);
+    if (c < 0) return -1;
+    shape = 1;
+    atom[0] = c;
+    atom[1] = other(0, c);
+    atom[2] = other(1, c);
+    con[1] = 1;
+  } else if (nc == 3 && na == 3) {
+    shape = 2;
+    for (int a = 0; a < 3; ++a) atom[a] = a;
+  } else if (nc == 3 && na == 4) {
+    const int c = center(3);
+    if (c >= 0) {
+      shape = 3;
+      atom[0] = c;
+      for (int k = 0; k < 3; ++k) atom[k + 1] = other(k, c);
+    } else {
+      const int p0 = center(1);
+      if (p0 < 0) return -1;
+      shape = 4;
+      atom[0] = p0;
+      for (int a = 1; a < 4; ++a) {  // walk the chain
+        int next = -1;
+        for (int k = 0; k < nc; ++k) {
+          const int y = M.ra[k] == atom[a - 1] ? M.rb[k] : (M.rb[k] == atom[a - 1] ? M.ra[k] : -1);
+          if (y >= 0 && (a < 2 || y != atom[a - 2])) next = y;
+        }
+        if (next < 0) return -1;
+        atom[a] = next;
+      }
+    }
+  } else {
+    return -1;
+  }
+  // every canonical constraint is one of the molecule's, each used once
+  bool used[kSmallCons] = {false, false, false};
+  for (int k = 0; k < nc; ++k) {
+    const int q = find(atom[small_topo_end(shape, k, 0)], atom[small_topo_end(shape, k, 1)]);
+    if (q < 0 || used[q]) return -1;
+    used[q] = true;
+    con[k] = q;
+  }
+  return shape;
 }
 
 template <typename V>
@@ -1831,26 +1956,42 @@ ilves_status_t build_device_plan(ilves_plan* P) {
     return static_cast<int64_t>(desc[x].n_up) + desc[x].n_l + desc[x].n >
            static_cast<int64_t>(desc[y].n_up) + desc[y].n_l + desc[y].n;
   });
-  // small molecules go to the one-thread-per-molecule kernel
+  // small molecules go to the one-thread-per-molecule kernel, numbered in
+  // their shape's canonical order and grouped by shape (the kernel branches
+  // on the shape, so a wave should hold one)
   std::vector<char> small(nm, 0);
   std::vector<SmallMol> smalls;
+  std::vector<int> shapes;
   for (int32_t i = 0; i < nm; ++i) {
     const ilves::MolPlan& M = P->mols[i];
     if (M.n > kSmallCons || M.s > kSmallAtoms || M.n < 1) continue;
+    int32_t atom[kSmallAtoms], con[kSmallCons];
+    const int shape = small_shape(M, atom, con);
+    if (shape < 0) continue;  // not one of the five shapes: the general path
     small[i] = 1;
     SmallMol r{};
-    for (int a = 0; a < kSmallAtoms; ++a) r.atom[a] = M.atom_gid[a < M.s ? a : 0];
+    for (int a = 0; a < kSmallAtoms; ++a) r.atom[a] = M.atom_gid[atom[a < M.s ? a : 0]];
     for (int k = 0; k < kSmallCons; ++k) {
       const bool used = k < M.n;
-      r.cid[k] = used ? M.cid[k] : M.cid[0];
-      r.a[k] = static_cast<uint8_t>(used ? M.ra[k] : 0);
-      r.b[k] = static_cast<uint8_t>(used ? M.rb[k] : 0);
-      r.d2[k] = used ? M.d2[k] : 1.0;
+      r.cid[k] = M.cid[used ? con[k] : con[0]];
+      r.a[k] = static_cast<uint8_t>(used ? small_topo_end(shape, k, 0) : 0);
+      r.b[k] = static_cast<uint8_t>(used ? small_topo_end(shape, k, 1) : 0);
+      r.d2[k] = used ? M.d2[con[k]] : 1.0;
     }
     r.mol = i;
     r.nc = static_cast<uint8_t>(M.n);
     r.na = static_cast<uint8_t>(M.s);
     smalls.push_back(r);
+    shapes.push_back(shape);
+  }
+  {
+    std::vector<int32_t> so(smalls.size());
+    for (size_t q = 0; q < so.size(); ++q) so[q] = static_cast<int32_t>(q);
+    std::stable_sort(so.begin(), so.end(), [&](int32_t x, int32_t y) { return shapes[x] < shapes[y]; });
+    std::vector<SmallMol> sorted;
+    sorted.reserve(smalls.size());
+    for (int32_t q : so) sorted.push_back(smalls[q]);
+    smalls.swap(sorted);
   }
   ord.erase(std::remove_if(ord.begin(), ord.end(), [&](int32_t i) { return small[i] != 0; }), ord.end());
   std::vector<char> is_split(nm, 0);
