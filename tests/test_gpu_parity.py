@@ -125,6 +125,25 @@ def test_small_molecules(small_case, name, prec, variant):
     _check(sm, ru, out, ref, f"small/{name}")
 
 
+@pytest.mark.parametrize("warm", [L.WARM_ZERO, L.WARM_DECOUPLED])
+def test_small_molecules_orientation(small_case, warm):
+    """Reversing the atom pair of every constraint leaves G(r), and so lambda
+    and r', unchanged (e_k and the signs of row k flip together).  The small
+    molecules are renumbered in their shape's canonical order at plan time,
+    so the reversed topology must give the oracle's result as well, and the
+    same numbers as the original one to rounding."""
+    import dataclasses
+    sm, ru, ref = small_case
+    flipped = dataclasses.replace(sm, pairs=np.ascontiguousarray(sm.pairs[:, ::-1]))
+    print(f"== small orientation warm {warm}", flush=True)
+    a = solve_once(sm, ru, TOL, L.PREC_FP64, warm=warm)
+    b = solve_once(flipped, ru, TOL, L.PREC_FP64, warm=warm)
+    _check(flipped, ru, b, ref, f"small/flipped/{warm}")
+    assert np.array_equal(a["iters"], b["iters"])
+    assert np.max(np.abs(a["r_out"] - b["r_out"])) <= 1e-13
+    assert np.max(np.abs(a["lam"] - b["lam"])) <= 1e-12 * np.max(np.abs(a["lam"]))
+
+
 def test_small_molecules_warm_start_and_failures(small_case):
     sm, ru, ref = small_case
     out = solve_once(sm, ru, TOL, L.PREC_FP64, lam0=ref["lam"])
