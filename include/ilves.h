@@ -239,7 +239,10 @@ ilves_status_t ilves_md_finish(double* r, const double* r_new, double h, int32_t
  * <= 64 KB, larger); molecules with only part (or none) of their data in LDS
  * fall in band 3 up to 4096 constraints and in band 4 above.  The partly-LDS
  * kernels exist with 512 and 1024 threads only; smaller requests round up to
- * 512.  lds_limit caps the LDS one molecule may use (0 = all of it); lowering
+ * 512.  The launch group of the largest molecules held in LDS runs 1024
+ * threads whatever its band's entry when its LDS allows one workgroup per
+ * CU and no group running beside it fits in the LDS it leaves (unless the
+ * plan's block_threads caps it lower).  lds_limit caps the LDS one molecule may use (0 = all of it); lowering
  * it moves molecules out of LDS.  Defined by: no passage (a launch knob of
  * this library; the ordering and factorisation it schedules are those of
  * Supplement section 3).

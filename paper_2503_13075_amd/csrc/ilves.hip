@@ -1611,6 +1611,7 @@ KernelFn pick_split(bool fp32, int mode) {
 }
 
 constexpr int kLdsMax = 160 * 1024 - 1024;  // dynamic LDS a molecule may use
+constexpr int kCuLds = 160 * 1024;          // LDS of a CU
 constexpr int kStreams = 4;                 // concurrent launch groups
 
 struct Group {
@@ -1624,7 +1625,7 @@ struct Group {
   int32_t counter = 0;  // index of the group's queue counter
   int stream = 0;       // index into the plan's streams
   int64_t work = 0;     // sum over its molecules of rows + off-diagonal slots
-  bool heavy = false;   // largest trees, one workgroup per CU: the wide-batch kernel
+  bool heavy = false;   // largest trees, 512 threads: the wide-batch kernel
 };
 constexpr int kMaxGroups = 64;
 
@@ -2421,17 +2422,36 @@ ilves_status_t finalize_groups(ilves_plan* P) {
       int per_cu = 0;
       HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, g.block, static_cast<size_t>(g.lds_bytes)));
       if (per_cu < 1) return fail(ILVES_ERR_HIP, "a solve kernel cannot be resident on a compute unit");
-      // one workgroup per CU by LDS: the wide-batch kernel costs the group no
-      // occupancy (512 threads: at 1024 the launch bounds leave 128 registers,
-      // too few).  Only the group of the largest trees takes it: a CU that
-      // holds a workgroup of another one-per-CU group has LDS left for
-      // smaller molecules, and the extra registers would keep them out.
-      if (per_cu == 1 && g.lds_bytes == lds_top && g.mode == ALL_LDS && !g.wide && g.block == 512) {
-        const void* kh = reinterpret_cast<const void*>(pick_kernel(prec == 1, g.mode, g.wide, g.block, true));
-        HIP_TRY(hipFuncSetAttribute(kh, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsMax));
-        int per_cu_h = 0;
-        HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_h, kh, g.block, static_cast<size_t>(g.lds_bytes)));
-        if (per_cu_h >= 1) g.heavy = true;
+      // The group of the largest trees, one workgroup per CU by LDS, has its
+      // CU to itself when no group running beside it (on another stream)
+      // fits in the LDS it leaves; the group chained behind it runs after it.
+      // It then runs 1024 threads whatever the tuning (not above the plan's
+      // cap on threads per workgroup), which halves its passes over the rows
+      // (set-up, residual, outputs).  Otherwise, or should that kernel not
+      // fit, the 512-thread wide-batch kernel (four row neighbours per batch)
+      // takes it.  Other one-per-CU groups keep the lean kernel: a CU holding
+      // one of their workgroups has LDS left for smaller molecules, which
+      // extra registers would keep out.
+      bool alone = true;
+      for (const Group& o : P->groups[prec])
+        if (o.stream != g.stream && o.lds_bytes + g.lds_bytes <= kCuLds) alone = false;
+      if (per_cu == 1 && g.lds_bytes == lds_top && g.mode == ALL_LDS && !g.wide) {
+        int per_cu_t = 0;
+        if (alone && (P->opt.block_threads <= 0 || P->opt.block_threads >= 1024)) {
+          const void* kt = reinterpret_cast<const void*>(pick_kernel(prec == 1, g.mode, g.wide, 1024));
+          HIP_TRY(hipFuncSetAttribute(kt, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsMax));
+          HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_t, kt, 1024, static_cast<size_t>(g.lds_bytes)));
+        }
+        if (per_cu_t >= 1) {
+          g.block = 1024;
+          per_cu = per_cu_t;
+        } else if (g.block == 512) {
+          const void* kh = reinterpret_cast<const void*>(pick_kernel(prec == 1, g.mode, g.wide, g.block, true));
+          HIP_TRY(hipFuncSetAttribute(kh, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsMax));
+          int per_cu_h = 0;
+          HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_h, kh, g.block, static_cast<size_t>(g.lds_bytes)));
+          if (per_cu_h >= 1) g.heavy = true;
+        }
       }
       g.grid = static_cast<int32_t>(std::min<int64_t>(g.count, static_cast<int64_t>(per_cu) * P->n_cu));
     }
